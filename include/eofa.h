@@ -1,0 +1,198 @@
+/*
+ * eofa.h -- C ABI of the MI355X (gfx950) EOFA Mobius domain-wall solver.
+ *
+ * The library solves the generic EOFA linear system (Sec. VI A, eqn
+ * generic_eofa_system, of Jung, Kelly, Mawhinney, Murphy, arXiv:1706.05843)
+ *
+ *     ( H(m_op) + beta * Delta_chi(m_a, m_b) P_chi ) psi = phi,
+ *     H = gamma_5 R5 D_EOFA,
+ *
+ * for Mobius domain-wall fermions, by the paper's route: multiply by
+ * gamma_5 R5 (App. B, eqn non_hermit_sys), right-precondition by D~^-1
+ * (App. B.2, eqn precond_mobius_eofa_system), even-odd Schur complement on
+ * the odd sublattice (App. B), CG on the normal equations, reconstruction.
+ *
+ * Conventions
+ * -----------
+ * * Lattice dims[4] = {Lx, Ly, Lz, Lt}; every entry even and >= 2; Ls even
+ *   (App. A assumes even Ls), 2 <= Ls <= 32.
+ * * Mobius (b5, c5): the paper's c = (b5+c5)/2, d = (b5-c5)/2; the paper
+ *   fixes d = 1/2 (Sec. II), so b5 - c5 must equal 1.
+ * * Gamma matrices in the chiral basis: gamma_k = [[0, -i sigma_k],
+ *   [i sigma_k, 0]] (k = x, y, z), gamma_t = [[0, 1], [1, 0]],
+ *   gamma_5 = diag(1, 1, -1, -1); P_+ keeps spins 0, 1.
+ * * Wilson hop (Sec. II, eqn Ddwf): forward hop (1 - gamma_mu) U_mu(x),
+ *   backward hop (1 + gamma_mu) U_mu(x - mu)^dag, overall -1/2; bc[mu] = +1
+ *   periodic, -1 antiperiodic (applied to fermion hops across the edge).
+ * * Parity of a site = (x + y + z + t) mod 2; even = 0, odd = 1.
+ *
+ * Canonical (user) layouts, complex128 = two doubles (re, im):
+ *   gauge   [4][Lt][Lz][Ly][Lx][3][3]           row-major SU(3) links U_mu(x)
+ *   fermion [nrhs][Ls][Lt][Lz][Ly][Lx][4][3]     spin then colour
+ *
+ * Packed (internal) half-field of one parity: site index
+ *   i = (((t*Lz + z)*Ly + y)*Lx + x) / 2,  Vh = Lx*Ly*Lz*Lt / 2,
+ * components c = spin*3 + colour grouped in pairs q = c/2 (q = 0..2 is the
+ * P_+ half, q = 3..5 the P_- half); element (rhs, q, s, i) at
+ *   ((rhs*6 + q)*Ls + s)*Vh + i
+ * with element = two complex numbers:
+ *   EOFA_FP64  : 2 x (double re, double im)      32 bytes
+ *   EOFA_FP32  : 2 x (float re, float im)        16 bytes
+ *   EOFA_FP16S : 2 x (half re, half im)           8 bytes, plus one float
+ *                scale per 5D site at ((rhs*Ls + s)*Vh + i) stored after
+ *                the values; the site's 24 reals are value * scale with
+ *                scale = max |re|, |im| of the site.
+ * eofa_packed_bytes() gives the size of one packed half-field block.
+ *
+ * Memory and streams
+ * ------------------
+ * Every field pointer is a DEVICE pointer owned by the caller (for example
+ * torch tensor data_ptr()), and must not alias another argument unless
+ * stated. `stream` is a hipStream_t (NULL = default stream). dslash,
+ * mooee, mooee_inv, pack and unpack are asynchronous on `stream`;
+ * cg_solve and heatbath_solve block until their result is on the device
+ * and the stats are filled. The context owns only its internal copies of
+ * the gauge field and its workspace, freed by eofa_destroy. Calls on one
+ * context must not overlap (one caller thread, one stream at a time).
+ *
+ * Errors
+ * ------
+ * Every entry point returns 0 on success or a negative eofa_status; on
+ * failure eofa_last_error() returns a message (thread-local, valid until
+ * the next call from that thread). Nothing aborts and no exception crosses
+ * the ABI.
+ */
+#ifndef EOFA_H
+#define EOFA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  EOFA_OK = 0,
+  EOFA_ERR_INVALID = -1,       /* bad argument: odd dims/Ls, b5-c5 != 1, |chi| != 1, null, alias */
+  EOFA_ERR_NOT_CONVERGED = -2, /* solve hit max_iter / max_outer; psi holds the last iterate      */
+  EOFA_ERR_BREAKDOWN = -3,     /* Sherman-Morrison denominator 0, NaN/Inf, CG breakdown            */
+  EOFA_ERR_HIP = -4,           /* a HIP runtime call failed                                        */
+  EOFA_ERR_OOM = -5            /* device allocation failed                                         */
+} eofa_status;
+
+typedef enum { EOFA_FP64 = 0, EOFA_FP32 = 1, EOFA_FP16S = 2 } eofa_prec;
+
+typedef struct eofa_ctx eofa_ctx;
+
+/* Mobius domain-wall action (Sec. II, eqn Ddwf; Table "ensembles" for bc). */
+typedef struct {
+  int32_t dims[4]; /* Lx, Ly, Lz, Lt                                  */
+  int32_t Ls;
+  double M5, b5, c5;
+  int32_t bc[4];   /* +1 periodic, -1 antiperiodic, per direction     */
+} eofa_action;
+
+/* One EOFA system (eqn generic_eofa_system):
+ *   (H(m_op) + beta Delta_chi(m_a, m_b) P_chi) psi = phi.
+ * beta = 0 gives the plain H(m_op) system; chi is then ignored.
+ * Delta_chi and k(m_a, m_b) follow App. A (Mobius kernel).            */
+typedef struct {
+  double m_op, m_a, m_b, beta;
+  int32_t chi; /* +1 or -1 */
+} eofa_system;
+
+typedef struct {
+  double tol;          /* stop when |phi - A psi| / |phi| <= tol, FP64 true residual           */
+  int32_t max_iter;    /* total inner CG iterations allowed (all outer passes)                 */
+  int32_t max_outer;   /* FP64 defect-correction passes (Sec. VI A); >= 1                      */
+  int32_t inner_prec;  /* eofa_prec of the inner CG (FP64: plain solve)                        */
+  double inner_tol;    /* inner CG stop |r_k| <= inner_tol |r_0| on the normal equations;
+                          0 = automatic (0.3*tol for FP64 inner, 1e-4 otherwise)               */
+  int32_t fixed_iters; /* > 0: exactly this many inner iterations in one pass, no early stop   */
+  int32_t check_every; /* host convergence poll period in iterations (0 = 16)                 */
+  int32_t profile;     /* 1: time the inner hop kernels with HIP events (stats.hop_ms)        */
+} eofa_solver_params;
+
+typedef struct {
+  int32_t iters;        /* inner CG iterations, summed over outer passes       */
+  int32_t outer_iters;  /* FP64 outer passes                                   */
+  int32_t converged;    /* 1 if true_resid <= tol                              */
+  int32_t status;       /* eofa_status of this right-hand side                 */
+  double true_resid;    /* |b - (D_DWF + chi beta Delta~) psi'| / |b|, FP64    */
+  double seconds;       /* wall time of the whole call                        */
+  double hop_ms[4];     /* profile=1: summed device time of the timed inner
+                           hop kernels: [0] M_ee^-1 Dhop D~, [1] M_ee - Dhop D~,
+                           [2] M_ee^-T D~^T Dhop^dag, [3] residual update       */
+  int32_t hop_timed;    /* profile=1: inner iterations whose kernels were timed */
+  int32_t pad;
+} eofa_solver_stats;
+
+/* Create a context: validates the action, packs the gauge field (device
+ * pointer, canonical complex128 layout above) per parity with boundary
+ * phases folded in. The gauge array is not retained.                    */
+int eofa_create(const eofa_action* act, const void* gauge, void* stream, eofa_ctx** out);
+int eofa_destroy(eofa_ctx* ctx);
+const char* eofa_last_error(void);
+
+/* Bytes of one packed half-field block for nrhs right-hand sides.        */
+size_t eofa_packed_bytes(const eofa_ctx* ctx, int32_t prec, int32_t nrhs);
+
+/* Canonical full field -> packed half-field of one parity (and back).
+ * g5r5 = 1 applies gamma_5 R5 on the way (App. B: b = gamma_5 R5 phi). */
+int eofa_pack(eofa_ctx* ctx, const void* full, void* packed, int32_t parity, int32_t prec,
+              int32_t nrhs, int32_t g5r5, void* stream);
+int eofa_unpack(eofa_ctx* ctx, const void* packed, void* full, int32_t parity, int32_t prec,
+                int32_t nrhs, void* stream);
+
+/* Off-parity block of D_DWF(m_op) (eqn Ddwf minus its site-local part):
+ *   out_p = Dhop_{p <- 1-p} D~(m_op) in_{1-p},   D~ = (c+d) + (c-d) L(m_op)
+ * (dagger = 1: out_p = D~^T gamma_5 Dhop gamma_5 in, its adjoint). in and
+ * out are packed half-fields of parities 1-out_parity and out_parity;
+ * sys[r] gives m_op for right-hand side r.                               */
+int eofa_dslash(eofa_ctx* ctx, const eofa_system* sys, const void* in, void* out,
+                int32_t out_parity, int32_t dagger, int32_t prec, int32_t nrhs, void* stream);
+
+/* Same-parity block of the Cayley-form operator (App. B.2):
+ *   M_ee = ((c+d)(4-M5)+1) - (1-(c-d)(4-M5)) L(m_op) + chi beta u_chi v_chi^T P_chi
+ * (eqn delta_rank_one), site local; out = M_ee in (dagger: M_ee^T in).   */
+int eofa_mooee(eofa_ctx* ctx, const eofa_system* sys, const void* in, void* out, int32_t dagger,
+               int32_t prec, int32_t nrhs, void* stream);
+
+/* out = M_ee^-1 in (dagger: M_ee^-T in); the inverse is built per system
+ * with Sherman-Morrison (eqn sherman_morrison_mobius_inv). Fails with
+ * EOFA_ERR_BREAKDOWN if the Sherman-Morrison denominator vanishes.       */
+int eofa_mooee_inv(eofa_ctx* ctx, const eofa_system* sys, const void* in, void* out,
+                   int32_t dagger, int32_t prec, int32_t nrhs, void* stream);
+
+/* Solve nrhs independent EOFA systems sys[r] for canonical phi[r] -> psi[r]
+ * (device, complex128, canonical layout; psi is output only). Inner CG in
+ * params->inner_prec with an FP64 defect-correction outer loop (Sec. VI A);
+ * all right-hand sides iterate together in batched kernels, each with its
+ * own CG scalars. stats: host array [nrhs] (may be NULL).                */
+int eofa_cg_solve(eofa_ctx* ctx, const eofa_system* sys, const void* phi, void* psi, int32_t nrhs,
+                  const eofa_solver_params* params, eofa_solver_stats* stats, void* stream);
+
+/* EOFA heatbath (Sec. IV B, eqn eofa_heatbath): phi = f(M_EOFA) eta for
+ * the rational f(x) = alpha[0] + sum_l alpha[l] / (beta[l-1] + x),
+ * l = 1..n_poles, via the 2*n_poles systems
+ *   LH: (H(m1) - gamma_l Delta_-(m1,m2) P_-),  RH: (H(m2) - beta_l gamma_l Delta_+(m1,m2) P_+),
+ * gamma_l = 1/(1+beta_l), solved as one batch. eta, phi: device canonical
+ * complex128 fields (one right-hand side). alpha: host [n_poles+1],
+ * beta: host [n_poles]. stats: host [2*n_poles] (LH poles then RH), may
+ * be NULL.                                                               */
+int eofa_heatbath_solve(eofa_ctx* ctx, double m1, double m2, int32_t n_poles, const double* alpha,
+                        const double* beta, const void* eta, void* phi,
+                        const eofa_solver_params* params, eofa_solver_stats* stats, void* stream);
+
+/* Host only (no device work): the fifth-dimension matrix `mat` that the
+ * library builds for one system, as out[2][Ls][Ls] (row-major; [0] acts on
+ * P_+ psi, [1] on P_- psi). mat: 0 M_ee, 1 M_ee^-1, 2 M_ee^T, 3 M_ee^-T,
+ * 4 M_ee^-T D~^T, 5 -D~^T, 6 D~^T, 7 D~ (App. A, App. B.2).
+ * Returns EOFA_ERR_BREAKDOWN if the Sherman-Morrison denominator vanishes. */
+int eofa_fifth_matrix(const eofa_action* act, const eofa_system* sys, int32_t mat, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

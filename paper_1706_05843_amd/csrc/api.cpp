@@ -1,0 +1,798 @@
+// C ABI, context and the batched CG driver (host side).
+//
+// Solve route (App. B, App. B.2, Sec. VI A), per right-hand side r:
+//   b = g5 R5 phi                                  (eqn non_hermit_sys)
+//   b~_o = b_o - M_oe M_ee^-1 b_e                  (Schur source)
+//   FP64 outer loop (defect correction):
+//     r_o = b~_o - M^ x_o,  stop if |r_o| <= tol |b|
+//     inner CGNR on M^dag M e = M^dag r_o in the inner precision
+//     x_o += e
+//   psi'_e = M_ee^-1 (b_e - M_eo x_o),  psi = D~ psi'   (eqn precond_mobius_eofa_system)
+// with M^ = M_ee - M_oe M_ee^-1 M_eo, M_eo = Dhop_eo D~. The odd Schur
+// residual equals the full residual of the Cayley system once psi'_e is
+// reconstructed, and |b| = |phi| since g5 R5 is unitary, so the outer test is
+// the FP64 true residual of the EOFA system; it is re-measured on the full
+// lattice at the end.
+//
+// Inner CGNR iteration (all right-hand sides in the same kernels, each with
+// its own scalars; a right-hand side that has converged is skipped by every
+// kernel through its halt flag):
+//   K1  t_e = M_ee^-1 Dhop D~ p_o
+//   K2  w_o = M_ee p_o - Dhop D~ t_e          |w|^2 -> alpha = |r|^2/|w|^2
+//   K3  t_e = M_ee^-T D~^T Dhop^dag w_o
+//   K4  r_o -= alpha (M_ee^T w_o - D~^T Dhop^dag t_e)   |r|^2 -> beta
+//   U   x_o += alpha p_o,  p_o = r_o + beta p_o
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace eofa;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(call)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) return fail(EOFA_ERR_HIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+#define CHK(call)                \
+  do {                           \
+    int c_ = (call);             \
+    if (c_ != EOFA_OK) return c_; \
+  } while (0)
+
+struct Buf {
+  void* p = nullptr;
+  size_t n = 0;
+};
+
+}  // namespace
+
+struct eofa_ctx {
+  Geometry g;
+  double M5, b5, c5, c, d;
+  int bc[4];
+  int device;
+  void* links[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+  int* nbr[2] = {nullptr, nullptr};
+  std::map<std::string, Buf> pool;
+  // fifth-dimension matrices of the last systems uploaded
+  std::vector<double> sys_key;
+  double* mats = nullptr;  // [nrhs][NMAT][2][Ls][Ls] then mop[nrhs]
+  size_t mats_n = 0;
+  double* host_stage = nullptr;  // pinned
+  size_t host_stage_n = 0;
+  std::vector<hipEvent_t> events;
+};
+
+namespace {
+
+int ws(eofa_ctx* C, const char* name, size_t bytes, void** out) {
+  Buf& b = C->pool[name];
+  if (b.n < bytes) {
+    if (b.p) HIPCHK(hipFree(b.p));
+    b.p = nullptr;
+    b.n = 0;
+    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(EOFA_ERR_OOM, std::string("hipMalloc failed for workspace ") + name);
+    }
+    b.n = bytes;
+  }
+  *out = b.p;
+  return EOFA_OK;
+}
+
+int stage(eofa_ctx* C, size_t bytes) {
+  if (C->host_stage_n < bytes) {
+    if (C->host_stage) HIPCHK(hipHostFree(C->host_stage));
+    C->host_stage = nullptr;
+    C->host_stage_n = 0;
+    HIPCHK(hipHostMalloc((void**)&C->host_stage, bytes, hipHostMallocDefault));
+    C->host_stage_n = bytes;
+  }
+  return EOFA_OK;
+}
+
+size_t mats_per_rhs(const Geometry& g) { return (size_t)NMAT * 2 * g.Ls * g.Ls; }
+
+// Build and upload the fifth-dimension matrices and operator masses of
+// sys[0..nrhs). Cached: a repeat of the same systems uploads nothing.
+int upload_systems(eofa_ctx* C, const eofa_system* sys, int nrhs, hipStream_t st) {
+  std::vector<double> key;
+  key.reserve(nrhs * 5);
+  for (int r = 0; r < nrhs; ++r) {
+    key.push_back(sys[r].m_op);
+    key.push_back(sys[r].m_a);
+    key.push_back(sys[r].m_b);
+    key.push_back(sys[r].beta);
+    key.push_back(sys[r].beta != 0.0 ? (double)sys[r].chi : 0.0);
+  }
+  if (key == C->sys_key && C->mats) return EOFA_OK;
+  const size_t per = mats_per_rhs(C->g);
+  const size_t n = per * nrhs + nrhs;
+  std::vector<double> h(n);
+  for (int r = 0; r < nrhs; ++r) {
+    std::string err;
+    const int rc = build_fifth(C->g, C->M5, C->b5, C->c5, sys[r], h.data() + per * r, err);
+    if (rc != EOFA_OK) return fail(rc, "right-hand side " + std::to_string(r) + ": " + err);
+    h[per * nrhs + r] = sys[r].m_op;
+  }
+  if (C->mats_n < n) {
+    if (C->mats) HIPCHK(hipFree(C->mats));
+    C->mats = nullptr;
+    if (hipMalloc((void**)&C->mats, n * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      C->mats_n = 0;
+      return fail(EOFA_ERR_OOM, "hipMalloc failed for coefficient buffer");
+    }
+    C->mats_n = n;
+  }
+  CHK(stage(C, n * sizeof(double)));
+  HIPCHK(hipStreamSynchronize(st));  // the staging buffer may still feed an earlier copy
+  std::memcpy(C->host_stage, h.data(), n * sizeof(double));
+  HIPCHK(hipMemcpyAsync(C->mats, C->host_stage, n * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  C->sys_key = key;
+  return EOFA_OK;
+}
+
+const double* mop_ptr(eofa_ctx* C, int nrhs) { return C->mats + mats_per_rhs(C->g) * nrhs; }
+
+int check_prec(int prec) {
+  if (prec < 0 || prec > 2) return fail(EOFA_ERR_INVALID, "precision must be EOFA_FP64, EOFA_FP32 or EOFA_FP16S");
+  return EOFA_OK;
+}
+
+int check_systems(const eofa_system* sys, int nrhs) {
+  if (!sys) return fail(EOFA_ERR_INVALID, "sys is NULL");
+  if (nrhs < 1) return fail(EOFA_ERR_INVALID, "nrhs must be >= 1");
+  for (int r = 0; r < nrhs; ++r) {
+    if (sys[r].beta != 0.0 && sys[r].chi != 1 && sys[r].chi != -1)
+      return fail(EOFA_ERR_INVALID, "eofa_system.chi must be +1 or -1");
+    if (!std::isfinite(sys[r].m_op) || !std::isfinite(sys[r].beta) || !std::isfinite(sys[r].m_a) ||
+        !std::isfinite(sys[r].m_b))
+      return fail(EOFA_ERR_INVALID, "non-finite system parameter");
+  }
+  return EOFA_OK;
+}
+
+HopArgs base_args(eofa_ctx* C, int prec, int out_parity, int nrhs) {
+  HopArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.links = C->links[prec][out_parity];
+  a.nbr = C->nbr[out_parity];
+  a.mats = C->mats;
+  a.matA = 0;
+  a.matB = 0;
+  a.cpd = C->c + C->d;
+  a.cmd = C->c - C->d;
+  a.mop = mop_ptr(C, nrhs);
+  a.Vh = C->g.Vh;
+  a.Ls = C->g.Ls;
+  a.nrhs = nrhs;
+  a.rhs_block = nrhs;
+  return a;
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* eofa_last_error(void) { return g_err.c_str(); }
+
+int eofa_create(const eofa_action* act, const void* gauge, void* stream, eofa_ctx** out) {
+  if (!act || !gauge || !out) return fail(EOFA_ERR_INVALID, "eofa_create: NULL argument");
+  *out = nullptr;
+  for (int k = 0; k < 4; ++k) {
+    if (act->dims[k] < 2 || act->dims[k] % 2 != 0)
+      return fail(EOFA_ERR_INVALID, "every lattice extent must be even and >= 2");
+    if (act->bc[k] != 1 && act->bc[k] != -1) return fail(EOFA_ERR_INVALID, "bc entries must be +1 or -1");
+  }
+  if (act->Ls < 2 || act->Ls > 32 || act->Ls % 2 != 0) return fail(EOFA_ERR_INVALID, "Ls must be even, 2..32");
+  if (std::fabs(act->b5 - act->c5 - 1.0) > 1e-12)
+    return fail(EOFA_ERR_INVALID, "b5 - c5 must be 1 (d = 1/2)");
+  if (!std::isfinite(act->M5) || !std::isfinite(act->b5) || !std::isfinite(act->c5))
+    return fail(EOFA_ERR_INVALID, "non-finite action parameter");
+  const double V = (double)act->dims[0] * act->dims[1] * act->dims[2] * act->dims[3];
+  if (V / 2 * act->Ls * 6 > 2.0e9) return fail(EOFA_ERR_INVALID, "lattice too large for 32-bit site indexing");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(EOFA_ERR_INVALID, std::string("this library is built for gfx950; device is ") + prop.gcnArchName);
+
+  eofa_ctx* C = new eofa_ctx();
+  C->device = dev;
+  for (int k = 0; k < 4; ++k) {
+    C->g.L[k] = act->dims[k];
+    C->bc[k] = act->bc[k];
+  }
+  C->g.Ls = act->Ls;
+  C->g.V = (int)V;
+  C->g.Vh = (int)(V / 2);
+  C->M5 = act->M5;
+  C->b5 = act->b5;
+  C->c5 = act->c5;
+  C->c = 0.5 * (act->b5 + act->c5);
+  C->d = 0.5 * (act->b5 - act->c5);
+  hipStream_t st = (hipStream_t)stream;
+  for (int p = 0; p < 3; ++p)
+    for (int par = 0; par < 2; ++par)
+      if (hipMalloc(&C->links[p][par], link_bytes(p, C->g)) != hipSuccess) {
+        (void)hipGetLastError();
+        eofa_destroy(C);
+        return fail(EOFA_ERR_OOM, "hipMalloc failed for links");
+      }
+  for (int par = 0; par < 2; ++par)
+    if (hipMalloc((void**)&C->nbr[par], (size_t)C->g.Vh * 8 * sizeof(int)) != hipSuccess) {
+      (void)hipGetLastError();
+      eofa_destroy(C);
+      return fail(EOFA_ERR_OOM, "hipMalloc failed for neighbour table");
+    }
+  void* l64[2] = {C->links[P64][0], C->links[P64][1]};
+  void* l32[2] = {C->links[P32][0], C->links[P32][1]};
+  void* l16[2] = {C->links[P16][0], C->links[P16][1]};
+  launch_gauge_pack(C->g, gauge, C->bc, l64, l32, l16, C->nbr, st);
+  hipError_t e = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) {
+    eofa_destroy(C);
+    return fail(EOFA_ERR_HIP, std::string("gauge packing: ") + hipGetErrorString(e));
+  }
+  *out = C;
+  return EOFA_OK;
+}
+
+int eofa_destroy(eofa_ctx* C) {
+  if (!C) return EOFA_OK;
+  for (int p = 0; p < 3; ++p)
+    for (int par = 0; par < 2; ++par)
+      if (C->links[p][par]) (void)hipFree(C->links[p][par]);
+  for (int par = 0; par < 2; ++par)
+    if (C->nbr[par]) (void)hipFree(C->nbr[par]);
+  for (auto& kv : C->pool)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  if (C->mats) (void)hipFree(C->mats);
+  if (C->host_stage) (void)hipHostFree(C->host_stage);
+  for (auto ev : C->events) (void)hipEventDestroy(ev);
+  delete C;
+  return EOFA_OK;
+}
+
+size_t eofa_packed_bytes(const eofa_ctx* C, int32_t prec, int32_t nrhs) {
+  if (!C || prec < 0 || prec > 2 || nrhs < 1) return 0;
+  return packed_bytes(prec, C->g, nrhs);
+}
+
+int eofa_pack(eofa_ctx* C, const void* full, void* packed, int32_t parity, int32_t prec, int32_t nrhs,
+              int32_t g5r5, void* stream) {
+  if (!C || !full || !packed) return fail(EOFA_ERR_INVALID, "eofa_pack: NULL argument");
+  if (parity != 0 && parity != 1) return fail(EOFA_ERR_INVALID, "parity must be 0 or 1");
+  if (nrhs < 1) return fail(EOFA_ERR_INVALID, "nrhs must be >= 1");
+  CHK(check_prec(prec));
+  launch_pack(prec, C->g, full, packed, parity, nrhs, g5r5 ? 1 : 0, (hipStream_t)stream);
+  HIPCHK(hipGetLastError());
+  return EOFA_OK;
+}
+
+int eofa_unpack(eofa_ctx* C, const void* packed, void* full, int32_t parity, int32_t prec, int32_t nrhs,
+                void* stream) {
+  if (!C || !full || !packed) return fail(EOFA_ERR_INVALID, "eofa_unpack: NULL argument");
+  if (parity != 0 && parity != 1) return fail(EOFA_ERR_INVALID, "parity must be 0 or 1");
+  if (nrhs < 1) return fail(EOFA_ERR_INVALID, "nrhs must be >= 1");
+  CHK(check_prec(prec));
+  launch_unpack(prec, C->g, packed, full, parity, nrhs, (hipStream_t)stream);
+  HIPCHK(hipGetLastError());
+  return EOFA_OK;
+}
+
+int eofa_dslash(eofa_ctx* C, const eofa_system* sys, const void* in, void* out, int32_t out_parity,
+                int32_t dagger, int32_t prec, int32_t nrhs, void* stream) {
+  if (!C || !in || !out) return fail(EOFA_ERR_INVALID, "eofa_dslash: NULL argument");
+  if (in == out) return fail(EOFA_ERR_INVALID, "eofa_dslash: in and out alias");
+  if (out_parity != 0 && out_parity != 1) return fail(EOFA_ERR_INVALID, "parity must be 0 or 1");
+  CHK(check_prec(prec));
+  CHK(check_systems(sys, nrhs));
+  hipStream_t st = (hipStream_t)stream;
+  CHK(upload_systems(C, sys, nrhs, st));
+  HopArgs a = base_args(C, prec, out_parity, nrhs);
+  a.in = in;
+  a.out = out;
+  a.matA = MAT_DT_T;
+  const int rc = launch_hop(prec, dagger ? ROLE_DSLASH_DAG : ROLE_DSLASH, a, st, nullptr);
+  if (rc != EOFA_OK) return fail(rc, std::string("hop kernel launch: ") + hipGetErrorString(hipGetLastError()));
+  return EOFA_OK;
+}
+
+static int smat_entry(eofa_ctx* C, const eofa_system* sys, const void* in, void* out, int mat, int prec,
+                      int nrhs, void* stream) {
+  if (!C || !in || !out) return fail(EOFA_ERR_INVALID, "NULL argument");
+  if (in == out) return fail(EOFA_ERR_INVALID, "in and out alias");
+  CHK(check_prec(prec));
+  CHK(check_systems(sys, nrhs));
+  hipStream_t st = (hipStream_t)stream;
+  CHK(upload_systems(C, sys, nrhs, st));
+  launch_smat(prec, C->g, in, out, C->mats, mat, nrhs, st);
+  HIPCHK(hipGetLastError());
+  return EOFA_OK;
+}
+
+int eofa_mooee(eofa_ctx* C, const eofa_system* sys, const void* in, void* out, int32_t dagger, int32_t prec,
+               int32_t nrhs, void* stream) {
+  return smat_entry(C, sys, in, out, dagger ? MAT_MEE_T : MAT_MEE, prec, nrhs, stream);
+}
+
+int eofa_mooee_inv(eofa_ctx* C, const eofa_system* sys, const void* in, void* out, int32_t dagger,
+                   int32_t prec, int32_t nrhs, void* stream) {
+  return smat_entry(C, sys, in, out, dagger ? MAT_MEE_INV_T : MAT_MEE_INV, prec, nrhs, stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched solve
+
+namespace {
+
+struct Scal {
+  CgState s;
+  void* base = nullptr;
+};
+
+int alloc_state(eofa_ctx* C, int nrhs, CgState& S) {
+  void* b = nullptr;
+  const size_t nd = 7, ni = 5;
+  CHK(ws(C, "cgstate", (nd * sizeof(double) + ni * sizeof(int)) * nrhs + 64, &b));
+  double* d = (double*)b;
+  S.rr = d;
+  S.stop = d + nrhs;
+  S.ww = d + 2 * nrhs;
+  S.alpha = d + 3 * nrhs;
+  S.beta = d + 4 * nrhs;
+  S.tol2 = d + 5 * nrhs;
+  S.norm = d + 6 * nrhs;
+  int* ip = (int*)(d + nd * nrhs);
+  S.iter = ip;
+  S.max_iter = ip + nrhs;
+  S.halt = ip + 2 * nrhs;
+  S.u2run = ip + 3 * nrhs;
+  S.breakdown = ip + 4 * nrhs;
+  return EOFA_OK;
+}
+
+int hop(eofa_ctx* C, int prec, int role, HopArgs a, hipStream_t st, int* nblk = nullptr) {
+  const int rc = launch_hop(prec, role, a, st, nblk);
+  if (rc != EOFA_OK) return fail(rc, std::string("hop kernel launch failed: ") + hipGetErrorString(hipGetLastError()));
+  return EOFA_OK;
+}
+
+// device norms |f|^2 per rhs -> host out[nrhs] (synchronises)
+int norms(eofa_ctx* C, int prec, const void* f, int nrhs, double* partial, CgState S, std::vector<double>& out,
+          hipStream_t st) {
+  const int nb = launch_norm2(prec, C->g, f, nrhs, partial, st);
+  launch_finalize(FIN_NORM, partial, nb, nrhs, S, S.norm, st);
+  out.resize(nrhs);
+  HIPCHK(hipMemcpyAsync(C->host_stage, S.norm, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::memcpy(out.data(), C->host_stage, nrhs * sizeof(double));
+  return EOFA_OK;
+}
+
+int fetch(eofa_ctx* C, const void* dev, size_t bytes, void* host, hipStream_t st) {
+  HIPCHK(hipMemcpyAsync(C->host_stage, dev, bytes, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::memcpy(host, C->host_stage, bytes);
+  return EOFA_OK;
+}
+
+int put(eofa_ctx* C, void* dev, const void* host, size_t bytes, hipStream_t st) {
+  HIPCHK(hipStreamSynchronize(st));
+  std::memcpy(C->host_stage, host, bytes);
+  HIPCHK(hipMemcpyAsync(dev, C->host_stage, bytes, hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return EOFA_OK;
+}
+
+int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, void* psi,
+                const eofa_solver_params* prm, eofa_solver_stats* stats, hipStream_t st) {
+  const double t0 = now_s();
+  const Geometry& g = C->g;
+  const int S = prm->inner_prec;
+  const int PR = S == P64 ? P64 : P32;
+  const bool fixed = prm->fixed_iters > 0;
+  const int max_outer = fixed ? 1 : std::max(1, prm->max_outer);
+  const int check = prm->check_every > 0 ? prm->check_every : 16;
+  double inner_tol = prm->inner_tol;
+  if (!(inner_tol > 0.0)) inner_tol = S == P64 ? 0.3 * prm->tol : 1e-4;
+
+  CHK(upload_systems(C, sys, nrhs, st));
+  CHK(stage(C, 64 * (size_t)std::max(nrhs, 16)));
+  const size_t b64 = packed_bytes(P64, g, nrhs), bS = packed_bytes(S, g, nrhs), bR = packed_bytes(PR, g, nrhs);
+  void *be, *bo, *bt, *x, *ro, *te, *tmp, *rS, *pS, *tS, *wS, *rin, *xin, *partial_v;
+  CHK(ws(C, "be", b64, &be));
+  CHK(ws(C, "bo", b64, &bo));
+  CHK(ws(C, "bt", b64, &bt));
+  CHK(ws(C, "x", b64, &x));
+  CHK(ws(C, "ro", b64, &ro));
+  CHK(ws(C, "te", b64, &te));
+  CHK(ws(C, "tmp", b64, &tmp));
+  CHK(ws(C, "rS", bS, &rS));
+  CHK(ws(C, "pS", bS, &pS));
+  CHK(ws(C, "tS", bS, &tS));
+  CHK(ws(C, "wS", bS, &wS));
+  CHK(ws(C, "rin", bR, &rin));
+  CHK(ws(C, "xin", bR, &xin));
+  const int maxblk = std::max(hop_blocks(P64, g.Vh), std::max(hop_blocks(P32, g.Vh), (g.Ls * g.Vh + 255) / 256));
+  CHK(ws(C, "partial", sizeof(double) * (size_t)maxblk * nrhs, &partial_v));
+  double* partial = (double*)partial_v;
+  CgState Sst;
+  CHK(alloc_state(C, nrhs, Sst));
+
+  // b = g5 R5 phi, |b|^2
+  launch_pack(P64, g, phi, be, 0, nrhs, 1, st);
+  launch_pack(P64, g, phi, bo, 1, nrhs, 1, st);
+  HIPCHK(hipGetLastError());
+  std::vector<double> ne, no, bb(nrhs);
+  CHK(norms(C, P64, be, nrhs, partial, Sst, ne, st));
+  CHK(norms(C, P64, bo, nrhs, partial, Sst, no, st));
+  for (int r = 0; r < nrhs; ++r) bb[r] = ne[r] + no[r];
+
+  // Schur source b~_o = b_o - Dhop D~ M_ee^-1 b_e
+  launch_smat(P64, g, be, te, C->mats, MAT_MEE_INV, nrhs, st);
+  {
+    HopArgs a = base_args(C, P64, 1, nrhs);
+    a.in = te;
+    a.z = bo;
+    a.out = bt;
+    CHK(hop(C, P64, ROLE_SRC, a, st));
+  }
+  launch_zero(P64, g, x, nrhs, st);
+
+  std::vector<int> done(nrhs, 0), iters(nrhs, 0), outers(nrhs, 0), status(nrhs, EOFA_OK);
+  std::vector<double> rro;
+  std::vector<int> hbuf(4 * nrhs);
+  std::vector<double> hd(2 * nrhs);
+  double hop_ms[4] = {0, 0, 0, 0};
+  int timed = 0;
+  const int max_timed = 4096;
+  if (prm->profile && C->events.empty()) {
+    C->events.resize(8 * 64);
+    for (auto& ev : C->events) HIPCHK(hipEventCreate(&ev));
+  }
+
+  for (int outer = 0; outer < max_outer; ++outer) {
+    // r_o = b~ - M^ x  (FP64)
+    if (outer == 0) {
+      launch_convert(P64, P64, g, bt, ro, nrhs, st);
+      CHK(norms(C, P64, ro, nrhs, partial, Sst, rro, st));
+    } else {
+      HopArgs a1 = base_args(C, P64, 0, nrhs);
+      a1.in = x;
+      a1.out = te;
+      a1.matA = MAT_MEE_INV;
+      CHK(hop(C, P64, ROLE_K1, a1, st));
+      HopArgs a2 = base_args(C, P64, 1, nrhs);
+      a2.in = te;
+      a2.y = x;
+      a2.z = bt;
+      a2.out = ro;
+      a2.matB = MAT_MEE;
+      a2.partial = partial;
+      int nb = 0;
+      CHK(hop(C, P64, ROLE_RES, a2, st, &nb));
+      launch_finalize(FIN_NORM, partial, nb, nrhs, Sst, Sst.norm, st);
+      rro.resize(nrhs);
+      CHK(fetch(C, Sst.norm, nrhs * sizeof(double), rro.data(), st));
+    }
+    bool all = true;
+    for (int r = 0; r < nrhs; ++r) {
+      if (done[r]) continue;
+      const double res = bb[r] > 0 ? std::sqrt(rro[r] / bb[r]) : 0.0;
+      if (!fixed && res <= prm->tol) done[r] = 1;
+      if (!fixed && iters[r] >= prm->max_iter) done[r] = 1;
+      if (!done[r]) all = false;
+    }
+    if (all) break;
+    if (fixed && outer >= 1) break;
+
+    // inner CGNR in precision S on M^ e = r_o
+    std::vector<int> mi(nrhs);
+    std::vector<double> t2(nrhs);
+    for (int r = 0; r < nrhs; ++r) {
+      mi[r] = done[r] ? 0 : (fixed ? prm->fixed_iters : std::max(0, prm->max_iter - iters[r]));
+      t2[r] = fixed ? 0.0 : inner_tol * inner_tol;
+      if (!done[r]) outers[r] += 1;
+    }
+    CHK(put(C, Sst.max_iter, mi.data(), nrhs * sizeof(int), st));
+    CHK(put(C, Sst.tol2, t2.data(), nrhs * sizeof(double), st));
+    launch_convert(P64, S, g, ro, rS, nrhs, st);
+    {
+      HopArgs a3 = base_args(C, S, 0, nrhs);
+      a3.in = rS;
+      a3.out = tS;
+      a3.matA = MAT_MEE_INV_T_DT_T;
+      CHK(hop(C, S, ROLE_K3, a3, st));
+      HopArgs a4 = base_args(C, S, 1, nrhs);
+      a4.in = tS;
+      a4.y = rS;
+      a4.r = rin;
+      a4.matA = MAT_NEG_DT_T;
+      a4.matB = MAT_MEE_T;
+      a4.partial = partial;
+      int nb = 0;
+      CHK(hop(C, S, ROLE_K4S, a4, st, &nb));
+      launch_finalize(FIN_INIT, partial, nb, nrhs, Sst, nullptr, st);
+    }
+    launch_convert(PR, S, g, rin, pS, nrhs, st);
+    launch_zero(PR, g, xin, nrhs, st);
+
+    HopArgs k1 = base_args(C, S, 0, nrhs);
+    k1.in = pS;
+    k1.out = tS;
+    k1.matA = MAT_MEE_INV;
+    k1.halt = Sst.halt;
+    HopArgs k2 = base_args(C, S, 1, nrhs);
+    k2.in = tS;
+    k2.y = pS;
+    k2.out = wS;
+    k2.matB = MAT_MEE;
+    k2.partial = partial;
+    k2.halt = Sst.halt;
+    HopArgs k3 = base_args(C, S, 0, nrhs);
+    k3.in = wS;
+    k3.out = tS;
+    k3.matA = MAT_MEE_INV_T_DT_T;
+    k3.halt = Sst.halt;
+    HopArgs k4 = base_args(C, S, 1, nrhs);
+    k4.in = tS;
+    k4.y = wS;
+    k4.r = rin;
+    k4.matA = MAT_NEG_DT_T;
+    k4.matB = MAT_MEE_T;
+    k4.alpha = Sst.alpha;
+    k4.partial = partial;
+    k4.halt = Sst.halt;
+    const int nbh = hop_blocks(S, g.Vh);
+
+    int it = 0;
+    const int cap = fixed ? prm->fixed_iters : prm->max_iter + 1;
+    while (true) {
+      const bool prof = prm->profile && timed < max_timed && (it % 8 == 0);
+      hipEvent_t* ev = prof ? &C->events[(timed % 64) * 8] : nullptr;
+      if (prof) HIPCHK(hipEventRecord(ev[0], st));
+      CHK(hop(C, S, ROLE_K1, k1, st));
+      if (prof) HIPCHK(hipEventRecord(ev[1], st));
+      if (prof) HIPCHK(hipEventRecord(ev[2], st));
+      CHK(hop(C, S, ROLE_K2, k2, st));
+      if (prof) HIPCHK(hipEventRecord(ev[3], st));
+      launch_finalize(FIN_ALPHA, partial, nbh, nrhs, Sst, nullptr, st);
+      if (prof) HIPCHK(hipEventRecord(ev[4], st));
+      CHK(hop(C, S, ROLE_K3, k3, st));
+      if (prof) HIPCHK(hipEventRecord(ev[5], st));
+      if (prof) HIPCHK(hipEventRecord(ev[6], st));
+      CHK(hop(C, S, ROLE_K4, k4, st));
+      if (prof) HIPCHK(hipEventRecord(ev[7], st));
+      launch_finalize(FIN_BETA, partial, nbh, nrhs, Sst, nullptr, st);
+      launch_cg_update(S, PR, g, xin, rin, pS, Sst.alpha, Sst.beta, Sst.u2run, nrhs, st);
+      if (prof) {
+        HIPCHK(hipEventSynchronize(ev[7]));
+        float ms;
+        for (int k = 0; k < 4; ++k) {
+          HIPCHK(hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
+          hop_ms[k] += ms;
+        }
+        ++timed;
+      }
+      ++it;
+      if (it % check == 0 || it >= cap) {
+        CHK(fetch(C, Sst.halt, nrhs * sizeof(int), hbuf.data(), st));
+        bool stop = true;
+        for (int r = 0; r < nrhs; ++r) stop = stop && hbuf[r] != 0;
+        if (stop || it >= cap) break;
+      }
+    }
+    HIPCHK(hipGetLastError());
+    launch_axpy_to64(PR, g, x, xin, nrhs, st);
+    std::vector<int> hi(nrhs), hb(nrhs);
+    CHK(fetch(C, Sst.iter, nrhs * sizeof(int), hi.data(), st));
+    CHK(fetch(C, Sst.breakdown, nrhs * sizeof(int), hb.data(), st));
+    for (int r = 0; r < nrhs; ++r) {
+      if (done[r]) continue;
+      iters[r] += hi[r];
+      if (hb[r]) {
+        status[r] = EOFA_ERR_BREAKDOWN;
+        done[r] = 1;
+      }
+    }
+  }
+
+  // reconstruct psi'_e = M_ee^-1 (b_e - Dhop D~ x_o)
+  {
+    HopArgs a = base_args(C, P64, 0, nrhs);
+    a.in = x;
+    a.z = be;
+    a.out = tmp;
+    CHK(hop(C, P64, ROLE_SRC, a, st));
+  }
+  launch_smat(P64, g, tmp, te, C->mats, MAT_MEE_INV, nrhs, st);
+  // FP64 true residual of the Cayley system on both parities
+  std::vector<double> re(nrhs), rodd(nrhs);
+  {
+    HopArgs a = base_args(C, P64, 0, nrhs);
+    a.in = x;
+    a.y = te;
+    a.z = be;
+    a.out = tmp;
+    a.matB = MAT_MEE;
+    a.partial = partial;
+    int nb = 0;
+    CHK(hop(C, P64, ROLE_FULLRES, a, st, &nb));
+    launch_finalize(FIN_NORM, partial, nb, nrhs, Sst, Sst.norm, st);
+    CHK(fetch(C, Sst.norm, nrhs * sizeof(double), re.data(), st));
+    HopArgs b = base_args(C, P64, 1, nrhs);
+    b.in = te;
+    b.y = x;
+    b.z = bo;
+    b.out = ro;
+    b.matB = MAT_MEE;
+    b.partial = partial;
+    CHK(hop(C, P64, ROLE_FULLRES, b, st, &nb));
+    launch_finalize(FIN_NORM, partial, nb, nrhs, Sst, Sst.norm, st);
+    CHK(fetch(C, Sst.norm, nrhs * sizeof(double), rodd.data(), st));
+  }
+  // psi = D~ psi'
+  launch_smat(P64, g, te, tmp, C->mats, MAT_DT, nrhs, st);
+  launch_unpack(P64, g, tmp, psi, 0, nrhs, st);
+  launch_smat(P64, g, x, ro, C->mats, MAT_DT, nrhs, st);
+  launch_unpack(P64, g, ro, psi, 1, nrhs, st);
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+  const double t1 = now_s();
+
+  int worst = EOFA_OK;
+  for (int r = 0; r < nrhs; ++r) {
+    const double tr = bb[r] > 0 ? std::sqrt((re[r] + rodd[r]) / bb[r]) : 0.0;
+    const bool conv = std::isfinite(tr) && tr <= prm->tol;
+    if (status[r] == EOFA_OK && !conv && !fixed) status[r] = std::isfinite(tr) ? EOFA_ERR_NOT_CONVERGED : EOFA_ERR_BREAKDOWN;
+    if (stats) {
+      eofa_solver_stats& o = stats[r];
+      std::memset(&o, 0, sizeof(o));
+      o.iters = iters[r];
+      o.outer_iters = outers[r];
+      o.converged = conv ? 1 : 0;
+      o.status = status[r];
+      o.true_resid = tr;
+      o.seconds = t1 - t0;
+      for (int k = 0; k < 4; ++k) o.hop_ms[k] = hop_ms[k];
+      o.hop_timed = timed;
+    }
+    if (status[r] != EOFA_OK && (worst == EOFA_OK || status[r] == EOFA_ERR_BREAKDOWN)) worst = status[r];
+  }
+  if (worst == EOFA_ERR_NOT_CONVERGED) g_err = "solve did not reach the requested true residual";
+  if (worst == EOFA_ERR_BREAKDOWN) g_err = "CG breakdown (non-finite value or non-positive curvature)";
+  return worst;
+}
+
+int check_params(const eofa_solver_params* prm) {
+  if (!prm) return fail(EOFA_ERR_INVALID, "params is NULL");
+  CHK(check_prec(prm->inner_prec));
+  if (prm->fixed_iters <= 0 && !(prm->tol > 0.0)) return fail(EOFA_ERR_INVALID, "tol must be > 0");
+  if (prm->fixed_iters <= 0 && prm->max_iter < 1) return fail(EOFA_ERR_INVALID, "max_iter must be >= 1");
+  return EOFA_OK;
+}
+
+}  // namespace
+
+extern "C" int eofa_cg_solve(eofa_ctx* C, const eofa_system* sys, const void* phi, void* psi, int32_t nrhs,
+                             const eofa_solver_params* prm, eofa_solver_stats* stats, void* stream) {
+  if (!C || !phi || !psi) return fail(EOFA_ERR_INVALID, "eofa_cg_solve: NULL argument");
+  if (phi == psi) return fail(EOFA_ERR_INVALID, "eofa_cg_solve: phi and psi alias");
+  CHK(check_systems(sys, nrhs));
+  CHK(check_params(prm));
+  return solve_batch(C, sys, nrhs, phi, psi, prm, stats, (hipStream_t)stream);
+}
+
+extern "C" int eofa_fifth_matrix(const eofa_action* act, const eofa_system* sys, int32_t mat, double* out) {
+  if (!act || !sys || !out) return fail(EOFA_ERR_INVALID, "eofa_fifth_matrix: NULL argument");
+  if (mat < 0 || mat >= NMAT) return fail(EOFA_ERR_INVALID, "matrix id out of range");
+  if (act->Ls < 2 || act->Ls > 32 || act->Ls % 2 != 0) return fail(EOFA_ERR_INVALID, "Ls must be even, 2..32");
+  if (std::fabs(act->b5 - act->c5 - 1.0) > 1e-12) return fail(EOFA_ERR_INVALID, "b5 - c5 must be 1 (d = 1/2)");
+  CHK(check_systems(sys, 1));
+  Geometry g;
+  for (int k = 0; k < 4; ++k) g.L[k] = act->dims[k];
+  g.Ls = act->Ls;
+  g.V = g.Vh = 0;
+  const size_t n = (size_t)g.Ls * g.Ls;
+  std::vector<double> all(NMAT * 2 * n);
+  std::string err;
+  const int rc = build_fifth(g, act->M5, act->b5, act->c5, *sys, all.data(), err);
+  if (rc != EOFA_OK) return fail(rc, err);
+  std::memcpy(out, all.data() + (size_t)mat * 2 * n, sizeof(double) * 2 * n);
+  return EOFA_OK;
+}
+
+extern "C" int eofa_heatbath_solve(eofa_ctx* C, double m1, double m2, int32_t n_poles, const double* alpha,
+                                   const double* beta, const void* eta, void* phi,
+                                   const eofa_solver_params* prm, eofa_solver_stats* stats, void* stream) {
+  if (!C || !alpha || !beta || !eta || !phi) return fail(EOFA_ERR_INVALID, "eofa_heatbath_solve: NULL argument");
+  if (eta == phi) return fail(EOFA_ERR_INVALID, "eofa_heatbath_solve: eta and phi alias");
+  if (n_poles < 1) return fail(EOFA_ERR_INVALID, "n_poles must be >= 1");
+  CHK(check_params(prm));
+  hipStream_t st = (hipStream_t)stream;
+  const Geometry& g = C->g;
+  const int nsys = 2 * n_poles;
+  std::vector<eofa_system> sys(nsys);
+  std::vector<double> coef(nsys), om(nsys * g.Ls);
+  std::vector<int> chir(nsys);
+  std::vector<double> wp(g.Ls), wm(g.Ls);
+  omega_col(g.Ls, C->c, C->d, +1, wp.data());
+  omega_col(g.Ls, C->c, C->d, -1, wm.data());
+  const double k = k_eofa(g.Ls, C->c, C->d, m1, m2);
+  double a_eta = alpha[0];
+  for (int l = 0; l < n_poles; ++l) {
+    const double bl = beta[l];
+    if (!(1.0 + bl != 0.0) || !std::isfinite(bl)) return fail(EOFA_ERR_INVALID, "pole beta_l = -1 or non-finite");
+    const double gl = 1.0 / (1.0 + bl);
+    a_eta += alpha[l + 1] * gl;
+    // LH: (H(m1) - gamma_l Delta_-(m1,m2) P_-),  RH: (H(m2) - beta_l gamma_l Delta_+(m1,m2) P_+)
+    sys[l] = eofa_system{m1, m1, m2, -gl, -1};
+    sys[n_poles + l] = eofa_system{m2, m1, m2, -bl * gl, +1};
+    coef[l] = alpha[l + 1] * gl * k * gl;
+    coef[n_poles + l] = -alpha[l + 1] * gl * k * gl;
+    chir[l] = -1;
+    chir[n_poles + l] = +1;
+    for (int s = 0; s < g.Ls; ++s) {
+      om[l * g.Ls + s] = wm[s];
+      om[(n_poles + l) * g.Ls + s] = wp[s];
+    }
+  }
+  const size_t fbytes = (size_t)g.Ls * g.V * 12 * 16;
+  void *rhs, *sol, *cdev;
+  CHK(ws(C, "hb_rhs", fbytes * nsys, &rhs));
+  CHK(ws(C, "hb_sol", fbytes * nsys, &sol));
+  const size_t cbytes = sizeof(double) * (nsys + nsys * g.Ls) + sizeof(int) * nsys;
+  CHK(ws(C, "hb_coef", cbytes, &cdev));
+  CHK(stage(C, cbytes));
+  {
+    std::vector<unsigned char> h(cbytes);
+    std::memcpy(h.data(), coef.data(), sizeof(double) * nsys);
+    std::memcpy(h.data() + sizeof(double) * nsys, om.data(), sizeof(double) * nsys * g.Ls);
+    std::memcpy(h.data() + sizeof(double) * (nsys + nsys * g.Ls), chir.data(), sizeof(int) * nsys);
+    CHK(put(C, cdev, h.data(), cbytes, st));
+  }
+  const double* d_coef = (const double*)cdev;
+  const double* d_om = d_coef + nsys;
+  const int* d_chir = (const int*)(d_om + nsys * g.Ls);
+  launch_omega_rhs(g, eta, rhs, d_om, d_chir, nsys, st);
+  HIPCHK(hipGetLastError());
+  std::vector<eofa_solver_stats> st_local(nsys);
+  const int rc = solve_batch(C, sys.data(), nsys, rhs, sol, prm, stats ? stats : st_local.data(), st);
+  if (rc != EOFA_OK && rc != EOFA_ERR_NOT_CONVERGED) return rc;
+  launch_heatbath_combine(g, eta, sol, phi, a_eta, d_coef, d_om, d_chir, nsys, st);
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+  return rc;
+}

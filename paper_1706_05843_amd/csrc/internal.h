@@ -1,0 +1,126 @@
+// Internal declarations shared by the host solver and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/eofa.h"
+
+namespace eofa {
+
+enum Prec { P64 = 0, P32 = 1, P16 = 2 };
+
+// Per-system fifth-dimension matrices, [NMAT][2 chiralities][Ls][Ls] doubles.
+// chirality index 0 multiplies P_+ psi, index 1 multiplies P_- psi.
+enum MatId {
+  MAT_MEE = 0,         // M_ee = bee - cee L(m_op) + chi beta u v^T P_chi
+  MAT_MEE_INV,         // M_ee^-1 (Sherman-Morrison on an LU inverse)
+  MAT_MEE_T,           // M_ee^T
+  MAT_MEE_INV_T,       // M_ee^-T
+  MAT_MEE_INV_T_DT_T,  // M_ee^-T D~^T
+  MAT_NEG_DT_T,        // -D~^T
+  MAT_DT_T,            // D~^T
+  MAT_DT,              // D~ = (c+d) + (c-d) L(m_op)
+  NMAT
+};
+
+struct Geometry {
+  int L[4];  // Lx, Ly, Lz, Lt
+  int Ls;
+  int V, Vh;
+};
+
+// host: build the matrices of one system; returns EOFA_OK or an error code
+int build_fifth(const Geometry& g, double M5, double b5, double c5, const eofa_system& sys,
+                double* out /* NMAT*2*Ls*Ls */, std::string& err);
+// host: EOFA constant k(m_a, m_b) and the Omega_+- columns (App. A)
+double k_eofa(int Ls, double c, double d, double m_a, double m_b);
+void omega_col(int Ls, double c, double d, int chir, double* w /* Ls */);
+
+// Device-side CG scalars, one entry per right-hand side (struct of arrays).
+struct CgState {
+  double* rr;      // |r|^2 of the normal-equation residual
+  double* stop;    // stop when rr <= stop
+  double* ww;      // |M p|^2
+  double* alpha;
+  double* beta;
+  double* tol2;    // inner_tol^2 per rhs
+  double* norm;    // scratch norms (FIN_NORM target)
+  int* iter;
+  int* max_iter;
+  int* halt;       // 1: this rhs does no more CG work
+  int* u2run;      // 1: the x/p update of this iteration runs
+  int* breakdown;  // 1: non-finite or non-positive curvature met
+};
+
+enum FinMode { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_NORM = 3 };
+
+// Roles of the fused hop kernel (see kernels.hip).
+enum HopRole {
+  ROLE_DSLASH = 0,   // out = Dhop D~ in
+  ROLE_DSLASH_DAG,   // out = D~^T g5 Dhop g5 in
+  ROLE_K1,           // out = A (Dhop D~ in)
+  ROLE_K2,           // out = B y - Dhop D~ in, |out|^2
+  ROLE_K3,           // out = A (g5 Dhop g5 in)
+  ROLE_K4,           // r -= alpha (A g5Dhopg5 in + B y), |r|^2
+  ROLE_K4S,          // r  = A g5Dhopg5 in + B y, |r|^2   (r in accumulator precision)
+  ROLE_SRC,          // out = z - Dhop D~ in
+  ROLE_RES,          // out = z - (B y - Dhop D~ in), |out|^2
+  ROLE_FULLRES,      // out = z - (B y + Dhop D~ in), |out|^2
+  NROLE
+};
+
+struct HopArgs {
+  const void* in;     // packed, parity 1-p, storage precision
+  void* out;          // packed, parity p, storage precision
+  const void* y;      // packed, parity p (B y term)
+  const void* z;      // packed, parity p (ADDZ)
+  void* r;            // packed, parity p, accumulator precision (K4/K4S)
+  const void* links;  // [Vh][8][9] complex for output parity p
+  const int* nbr;     // [Vh][8] checkerboard index in parity 1-p
+  const double* mats; // [nrhs][NMAT][2][Ls][Ls]
+  int matA, matB;
+  double cpd, cmd;    // c+d, c-d (premix)
+  const double* mop;  // [nrhs] operator mass
+  const double* alpha;
+  const int* halt;    // may be null
+  double* partial;    // [nrhs][gridDim.x]
+  int Vh, Ls, nrhs, rhs_block;
+};
+
+// kernel launchers (kernels.hip)
+int launch_hop(int prec, int role, const HopArgs& a, hipStream_t st, int* nblk_out);
+int hop_blocks(int prec, int Vh);
+void launch_pack(int prec, const Geometry& g, const void* full, void* packed, int parity, int nrhs,
+                 int g5r5, hipStream_t st);
+void launch_unpack(int prec, const Geometry& g, const void* packed, void* full, int parity, int nrhs,
+                   hipStream_t st);
+void launch_gauge_pack(const Geometry& g, const void* gauge, const int bc[4], void* l64[2], void* l32[2],
+                       void* l16[2], int* nbr[2], hipStream_t st);
+void launch_smat(int prec, const Geometry& g, const void* in, void* out, const double* mats, int mat,
+                 int nrhs, hipStream_t st);
+void launch_convert(int pin, int pout, const Geometry& g, const void* in, void* out, int nrhs,
+                    hipStream_t st);
+void launch_axpy_to64(int pin, const Geometry& g, void* x64, const void* e, int nrhs, hipStream_t st);
+void launch_zero(int prec, const Geometry& g, void* f, int nrhs, hipStream_t st);
+int launch_norm2(int prec, const Geometry& g, const void* f, int nrhs, double* partial, hipStream_t st);
+void launch_cg_update(int ps, int pr, const Geometry& g, void* x, const void* r, void* p, const double* alpha,
+                      const double* beta, const int* u2run, int nrhs, hipStream_t st);
+void launch_finalize(int mode, const double* partial, int nblk, int nrhs, CgState st_, double* out,
+                     hipStream_t st);
+
+// heatbath helpers on canonical complex128 fields [nsys][Ls][V][4][3]
+//   rhs[r]_s = om[r][s] P_chir[r] eta_0                      (Omega P eta, App. A)
+//   phi_s    = a_eta eta_s + delta_{s,0} sum_r coef[r] P_chir[r] sum_s' om[r][s'] sol[r]_s'
+void launch_omega_rhs(const Geometry& g, const void* eta, void* rhs, const double* om, const int* chir, int nsys,
+                      hipStream_t st);
+void launch_heatbath_combine(const Geometry& g, const void* eta, const void* sol, void* phi, double a_eta,
+                             const double* coef, const double* om, const int* chir, int nsys, hipStream_t st);
+
+size_t packed_bytes(int prec, const Geometry& g, int nrhs);
+size_t link_bytes(int prec, const Geometry& g);
+
+}  // namespace eofa

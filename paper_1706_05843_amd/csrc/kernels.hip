@@ -1,0 +1,1063 @@
+// HIP kernels for gfx950 (CDNA4, 64-wide wavefronts).
+//
+// Operators (Sec. II, eqn Ddwf; App. B):
+//   Dhop psi(x) = -1/2 sum_mu [ (1 - g_mu) U_mu(x) psi(x+mu) + (1 + g_mu) U_mu(x-mu)^dag psi(x-mu) ]
+//   D~ = (c+d) + (c-d) L(m):  (D~ psi)_s = (c+d) psi_s + (c-d) (P_+ (L_+ psi)_s + P_- (L_- psi)_s)
+//   (L_+ psi)_s = psi_{s-1} (s >= 1), -m psi_{Ls-1} (s = 0);  (L_- psi)_s = psi_{s+1}, -m psi_0 at Ls-1
+// The off-parity block of D_DWF is Dhop D~; its adjoint is D~^T g5 Dhop g5, and
+// g5 Dhop g5 is Dhop with (1 -+ g_mu) swapped.
+//
+// Layout: see include/eofa.h. One thread owns one 5D site (i, s); a work-group
+// holds SB consecutive 4D sites with their whole Ls column, so
+//  * the 8 links of each 4D site are staged once in LDS and reused by all Ls
+//    threads of that site and by every right-hand side of the block;
+//  * the Ls x Ls fifth-dimension epilogues (M_ee^-1, M_ee, D~^T) exchange the
+//    column through LDS.
+// Spin projection: in the chiral basis g_mu = [[0, A_mu], [A_mu^dag, 0]], so
+// (1 + sg g_mu) psi = [h ; sg A^dag h] with h = psi_up + sg A psi_lo: the link
+// multiplies a 2-spinor only.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+
+#include "internal.h"
+
+namespace eofa {
+
+typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+
+template <class T>
+struct cx {
+  T r, i;
+};
+template <class T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.r + b.r, a.i + b.i}; }
+template <class T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.r - b.r, a.i - b.i}; }
+template <class T>
+__device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return {s * a.r, s * a.i}; }
+template <class T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r};
+}
+template <class T>
+__device__ __forceinline__ cx<T> cfma(cx<T> a, cx<T> b, cx<T> c) {  // a*b + c
+  return {fma(a.r, b.r, fma(-a.i, b.i, c.r)), fma(a.r, b.i, fma(a.i, b.r, c.i))};
+}
+template <class T>
+__device__ __forceinline__ cx<T> mul_i(cx<T> a) { return {-a.i, a.r}; }  // i a
+
+template <int P>
+struct ST;
+template <>
+struct ST<P64> {
+  using R = double;
+};
+template <>
+struct ST<P32> {
+  using R = float;
+};
+template <>
+struct ST<P16> {
+  using R = float;
+};
+
+// ---------------------------------------------------------------------------
+// packed field access
+
+struct FD {
+  int Ls, Vh, nrhs;
+};
+
+__device__ __forceinline__ size_t eidx(const FD& f, int r, int q, int s, int i) {
+  return ((size_t)(r * 6 + q) * f.Ls + s) * f.Vh + i;
+}
+__device__ __forceinline__ const float* scale_ptr(const void* base, const FD& f) {
+  return (const float*)((const char*)base + (size_t)f.nrhs * 6 * f.Ls * f.Vh * 8);
+}
+__device__ __forceinline__ size_t sidx(const FD& f, int r, int s, int i) {
+  return ((size_t)r * f.Ls + s) * f.Vh + i;
+}
+
+template <int P>
+__device__ __forceinline__ void ld_pair(const void* base, size_t e, cx<typename ST<P>::R>& a,
+                                        cx<typename ST<P>::R>& b) {
+  if constexpr (P == P64) {
+    const double2* p = (const double2*)base + 2 * e;
+    const double2 v0 = p[0], v1 = p[1];
+    a = {v0.x, v0.y};
+    b = {v1.x, v1.y};
+  } else if constexpr (P == P32) {
+    const float4 v = ((const float4*)base)[e];
+    a = {v.x, v.y};
+    b = {v.z, v.w};
+  } else {
+    const uint2 v = ((const uint2*)base)[e];
+    const h2_t h0 = __builtin_bit_cast(h2_t, v.x);
+    const h2_t h1 = __builtin_bit_cast(h2_t, v.y);
+    a = {(float)h0.x, (float)h0.y};
+    b = {(float)h1.x, (float)h1.y};
+  }
+}
+
+template <int P>
+__device__ __forceinline__ void st_pair(void* base, size_t e, cx<typename ST<P>::R> a,
+                                        cx<typename ST<P>::R> b) {
+  if constexpr (P == P64) {
+    double2* p = (double2*)base + 2 * e;
+    p[0] = make_double2(a.r, a.i);
+    p[1] = make_double2(b.r, b.i);
+  } else if constexpr (P == P32) {
+    ((float4*)base)[e] = make_float4(a.r, a.i, b.r, b.i);
+  } else {
+    h2_t h0, h1;
+    h0.x = (_Float16)a.r;
+    h0.y = (_Float16)a.i;
+    h1.x = (_Float16)b.r;
+    h1.y = (_Float16)b.i;
+    uint2 v;
+    v.x = __builtin_bit_cast(unsigned int, h0);
+    v.y = __builtin_bit_cast(unsigned int, h1);
+    ((uint2*)base)[e] = v;
+  }
+}
+
+// load pairs [q0, q1) of the spinor at (r, s, i) into v[2*q0 .. 2*q1)
+template <int P, class R>
+__device__ __forceinline__ void ld_spinor(const void* base, const FD& f, int r, int s, int i, cx<R>* v,
+                                          int q0 = 0, int q1 = 6) {
+  R sc = R(1);
+  if constexpr (P == P16) sc = scale_ptr(base, f)[sidx(f, r, s, i)];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    if (q < q0 || q >= q1) continue;
+    cx<R> a, b;
+    ld_pair<P>(base, eidx(f, r, q, s, i), a, b);
+    if constexpr (P == P16) {
+      a = sc * a;
+      b = sc * b;
+    }
+    v[2 * q] = a;
+    v[2 * q + 1] = b;
+  }
+}
+
+template <int P, class R>
+__device__ __forceinline__ void st_spinor(void* base, const FD& f, int r, int s, int i, const cx<R>* v) {
+  if constexpr (P == P16) {
+    float m = 0.f;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf((float)v[c].r), fabsf((float)v[c].i)));
+    const float inv = m > 0.f ? 1.0f / m : 0.f;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      cx<float> a = {(float)v[2 * q].r * inv, (float)v[2 * q].i * inv};
+      cx<float> b = {(float)v[2 * q + 1].r * inv, (float)v[2 * q + 1].i * inv};
+      st_pair<P16>(base, eidx(f, r, q, s, i), a, b);
+    }
+    float* sp = (float*)scale_ptr(base, f);
+    sp[sidx(f, r, s, i)] = m;
+  } else {
+    using RS = typename ST<P>::R;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      cx<RS> a = {(RS)v[2 * q].r, (RS)v[2 * q].i};
+      cx<RS> b = {(RS)v[2 * q + 1].r, (RS)v[2 * q + 1].i};
+      st_pair<P>(base, eidx(f, r, q, s, i), a, b);
+    }
+  }
+}
+
+template <int P>
+__device__ __forceinline__ cx<typename ST<P>::R> ld_link(const void* base, size_t j) {
+  if constexpr (P == P64) {
+    const double2 v = ((const double2*)base)[j];
+    return {v.x, v.y};
+  } else if constexpr (P == P32) {
+    const float2 v = ((const float2*)base)[j];
+    return {v.x, v.y};
+  } else {
+    const h2_t h = __builtin_bit_cast(h2_t, ((const unsigned int*)base)[j]);
+    return {(float)h.x, (float)h.y};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the fused hop kernel
+
+enum { A_ID = 0, A_NEG = 1, A_MAT = 2 };
+enum { O_STORE = 0, O_ADDZ = 1, O_RUPD = 2, O_STORE_R = 3 };
+
+template <int ROLE>
+struct RoleT;
+#define EOFA_ROLE(NAME, dag, pre, am, bm, om, nrm)   \
+  template <>                                        \
+  struct RoleT<NAME> {                               \
+    static constexpr bool DAG = dag, PRE = pre;      \
+    static constexpr int AM = am;                    \
+    static constexpr bool BM = bm;                   \
+    static constexpr int OM = om;                    \
+    static constexpr bool NRM = nrm;                 \
+  };
+EOFA_ROLE(ROLE_DSLASH, false, true, A_ID, false, O_STORE, false)
+EOFA_ROLE(ROLE_DSLASH_DAG, true, false, A_MAT, false, O_STORE, false)
+EOFA_ROLE(ROLE_K1, false, true, A_MAT, false, O_STORE, false)
+EOFA_ROLE(ROLE_K2, false, true, A_NEG, true, O_STORE, true)
+EOFA_ROLE(ROLE_K3, true, false, A_MAT, false, O_STORE, false)
+EOFA_ROLE(ROLE_K4, true, false, A_MAT, true, O_RUPD, true)
+EOFA_ROLE(ROLE_K4S, true, false, A_MAT, true, O_STORE_R, true)
+EOFA_ROLE(ROLE_SRC, false, true, A_ID, false, O_ADDZ, false)
+EOFA_ROLE(ROLE_RES, false, true, A_NEG, true, O_ADDZ, true)
+EOFA_ROLE(ROLE_FULLRES, false, true, A_ID, true, O_ADDZ, true)
+#undef EOFA_ROLE
+
+constexpr int LSTR = 73;  // padded link stride per site in LDS (complex units)
+constexpr int NSTR = 9;   // padded neighbour stride per site in LDS
+
+template <int P>
+constexpr int sites_per_block() {
+  return P == P64 ? 8 : 16;
+}
+
+template <class R>
+struct HopLds {
+  // byte sizes of the LDS regions
+  static __host__ __device__ size_t links(int SB) { return (size_t)SB * LSTR * sizeof(cx<R>); }
+  static __host__ __device__ size_t nbr(int SB) { return (size_t)SB * NSTR * 4; }
+  static __host__ __device__ size_t mat(int Ls) { return (((size_t)2 * Ls * (Ls + 1) * sizeof(R) + 15) / 16) * 16; }
+  static __host__ __device__ size_t col(int SB, int Ls) { return (size_t)SB * (Ls * 6 + 1) * sizeof(cx<R>); }
+};
+
+// Dhop (or g5 Dhop g5 when DAG) applied to D~ in (PRE) at 5D site (s, neighbours of il)
+template <int P, bool DAG, bool PRE>
+__device__ __forceinline__ void hop_site(const HopArgs& a, const FD& fin, int r, int s, int il,
+                                         const cx<typename ST<P>::R>* s_link, const int* s_nbr,
+                                         cx<typename ST<P>::R>* acc) {
+  using R = typename ST<P>::R;
+  const int Ls = a.Ls;
+  R cpd = R(1), aup = R(0), alo = R(0);
+  int sup = 0, slo = 0;
+  if constexpr (PRE) {
+    const R cmd = (R)a.cmd;
+    const R m = (R)a.mop[r];
+    cpd = (R)a.cpd;
+    sup = s > 0 ? s - 1 : Ls - 1;
+    aup = s > 0 ? cmd : -m * cmd;
+    slo = s < Ls - 1 ? s + 1 : 0;
+    alo = s < Ls - 1 ? cmd : -m * cmd;
+  }
+#pragma unroll
+  for (int c = 0; c < 12; ++c) acc[c] = {R(0), R(0)};
+#pragma unroll
+  for (int dir = 0; dir < 8; ++dir) {
+    const int mu = dir & 3;
+    const bool fwd = dir < 4;
+    const int n = s_nbr[il * NSTR + dir];
+    cx<R> sp[12];
+    ld_spinor<P>(a.in, fin, r, s, n, sp);
+    if constexpr (PRE) {
+      cx<R> t[12];
+      ld_spinor<P>(a.in, fin, r, sup, n, t, 0, 3);
+      ld_spinor<P>(a.in, fin, r, slo, n, t, 3, 6);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) sp[c] = cpd * sp[c] + aup * t[c];
+#pragma unroll
+      for (int c = 6; c < 12; ++c) sp[c] = cpd * sp[c] + alo * t[c];
+    }
+    // sg = -1 for (1 - g_mu), +1 for (1 + g_mu)
+    const R sg = (fwd != DAG) ? R(-1) : R(1);
+    cx<R> h[6];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const cx<R> u0 = sp[c], u1 = sp[3 + c], l0 = sp[6 + c], l1 = sp[9 + c];
+      if (mu == 0) {  // A = -i sigma_1
+        h[c] = u0 - sg * mul_i(l1);
+        h[3 + c] = u1 - sg * mul_i(l0);
+      } else if (mu == 1) {  // A = -i sigma_2
+        h[c] = u0 - sg * l1;
+        h[3 + c] = u1 + sg * l0;
+      } else if (mu == 2) {  // A = -i sigma_3
+        h[c] = u0 - sg * mul_i(l0);
+        h[3 + c] = u1 + sg * mul_i(l1);
+      } else {  // A = 1
+        h[c] = u0 + sg * l0;
+        h[3 + c] = u1 + sg * l1;
+      }
+    }
+    const cx<R>* U = s_link + il * LSTR + dir * 9;
+    cx<R> g[6];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int a3 = 0; a3 < 3; ++a3) {
+        cx<R> v = cmul(U[a3 * 3 + 0], h[k * 3 + 0]);
+        v = cfma(U[a3 * 3 + 1], h[k * 3 + 1], v);
+        v = cfma(U[a3 * 3 + 2], h[k * 3 + 2], v);
+        g[k * 3 + a3] = v;
+      }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const cx<R> g0 = g[c], g1 = g[3 + c];
+      acc[c] = acc[c] + g0;
+      acc[3 + c] = acc[3 + c] + g1;
+      if (mu == 0) {  // A^dag g = (i g1, i g0)
+        acc[6 + c] = acc[6 + c] + sg * mul_i(g1);
+        acc[9 + c] = acc[9 + c] + sg * mul_i(g0);
+      } else if (mu == 1) {  // A^dag g = (g1, -g0)
+        acc[6 + c] = acc[6 + c] + sg * g1;
+        acc[9 + c] = acc[9 + c] - sg * g0;
+      } else if (mu == 2) {  // A^dag g = (i g0, -i g1)
+        acc[6 + c] = acc[6 + c] + sg * mul_i(g0);
+        acc[9 + c] = acc[9 + c] - sg * mul_i(g1);
+      } else {
+        acc[6 + c] = acc[6 + c] + sg * g0;
+        acc[9 + c] = acc[9 + c] + sg * g1;
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 12; ++c) acc[c] = R(-0.5) * acc[c];
+}
+
+template <class R>
+__device__ __forceinline__ void load_mat(R* dst, const double* src, int Ls, int tid, int nthr) {
+  // src: [2][Ls][Ls] doubles -> dst rows padded to Ls+1
+  for (int j = tid; j < 2 * Ls * Ls; j += nthr) {
+    const int ch = j / (Ls * Ls), rem = j % (Ls * Ls), row = rem / Ls, col = rem % Ls;
+    dst[(ch * Ls + row) * (Ls + 1) + col] = (R)src[j];
+  }
+}
+
+// out(s) for one chirality half: v[c] = sum_s' M[ch][s][s'] col[s'][c]
+template <class R>
+__device__ __forceinline__ void col_matvec(const R* M, const cx<R>* col, int Ls, int s, int half,
+                                           cx<R>* v, bool accumulate) {
+  const R* row = M + (half * Ls + s) * (Ls + 1);
+  cx<R> t[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) t[c] = accumulate ? v[half * 6 + c] : cx<R>{R(0), R(0)};
+  for (int sp = 0; sp < Ls; ++sp) {
+    const R m = row[sp];
+    const cx<R>* src = col + sp * 6;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      t[c].r = fma(m, src[c].r, t[c].r);
+      t[c].i = fma(m, src[c].i, t[c].i);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) v[half * 6 + c] = t[c];
+}
+
+template <int P, int PR, int SB, int ROLE>
+__global__ void __launch_bounds__(512) hop_kernel(HopArgs a) {
+  using RT = RoleT<ROLE>;
+  using R = typename ST<P>::R;
+  using L = HopLds<R>;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  __shared__ double s_red[16];
+
+  const int Ls = a.Ls, Vh = a.Vh;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int il = tid % SB;
+  const int s = tid / SB;
+  const int i0 = blockIdx.x * SB;
+  const int i = i0 + il;
+  const bool live = (s < Ls) && (i < Vh);
+  const FD fd = {Ls, Vh, a.nrhs};
+
+  unsigned char* p = smem;
+  cx<R>* s_link = (cx<R>*)p;
+  p += L::links(SB);
+  int* s_nbr = (int*)p;
+  p += L::nbr(SB);
+  R* s_mA = (R*)p;
+  if (RT::AM == A_MAT) p += L::mat(Ls);
+  R* s_mB = (R*)p;
+  if (RT::BM) p += L::mat(Ls);
+  cx<R>* s_col = (cx<R>*)p;  // SB x (Ls*6+1) complex: one chirality half of a column
+  const int cstr = Ls * 6 + 1;
+
+  // stage the links and neighbour indices of this block's sites
+  for (int j = tid; j < SB * 72; j += nthr) {
+    const int site = j / 72, k = j % 72;
+    cx<R> v = {R(0), R(0)};
+    if (i0 + site < Vh) v = ld_link<P>(a.links, (size_t)(i0 + site) * 72 + k);
+    s_link[site * LSTR + k] = v;
+  }
+  for (int j = tid; j < SB * 8; j += nthr) {
+    const int site = j / 8, k = j % 8;
+    s_nbr[site * NSTR + k] = (i0 + site < Vh) ? a.nbr[(size_t)(i0 + site) * 8 + k] : 0;
+  }
+
+  const int rb0 = blockIdx.y * a.rhs_block;
+  const int rb1 = min(rb0 + a.rhs_block, a.nrhs);
+  for (int r = rb0; r < rb1; ++r) {
+    if (a.halt != nullptr && a.halt[r] != 0) continue;  // uniform over the block
+    __syncthreads();
+    const double* mats_r = a.mats + (size_t)r * NMAT * 2 * Ls * Ls;
+    if constexpr (RT::AM == A_MAT) load_mat<R>(s_mA, mats_r + (size_t)a.matA * 2 * Ls * Ls, Ls, tid, nthr);
+    if constexpr (RT::BM) load_mat<R>(s_mB, mats_r + (size_t)a.matB * 2 * Ls * Ls, Ls, tid, nthr);
+    __syncthreads();
+
+    cx<R> acc[12];
+    if (live) {
+      hop_site<P, RT::DAG, RT::PRE>(a, fd, r, s, il, s_link, s_nbr, acc);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) acc[c] = {R(0), R(0)};
+    }
+
+    cx<R> v[12];
+    if constexpr (RT::AM == A_NEG) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) v[c] = R(-1) * acc[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) v[c] = acc[c];
+    }
+    if constexpr (RT::AM == A_MAT || RT::BM) {
+      cx<R> y[12];
+      if constexpr (RT::BM) {
+        if (live) ld_spinor<P>(a.y, fd, r, s, i, y);
+      }
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        if constexpr (RT::AM == A_MAT) {
+          if (half == 1) __syncthreads();
+          if (live)
+            for (int c = 0; c < 6; ++c) s_col[il * cstr + s * 6 + c] = acc[half * 6 + c];
+          __syncthreads();
+          if (live) col_matvec<R>(s_mA, s_col + il * cstr, Ls, s, half, v, false);
+        }
+        if constexpr (RT::BM) {
+          __syncthreads();
+          if (live)
+            for (int c = 0; c < 6; ++c) s_col[il * cstr + s * 6 + c] = y[half * 6 + c];
+          __syncthreads();
+          if (live) col_matvec<R>(s_mB, s_col + il * cstr, Ls, s, half, v, true);
+        }
+      }
+    }
+
+    double nrm = 0.0;
+    if (live) {
+      if constexpr (RT::OM == O_STORE) {
+        st_spinor<P>(a.out, fd, r, s, i, v);
+      } else if constexpr (RT::OM == O_ADDZ) {
+        cx<R> z[12];
+        ld_spinor<P>(a.z, fd, r, s, i, z);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) v[c] = z[c] - v[c];
+        st_spinor<P>(a.out, fd, r, s, i, v);
+      } else {
+        using RR = typename ST<PR>::R;
+        cx<RR> w[12];
+        if constexpr (RT::OM == O_RUPD) {
+          ld_spinor<PR>(a.r, fd, r, s, i, w);
+          const RR al = (RR)a.alpha[r];
+#pragma unroll
+          for (int c = 0; c < 12; ++c) {
+            w[c].r = fma(-al, (RR)v[c].r, w[c].r);
+            w[c].i = fma(-al, (RR)v[c].i, w[c].i);
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < 12; ++c) w[c] = {(RR)v[c].r, (RR)v[c].i};
+        }
+        st_spinor<PR>(a.r, fd, r, s, i, w);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) v[c] = {(R)w[c].r, (R)w[c].i};
+      }
+      if constexpr (RT::NRM) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) nrm += (double)v[c].r * v[c].r + (double)v[c].i * v[c].i;
+      }
+    }
+    if constexpr (RT::NRM) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
+      if ((tid & 63) == 0) s_red[tid >> 6] = nrm;
+      __syncthreads();
+      if (tid == 0) {
+        double t = 0.0;
+        for (int w = 0; w < (nthr + 63) / 64; ++w) t += s_red[w];
+        a.partial[(size_t)r * gridDim.x + blockIdx.x] = t;
+      }
+    }
+  }
+}
+
+template <int P>
+constexpr int acc_prec() {
+  return P == P64 ? P64 : P32;
+}
+
+template <int P, int ROLE>
+int launch_hop_t(const HopArgs& a, hipStream_t st, int* nblk_out) {
+  using R = typename ST<P>::R;
+  using RT = RoleT<ROLE>;
+  using L = HopLds<R>;
+  constexpr int SB = sites_per_block<P>();
+  const int Ls = a.Ls;
+  size_t lds = L::links(SB) + L::nbr(SB);
+  if (RT::AM == A_MAT) lds += L::mat(Ls);
+  if (RT::BM) lds += L::mat(Ls);
+  if (RT::AM == A_MAT || RT::BM) lds += L::col(SB, Ls);
+  const int threads = ((SB * Ls + 63) / 64) * 64;
+  const int nblk = (a.Vh + SB - 1) / SB;
+  const int rb = a.rhs_block > 0 ? a.rhs_block : 1;
+  dim3 grid(nblk, (a.nrhs + rb - 1) / rb);
+  HopArgs b = a;
+  b.rhs_block = rb;
+  auto fn = hop_kernel<P, acc_prec<P>(), SB, ROLE>;
+  if (lds > 65536) {
+    if (hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+        hipSuccess)
+      return EOFA_ERR_HIP;
+  }
+  hipLaunchKernelGGL(fn, grid, dim3(threads), lds, st, b);
+  if (nblk_out) *nblk_out = nblk;
+  return hipGetLastError() == hipSuccess ? EOFA_OK : EOFA_ERR_HIP;
+}
+
+template <int P>
+int launch_hop_p(int role, const HopArgs& a, hipStream_t st, int* nb) {
+  switch (role) {
+    case ROLE_DSLASH: return launch_hop_t<P, ROLE_DSLASH>(a, st, nb);
+    case ROLE_DSLASH_DAG: return launch_hop_t<P, ROLE_DSLASH_DAG>(a, st, nb);
+    case ROLE_K1: return launch_hop_t<P, ROLE_K1>(a, st, nb);
+    case ROLE_K2: return launch_hop_t<P, ROLE_K2>(a, st, nb);
+    case ROLE_K3: return launch_hop_t<P, ROLE_K3>(a, st, nb);
+    case ROLE_K4: return launch_hop_t<P, ROLE_K4>(a, st, nb);
+    case ROLE_K4S: return launch_hop_t<P, ROLE_K4S>(a, st, nb);
+    case ROLE_SRC: return launch_hop_t<P, ROLE_SRC>(a, st, nb);
+    case ROLE_RES: return launch_hop_t<P, ROLE_RES>(a, st, nb);
+    case ROLE_FULLRES: return launch_hop_t<P, ROLE_FULLRES>(a, st, nb);
+  }
+  return EOFA_ERR_INVALID;
+}
+
+int launch_hop(int prec, int role, const HopArgs& a, hipStream_t st, int* nblk_out) {
+  switch (prec) {
+    case P64: return launch_hop_p<P64>(role, a, st, nblk_out);
+    case P32: return launch_hop_p<P32>(role, a, st, nblk_out);
+    case P16: return launch_hop_p<P16>(role, a, st, nblk_out);
+  }
+  return EOFA_ERR_INVALID;
+}
+
+int hop_blocks(int prec, int Vh) {
+  const int SB = prec == P64 ? sites_per_block<P64>() : sites_per_block<P32>();
+  return (Vh + SB - 1) / SB;
+}
+
+// ---------------------------------------------------------------------------
+// geometry helpers
+
+struct GeoD {
+  int L[4];
+  int Ls, Vh;
+};
+
+__device__ __forceinline__ void site_coords(const GeoD& g, int parity, int i, int x[4]) {
+  const int hx = g.L[0] / 2;
+  int rest = i / hx;
+  const int xh = i - rest * hx;
+  x[1] = rest % g.L[1];
+  rest /= g.L[1];
+  x[2] = rest % g.L[2];
+  x[3] = rest / g.L[2];
+  x[0] = 2 * xh + ((x[1] + x[2] + x[3] + parity) & 1);
+}
+
+__device__ __forceinline__ size_t lex(const GeoD& g, const int x[4]) {
+  return (((size_t)x[3] * g.L[2] + x[2]) * g.L[1] + x[1]) * g.L[0] + x[0];
+}
+
+static GeoD geo_d(const Geometry& g) {
+  GeoD d;
+  for (int k = 0; k < 4; ++k) d.L[k] = g.L[k];
+  d.Ls = g.Ls;
+  d.Vh = g.Vh;
+  return d;
+}
+
+// ---------------------------------------------------------------------------
+// gauge packing: per output parity p and site i, 8 links
+//   dir mu   : U_mu(x) * (bc_mu if x_mu = L_mu - 1)
+//   dir 4+mu : U_mu(x - mu)^dag * (bc_mu if x_mu = 0)
+// and the checkerboard index of the neighbour x +- mu (parity 1-p).
+
+__global__ void gauge_pack_kernel(GeoD g, const double2* __restrict__ U, int bc0, int bc1, int bc2, int bc3,
+                                  double2* l64p0, double2* l64p1, float2* l32p0, float2* l32p1,
+                                  unsigned int* l16p0, unsigned int* l16p1, int* nbr0, int* nbr1) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (i >= g.Vh) return;
+  const int bc[4] = {bc0, bc1, bc2, bc3};
+  int x[4];
+  site_coords(g, p, i, x);
+  const size_t V = (size_t)g.L[0] * g.L[1] * g.L[2] * g.L[3];
+  double2* l64 = p ? l64p1 : l64p0;
+  float2* l32 = p ? l32p1 : l32p0;
+  unsigned int* l16 = p ? l16p1 : l16p0;
+  int* nbr = p ? nbr1 : nbr0;
+  for (int dir = 0; dir < 8; ++dir) {
+    const int mu = dir & 3;
+    const bool fwd = dir < 4;
+    int y[4] = {x[0], x[1], x[2], x[3]};
+    double sign = 1.0;
+    if (fwd) {
+      if (x[mu] == g.L[mu] - 1) sign = bc[mu];
+      y[mu] = (x[mu] + 1) % g.L[mu];
+    } else {
+      if (x[mu] == 0) sign = bc[mu];
+      y[mu] = (x[mu] - 1 + g.L[mu]) % g.L[mu];
+    }
+    nbr[(size_t)i * 8 + dir] = (int)(lex(g, y) / 2);
+    const size_t site = fwd ? lex(g, x) : lex(g, y);
+    const double2* u = U + ((size_t)mu * V + site) * 9;
+    for (int a3 = 0; a3 < 3; ++a3)
+      for (int b = 0; b < 3; ++b) {
+        double2 v = fwd ? u[a3 * 3 + b] : make_double2(u[b * 3 + a3].x, -u[b * 3 + a3].y);
+        v.x *= sign;
+        v.y *= sign;
+        const size_t j = ((size_t)i * 8 + dir) * 9 + a3 * 3 + b;
+        l64[j] = v;
+        l32[j] = make_float2((float)v.x, (float)v.y);
+        h2_t h;
+        h.x = (_Float16)v.x;
+        h.y = (_Float16)v.y;
+        l16[j] = __builtin_bit_cast(unsigned int, h);
+      }
+  }
+}
+
+void launch_gauge_pack(const Geometry& g, const void* gauge, const int bc[4], void* l64[2], void* l32[2],
+                       void* l16[2], int* nbr[2], hipStream_t st) {
+  const GeoD d = geo_d(g);
+  dim3 grid((g.Vh + 127) / 128, 2);
+  hipLaunchKernelGGL(gauge_pack_kernel, grid, dim3(128), 0, st, d, (const double2*)gauge, bc[0], bc[1], bc[2],
+                     bc[3], (double2*)l64[0], (double2*)l64[1], (float2*)l32[0], (float2*)l32[1],
+                     (unsigned int*)l16[0], (unsigned int*)l16[1], nbr[0], nbr[1]);
+}
+
+// ---------------------------------------------------------------------------
+// pack / unpack: canonical [rhs][Ls][T][Z][Y][X][4][3] complex128 <-> packed parity
+
+template <int P>
+__global__ void __launch_bounds__(256) pack_kernel(GeoD g, int parity, int nrhs, int g5r5, const double2* __restrict__ full, void* packed) {
+  using R = typename ST<P>::R;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (idx >= g.Ls * g.Vh) return;
+  const int s = idx / g.Vh, i = idx - s * g.Vh;
+  int x[4];
+  site_coords(g, parity, i, x);
+  const size_t V = (size_t)g.L[0] * g.L[1] * g.L[2] * g.L[3];
+  const int ssrc = g5r5 ? g.Ls - 1 - s : s;
+  const double2* src = full + (((size_t)r * g.Ls + ssrc) * V + lex(g, x)) * 12;
+  cx<R> v[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const double2 t = src[c];
+    const double sg = (g5r5 && c >= 6) ? -1.0 : 1.0;
+    v[c] = {(R)(sg * t.x), (R)(sg * t.y)};
+  }
+  const FD f = {g.Ls, g.Vh, nrhs};
+  st_spinor<P>(packed, f, r, s, i, v);
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) unpack_kernel(GeoD g, int parity, int nrhs, const void* packed, double2* full) {
+  using R = typename ST<P>::R;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (idx >= g.Ls * g.Vh) return;
+  const int s = idx / g.Vh, i = idx - s * g.Vh;
+  int x[4];
+  site_coords(g, parity, i, x);
+  const size_t V = (size_t)g.L[0] * g.L[1] * g.L[2] * g.L[3];
+  const FD f = {g.Ls, g.Vh, nrhs};
+  cx<R> v[12];
+  ld_spinor<P>(packed, f, r, s, i, v);
+  double2* dst = full + (((size_t)r * g.Ls + s) * V + lex(g, x)) * 12;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) dst[c] = make_double2((double)v[c].r, (double)v[c].i);
+}
+
+void launch_pack(int prec, const Geometry& g, const void* full, void* packed, int parity, int nrhs, int g5r5,
+                 hipStream_t st) {
+  const GeoD d = geo_d(g);
+  dim3 grid((g.Ls * g.Vh + 255) / 256, nrhs);
+  if (prec == P64)
+    hipLaunchKernelGGL(pack_kernel<P64>, grid, dim3(256), 0, st, d, parity, nrhs, g5r5, (const double2*)full, packed);
+  else if (prec == P32)
+    hipLaunchKernelGGL(pack_kernel<P32>, grid, dim3(256), 0, st, d, parity, nrhs, g5r5, (const double2*)full, packed);
+  else
+    hipLaunchKernelGGL(pack_kernel<P16>, grid, dim3(256), 0, st, d, parity, nrhs, g5r5, (const double2*)full, packed);
+}
+
+void launch_unpack(int prec, const Geometry& g, const void* packed, void* full, int parity, int nrhs,
+                   hipStream_t st) {
+  const GeoD d = geo_d(g);
+  dim3 grid((g.Ls * g.Vh + 255) / 256, nrhs);
+  if (prec == P64)
+    hipLaunchKernelGGL(unpack_kernel<P64>, grid, dim3(256), 0, st, d, parity, nrhs, packed, (double2*)full);
+  else if (prec == P32)
+    hipLaunchKernelGGL(unpack_kernel<P32>, grid, dim3(256), 0, st, d, parity, nrhs, packed, (double2*)full);
+  else
+    hipLaunchKernelGGL(unpack_kernel<P16>, grid, dim3(256), 0, st, d, parity, nrhs, packed, (double2*)full);
+}
+
+// ---------------------------------------------------------------------------
+// site-local fifth-dimension matrix: out(s) = sum_s' M[ch][s][s'] in(s')
+
+template <int P>
+__global__ void __launch_bounds__(256) smat_kernel(int Ls, int Vh, int nrhs, const void* in, void* out, const double* mats, int mat) {
+  using R = typename ST<P>::R;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (idx >= Ls * Vh) return;
+  const int s = idx / Vh, i = idx - s * Vh;
+  const FD f = {Ls, Vh, nrhs};
+  const double* M = mats + ((size_t)r * NMAT + mat) * 2 * Ls * Ls;
+  cx<R> v[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) v[c] = {R(0), R(0)};
+  for (int sp = 0; sp < Ls; ++sp) {
+    cx<R> t[12];
+    ld_spinor<P>(in, f, r, sp, i, t);
+    const R mp = (R)M[s * Ls + sp], mm = (R)M[Ls * Ls + s * Ls + sp];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c] = v[c] + mp * t[c];
+#pragma unroll
+    for (int c = 6; c < 12; ++c) v[c] = v[c] + mm * t[c];
+  }
+  st_spinor<P>(out, f, r, s, i, v);
+}
+
+void launch_smat(int prec, const Geometry& g, const void* in, void* out, const double* mats, int mat, int nrhs,
+                 hipStream_t st) {
+  dim3 grid((g.Ls * g.Vh + 255) / 256, nrhs);
+  if (prec == P64)
+    hipLaunchKernelGGL(smat_kernel<P64>, grid, dim3(256), 0, st, g.Ls, g.Vh, nrhs, in, out, mats, mat);
+  else if (prec == P32)
+    hipLaunchKernelGGL(smat_kernel<P32>, grid, dim3(256), 0, st, g.Ls, g.Vh, nrhs, in, out, mats, mat);
+  else
+    hipLaunchKernelGGL(smat_kernel<P16>, grid, dim3(256), 0, st, g.Ls, g.Vh, nrhs, in, out, mats, mat);
+}
+
+// ---------------------------------------------------------------------------
+// element-wise kernels over 5D sites
+
+template <int PI, int PO>
+__global__ void __launch_bounds__(256) convert_kernel(int Ls, int Vh, int nrhs, const void* in, void* out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (idx >= Ls * Vh) return;
+  const int s = idx / Vh, i = idx - s * Vh;
+  const FD f = {Ls, Vh, nrhs};
+  cx<double> v[12];
+  {
+    using RI = typename ST<PI>::R;
+    cx<RI> t[12];
+    ld_spinor<PI>(in, f, r, s, i, t);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) v[c] = {(double)t[c].r, (double)t[c].i};
+  }
+  using RO = typename ST<PO>::R;
+  cx<RO> o[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) o[c] = {(RO)v[c].r, (RO)v[c].i};
+  st_spinor<PO>(out, f, r, s, i, o);
+}
+
+template <int PI>
+__global__ void __launch_bounds__(256) axpy64_kernel(int Ls, int Vh, int nrhs, double* x, const void* e) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (idx >= Ls * Vh) return;
+  const int s = idx / Vh, i = idx - s * Vh;
+  const FD f = {Ls, Vh, nrhs};
+  using RI = typename ST<PI>::R;
+  cx<RI> t[12];
+  ld_spinor<PI>(e, f, r, s, i, t);
+  cx<double> v[12];
+  ld_spinor<P64>(x, f, r, s, i, v);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) v[c] = v[c] + cx<double>{(double)t[c].r, (double)t[c].i};
+  st_spinor<P64>(x, f, r, s, i, v);
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) zero_kernel(int Ls, int Vh, int nrhs, void* out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (idx >= Ls * Vh) return;
+  const int s = idx / Vh, i = idx - s * Vh;
+  const FD f = {Ls, Vh, nrhs};
+  using R = typename ST<P>::R;
+  cx<R> v[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) v[c] = {R(0), R(0)};
+  st_spinor<P>(out, f, r, s, i, v);
+}
+
+__device__ __forceinline__ void block_sum_store(double v, double* dst) {
+  __shared__ double red[16];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) t += red[w];
+    *dst = t;
+  }
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) norm2_kernel(int Ls, int Vh, int nrhs, const void* in, double* partial) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  double n = 0.0;
+  if (idx < Ls * Vh) {
+    const int s = idx / Vh, i = idx - s * Vh;
+    const FD f = {Ls, Vh, nrhs};
+    using R = typename ST<P>::R;
+    cx<R> v[12];
+    ld_spinor<P>(in, f, r, s, i, v);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) n += (double)v[c].r * v[c].r + (double)v[c].i * v[c].i;
+  }
+  block_sum_store(n, partial + (size_t)r * gridDim.x + blockIdx.x);
+}
+
+// x += alpha p;  p = r + beta p   (CG, after the residual update)
+template <int PS, int PR>
+__global__ void __launch_bounds__(256) cg_update_kernel(int Ls, int Vh, int nrhs, void* x, const void* rr, void* p, const double* alpha,
+                                 const double* beta, const int* u2run) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (idx >= Ls * Vh || u2run[r] == 0) return;
+  const int s = idx / Vh, i = idx - s * Vh;
+  const FD f = {Ls, Vh, nrhs};
+  using RR = typename ST<PR>::R;
+  using RS = typename ST<PS>::R;
+  cx<RS> pv[12];
+  cx<RR> xv[12], rv[12];
+  ld_spinor<PS>(p, f, r, s, i, pv);
+  ld_spinor<PR>(x, f, r, s, i, xv);
+  ld_spinor<PR>(rr, f, r, s, i, rv);
+  const RR al = (RR)alpha[r], be = (RR)beta[r];
+  cx<RS> pn[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const cx<RR> pc = {(RR)pv[c].r, (RR)pv[c].i};
+    xv[c].r = fma(al, pc.r, xv[c].r);
+    xv[c].i = fma(al, pc.i, xv[c].i);
+    pn[c] = {(RS)fma(be, pc.r, rv[c].r), (RS)fma(be, pc.i, rv[c].i)};
+  }
+  st_spinor<PR>(x, f, r, s, i, xv);
+  st_spinor<PS>(p, f, r, s, i, pn);
+}
+
+#define EOFA_EW_GRID dim3((g.Ls * g.Vh + 255) / 256, nrhs), dim3(256), 0, st
+
+void launch_convert(int pin, int pout, const Geometry& g, const void* in, void* out, int nrhs, hipStream_t st) {
+#define CV(A, B)                                                                          \
+  if (pin == A && pout == B) {                                                            \
+    hipLaunchKernelGGL((convert_kernel<A, B>), EOFA_EW_GRID, g.Ls, g.Vh, nrhs, in, out); \
+    return;                                                                               \
+  }
+  CV(P64, P64) CV(P64, P32) CV(P64, P16) CV(P32, P64) CV(P32, P32) CV(P32, P16) CV(P16, P64) CV(P16, P32)
+  CV(P16, P16)
+#undef CV
+}
+
+void launch_axpy_to64(int pin, const Geometry& g, void* x64, const void* e, int nrhs, hipStream_t st) {
+  if (pin == P64)
+    hipLaunchKernelGGL(axpy64_kernel<P64>, EOFA_EW_GRID, g.Ls, g.Vh, nrhs, (double*)x64, e);
+  else if (pin == P32)
+    hipLaunchKernelGGL(axpy64_kernel<P32>, EOFA_EW_GRID, g.Ls, g.Vh, nrhs, (double*)x64, e);
+  else
+    hipLaunchKernelGGL(axpy64_kernel<P16>, EOFA_EW_GRID, g.Ls, g.Vh, nrhs, (double*)x64, e);
+}
+
+void launch_zero(int prec, const Geometry& g, void* f, int nrhs, hipStream_t st) {
+  if (prec == P64)
+    hipLaunchKernelGGL(zero_kernel<P64>, EOFA_EW_GRID, g.Ls, g.Vh, nrhs, f);
+  else if (prec == P32)
+    hipLaunchKernelGGL(zero_kernel<P32>, EOFA_EW_GRID, g.Ls, g.Vh, nrhs, f);
+  else
+    hipLaunchKernelGGL(zero_kernel<P16>, EOFA_EW_GRID, g.Ls, g.Vh, nrhs, f);
+}
+
+int launch_norm2(int prec, const Geometry& g, const void* f, int nrhs, double* partial, hipStream_t st) {
+  const int nblk = (g.Ls * g.Vh + 255) / 256;
+  if (prec == P64)
+    hipLaunchKernelGGL(norm2_kernel<P64>, EOFA_EW_GRID, g.Ls, g.Vh, nrhs, f, partial);
+  else if (prec == P32)
+    hipLaunchKernelGGL(norm2_kernel<P32>, EOFA_EW_GRID, g.Ls, g.Vh, nrhs, f, partial);
+  else
+    hipLaunchKernelGGL(norm2_kernel<P16>, EOFA_EW_GRID, g.Ls, g.Vh, nrhs, f, partial);
+  return nblk;
+}
+
+void launch_cg_update(int ps, int pr, const Geometry& g, void* x, const void* r, void* p, const double* alpha,
+                      const double* beta, const int* u2run, int nrhs, hipStream_t st) {
+  if (ps == P64)
+    hipLaunchKernelGGL((cg_update_kernel<P64, P64>), EOFA_EW_GRID, g.Ls, g.Vh, nrhs, x, r, p, alpha, beta, u2run);
+  else if (ps == P32)
+    hipLaunchKernelGGL((cg_update_kernel<P32, P32>), EOFA_EW_GRID, g.Ls, g.Vh, nrhs, x, r, p, alpha, beta, u2run);
+  else
+    hipLaunchKernelGGL((cg_update_kernel<P16, P32>), EOFA_EW_GRID, g.Ls, g.Vh, nrhs, x, r, p, alpha, beta, u2run);
+}
+#undef EOFA_EW_GRID
+
+// ---------------------------------------------------------------------------
+// CG scalar finalisation: one block per right-hand side, fixed summation order
+
+__global__ void finalize_kernel(int mode, const double* __restrict__ partial, int nblk, CgState S, double* out) {
+  const int r = blockIdx.x;
+  __shared__ double red[256];
+  double t = 0.0;
+  for (int j = threadIdx.x; j < nblk; j += blockDim.x) t += partial[(size_t)r * nblk + j];
+  red[threadIdx.x] = t;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double sum = red[0];
+  if (mode == FIN_NORM) {
+    out[r] = sum;
+    return;
+  }
+  if (mode == FIN_INIT) {
+    S.rr[r] = sum;
+    S.stop[r] = S.tol2[r] * sum;
+    S.iter[r] = 0;
+    S.u2run[r] = 0;
+    S.breakdown[r] = 0;
+    S.halt[r] = (sum == 0.0 || S.max_iter[r] <= 0) ? 1 : 0;
+    if (!isfinite(sum)) {
+      S.breakdown[r] = 1;
+      S.halt[r] = 1;
+    }
+    return;
+  }
+  if (mode == FIN_ALPHA) {
+    if (S.halt[r]) return;
+    S.ww[r] = sum;
+    if (!(sum > 0.0) || !isfinite(sum)) {
+      S.breakdown[r] = 1;
+      S.halt[r] = 1;
+      S.alpha[r] = 0.0;
+      return;
+    }
+    S.alpha[r] = S.rr[r] / sum;
+    return;
+  }
+  // FIN_BETA
+  if (S.halt[r]) {
+    S.u2run[r] = 0;
+    return;
+  }
+  const double rrn = sum;
+  S.beta[r] = rrn / S.rr[r];
+  S.rr[r] = rrn;
+  S.iter[r] += 1;
+  S.u2run[r] = 1;
+  if (!isfinite(rrn)) {
+    S.breakdown[r] = 1;
+    S.halt[r] = 1;
+    S.u2run[r] = 0;
+  } else if (rrn <= S.stop[r] || S.iter[r] >= S.max_iter[r]) {
+    S.halt[r] = 1;
+  }
+}
+
+void launch_finalize(int mode, const double* partial, int nblk, int nrhs, CgState s, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(nrhs), dim3(256), 0, st, mode, partial, nblk, s, out);
+}
+
+// ---------------------------------------------------------------------------
+// heatbath right-hand sides and combination (canonical layout)
+
+__global__ void omega_rhs_kernel(int Ls, size_t V, const double2* __restrict__ eta, double2* rhs,
+                                 const double* om, const int* chir) {
+  const size_t site = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y, r = blockIdx.z;
+  if (site >= V) return;
+  const double w = om[r * Ls + s];
+  const int ch = chir[r];
+  const double2* src = eta + site * 12;  // s = 0 slice
+  double2* dst = rhs + (((size_t)r * Ls + s) * V + site) * 12;
+  for (int c = 0; c < 12; ++c) {
+    const bool keep = (ch > 0) ? (c < 6) : (c >= 6);
+    const double2 v = src[c];
+    dst[c] = keep ? make_double2(w * v.x, w * v.y) : make_double2(0.0, 0.0);
+  }
+}
+
+__global__ void heatbath_combine_kernel(int Ls, size_t V, int nsys, const double2* __restrict__ eta,
+                                        const double2* __restrict__ sol, double2* phi, double a_eta,
+                                        const double* coef, const double* om, const int* chir) {
+  const size_t site = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (site >= V) return;
+  const double2* e = eta + ((size_t)s * V + site) * 12;
+  double2 acc[12];
+  for (int c = 0; c < 12; ++c) acc[c] = make_double2(a_eta * e[c].x, a_eta * e[c].y);
+  if (s == 0) {
+    for (int r = 0; r < nsys; ++r) {
+      const int ch = chir[r];
+      const double cf = coef[r];
+      for (int sp = 0; sp < Ls; ++sp) {
+        const double w = cf * om[r * Ls + sp];
+        const double2* y = sol + (((size_t)r * Ls + sp) * V + site) * 12;
+        for (int c = 0; c < 12; ++c) {
+          const bool keep = (ch > 0) ? (c < 6) : (c >= 6);
+          if (keep) {
+            acc[c].x += w * y[c].x;
+            acc[c].y += w * y[c].y;
+          }
+        }
+      }
+    }
+  }
+  double2* o = phi + ((size_t)s * V + site) * 12;
+  for (int c = 0; c < 12; ++c) o[c] = acc[c];
+}
+
+void launch_omega_rhs(const Geometry& g, const void* eta, void* rhs, const double* om, const int* chir, int nsys,
+                      hipStream_t st) {
+  dim3 grid((g.V + 127) / 128, g.Ls, nsys);
+  hipLaunchKernelGGL(omega_rhs_kernel, grid, dim3(128), 0, st, g.Ls, (size_t)g.V, (const double2*)eta,
+                     (double2*)rhs, om, chir);
+}
+
+void launch_heatbath_combine(const Geometry& g, const void* eta, const void* sol, void* phi, double a_eta,
+                             const double* coef, const double* om, const int* chir, int nsys, hipStream_t st) {
+  dim3 grid((g.V + 127) / 128, g.Ls);
+  hipLaunchKernelGGL(heatbath_combine_kernel, grid, dim3(128), 0, st, g.Ls, (size_t)g.V, nsys,
+                     (const double2*)eta, (const double2*)sol, (double2*)phi, a_eta, coef, om, chir);
+}
+
+size_t packed_bytes(int prec, const Geometry& g, int nrhs) {
+  const size_t n = (size_t)nrhs * 6 * g.Ls * g.Vh;
+  if (prec == P64) return n * 32;
+  if (prec == P32) return n * 16;
+  return n * 8 + (size_t)nrhs * g.Ls * g.Vh * 4;
+}
+
+size_t link_bytes(int prec, const Geometry& g) {
+  const size_t n = (size_t)g.Vh * 72;
+  return n * (prec == P64 ? 16 : prec == P32 ? 8 : 4);
+}
+
+}  // namespace eofa

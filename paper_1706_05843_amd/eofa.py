@@ -1,0 +1,231 @@
+"""ctypes binding of libeofa.so (include/eofa.h).
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+Fields are torch tensors on the GPU (complex128 canonical layout, or uint8
+buffers holding packed half-fields); their data pointers and torch's current
+HIP stream are handed to the C entry points of the same names.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libeofa.so")
+
+EOFA_OK = 0
+EOFA_ERR_INVALID = -1
+EOFA_ERR_NOT_CONVERGED = -2
+EOFA_ERR_BREAKDOWN = -3
+EOFA_ERR_HIP = -4
+EOFA_ERR_OOM = -5
+
+FP64, FP32, FP16S = 0, 1, 2
+
+MAT_NAMES = ["mee", "mee_inv", "mee_t", "mee_inv_t", "mee_inv_t_dt_t", "neg_dt_t", "dt_t", "dt"]
+
+
+class Action(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32 * 4), ("Ls", ctypes.c_int32), ("M5", ctypes.c_double),
+                ("b5", ctypes.c_double), ("c5", ctypes.c_double), ("bc", ctypes.c_int32 * 4)]
+
+
+class System(ctypes.Structure):
+    _fields_ = [("m_op", ctypes.c_double), ("m_a", ctypes.c_double), ("m_b", ctypes.c_double),
+                ("beta", ctypes.c_double), ("chi", ctypes.c_int32)]
+
+
+class SolverParams(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("max_outer", ctypes.c_int32),
+                ("inner_prec", ctypes.c_int32), ("inner_tol", ctypes.c_double),
+                ("fixed_iters", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("profile", ctypes.c_int32)]
+
+
+class SolverStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("outer_iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("true_resid", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("hop_ms", ctypes.c_double * 4), ("hop_timed", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+    def as_dict(self):
+        return dict(iters=self.iters, outer_iters=self.outer_iters, converged=self.converged,
+                    status=self.status, true_resid=self.true_resid, seconds=self.seconds,
+                    hop_ms=list(self.hop_ms), hop_timed=self.hop_timed)
+
+
+_LIB = None
+_P = ctypes.c_void_p
+_I = ctypes.c_int32
+
+
+def lib():
+    """Load libeofa.so; raises if it is missing (there is no fallback)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1706_05843_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "eofa_create": ([ctypes.POINTER(Action), _P, _P, ctypes.POINTER(_P)], _I),
+        "eofa_destroy": ([_P], _I),
+        "eofa_last_error": ([], ctypes.c_char_p),
+        "eofa_packed_bytes": ([_P, _I, _I], ctypes.c_size_t),
+        "eofa_pack": ([_P, _P, _P, _I, _I, _I, _I, _P], _I),
+        "eofa_unpack": ([_P, _P, _P, _I, _I, _I, _P], _I),
+        "eofa_dslash": ([_P, ctypes.POINTER(System), _P, _P, _I, _I, _I, _I, _P], _I),
+        "eofa_mooee": ([_P, ctypes.POINTER(System), _P, _P, _I, _I, _I, _P], _I),
+        "eofa_mooee_inv": ([_P, ctypes.POINTER(System), _P, _P, _I, _I, _I, _P], _I),
+        "eofa_cg_solve": ([_P, ctypes.POINTER(System), _P, _P, _I, ctypes.POINTER(SolverParams),
+                           ctypes.POINTER(SolverStats), _P], _I),
+        "eofa_heatbath_solve": ([_P, ctypes.c_double, ctypes.c_double, _I, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_double), _P, _P, ctypes.POINTER(SolverParams),
+                                 ctypes.POINTER(SolverStats), _P], _I),
+        "eofa_fifth_matrix": ([ctypes.POINTER(Action), ctypes.POINTER(System), _I,
+                               ctypes.POINTER(ctypes.c_double)], _I),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _LIB = L
+    return L
+
+
+class EofaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"eofa error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != EOFA_OK:
+        raise EofaError(rc, lib().eofa_last_error().decode())
+    return rc
+
+
+def make_action(dims, Ls, M5, b5, c5, bc=(1, 1, 1, -1)):
+    a = Action()
+    for k in range(4):
+        a.dims[k] = int(dims[k])
+        a.bc[k] = int(bc[k])
+    a.Ls, a.M5, a.b5, a.c5 = int(Ls), float(M5), float(b5), float(c5)
+    return a
+
+
+def make_systems(systems):
+    """systems: list of (m_op, m_a, m_b, beta, chi) tuples or objects with those attributes."""
+    arr = (System * len(systems))()
+    for k, s in enumerate(systems):
+        if isinstance(s, tuple):
+            m_op, m_a, m_b, beta, chi = s
+        else:
+            m_op, m_a, m_b, beta, chi = s.m_op, s.m_a, s.m_b, s.beta, s.chi
+        arr[k].m_op, arr[k].m_a, arr[k].m_b, arr[k].beta, arr[k].chi = m_op, m_a, m_b, beta, int(chi)
+    return arr
+
+
+def make_params(tol=1e-10, max_iter=100000, max_outer=20, inner_prec=FP64, inner_tol=0.0,
+                fixed_iters=0, check_every=16, profile=0):
+    p = SolverParams()
+    p.tol, p.max_iter, p.max_outer, p.inner_prec = tol, max_iter, max_outer, inner_prec
+    p.inner_tol, p.fixed_iters, p.check_every, p.profile = inner_tol, fixed_iters, check_every, profile
+    return p
+
+
+def eofa_fifth_matrix(action, system, mat):
+    """Host-only: the [2][Ls][Ls] fifth-dimension matrix ``mat`` (name or index) the library builds."""
+    if isinstance(mat, str):
+        mat = MAT_NAMES.index(mat)
+    Ls = action.Ls
+    out = (ctypes.c_double * (2 * Ls * Ls))()
+    _check(lib().eofa_fifth_matrix(ctypes.byref(action), make_systems([system]), mat, out))
+    return np.frombuffer(out, dtype=np.float64).reshape(2, Ls, Ls).copy()
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(stream)
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """An eofa_ctx: the action and the packed gauge field on the current GPU."""
+
+    def __init__(self, action, gauge, stream=None):
+        import torch
+        assert gauge.is_cuda and gauge.dtype == torch.complex128 and gauge.is_contiguous()
+        self.action = action
+        self.dims = tuple(action.dims)
+        self.Ls = action.Ls
+        self._h = ctypes.c_void_p()
+        _check(lib().eofa_create(ctypes.byref(action), ctypes.c_void_p(gauge.data_ptr()), _stream(stream),
+                                 ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            lib().eofa_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- buffers -----------------------------------------------------------
+    def packed_bytes(self, prec, nrhs=1):
+        return int(lib().eofa_packed_bytes(self._h, prec, nrhs))
+
+    def new_packed(self, prec, nrhs=1):
+        import torch
+        return torch.empty(self.packed_bytes(prec, nrhs), dtype=torch.uint8, device="cuda")
+
+    def full_shape(self, nrhs=1):
+        lx, ly, lz, lt = self.dims
+        return (nrhs, self.Ls, lt, lz, ly, lx, 4, 3)
+
+    # --- entry points ------------------------------------------------------
+    def eofa_pack(self, full, packed, parity, prec, nrhs=1, g5r5=0, stream=None):
+        _check(lib().eofa_pack(self._h, _p(full), _p(packed), parity, prec, nrhs, g5r5, _stream(stream)))
+
+    def eofa_unpack(self, packed, full, parity, prec, nrhs=1, stream=None):
+        _check(lib().eofa_unpack(self._h, _p(packed), _p(full), parity, prec, nrhs, _stream(stream)))
+
+    def eofa_dslash(self, systems, inp, out, out_parity, dagger=0, prec=FP64, nrhs=1, stream=None):
+        _check(lib().eofa_dslash(self._h, make_systems(systems), _p(inp), _p(out), out_parity, dagger, prec,
+                                 nrhs, _stream(stream)))
+
+    def eofa_mooee(self, systems, inp, out, dagger=0, prec=FP64, nrhs=1, stream=None):
+        _check(lib().eofa_mooee(self._h, make_systems(systems), _p(inp), _p(out), dagger, prec, nrhs,
+                                _stream(stream)))
+
+    def eofa_mooee_inv(self, systems, inp, out, dagger=0, prec=FP64, nrhs=1, stream=None):
+        _check(lib().eofa_mooee_inv(self._h, make_systems(systems), _p(inp), _p(out), dagger, prec, nrhs,
+                                    _stream(stream)))
+
+    def eofa_cg_solve(self, systems, phi, psi, params, stream=None, raise_on=("invalid", "hip", "oom")):
+        n = len(systems)
+        stats = (SolverStats * n)()
+        rc = lib().eofa_cg_solve(self._h, make_systems(systems), _p(phi), _p(psi), n, ctypes.byref(params),
+                                 stats, _stream(stream))
+        if rc in (EOFA_ERR_INVALID, EOFA_ERR_HIP, EOFA_ERR_OOM):
+            _check(rc)
+        return rc, [s.as_dict() for s in stats]
+
+    def eofa_heatbath_solve(self, m1, m2, alpha, beta, eta, phi, params, stream=None):
+        npol = len(beta)
+        assert len(alpha) == npol + 1
+        a = (ctypes.c_double * (npol + 1))(*alpha)
+        b = (ctypes.c_double * npol)(*beta)
+        stats = (SolverStats * (2 * npol))()
+        rc = lib().eofa_heatbath_solve(self._h, m1, m2, npol, a, b, _p(eta), _p(phi), ctypes.byref(params),
+                                       stats, _stream(stream))
+        if rc in (EOFA_ERR_INVALID, EOFA_ERR_HIP, EOFA_ERR_OOM):
+            _check(rc)
+        return rc, [s.as_dict() for s in stats]
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr())
