@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""EOFA solve benchmark on one MI355X.
+
+Workload (default): 16^3 x 32 lattice, Ls = 16, Mobius b5 = 1.5, c5 = 0.5,
+M5 = 1.8, antiperiodic time; links exp(i 0.5 H) (seeded), one Gaussian
+source; the shifted EOFA system of the action and force,
+(H(m2) - Delta_+(m1, m2) P_+) psi = phi with m1 = 0.04, m2 = 1.0, solved to
+an FP64 true residual of 1e-10 with FP16-storage / FP32-arithmetic inner CG
+and an FP64 defect-correction outer loop. A step is one complete solve
+(pack, Schur source, outer/inner CG, reconstruction, FP64 true residual,
+unpack), inputs resident in HBM.
+
+Output: one JSON line. ``value`` is the whole-job Dslash throughput: the
+algorithmic bytes of every inner-solve hop kernel divided by the wall time of
+the timed steps. ``roofline`` is the dominant hop kernel alone (HIP events on
+the solve's stream, every 8th iteration). ``cpu_baseline`` times the CPU
+oracle's off-parity operator on the same lattice.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Dslash HBM GB/s (% peak); EOFA CG time-to-1e-10 residual, mixed/learned vs plain FP64"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: dims (Lx, Ly, Lz, Lt), Ls, eps, m1, gauge seed, source seed
+    "c1": ((4, 4, 4, 4), 8, 0.3, 0.04, 1000, 2000),
+    "c2": ((16, 16, 16, 32), 16, 0.5, 0.04, 1001, 2001),
+}
+ROLE_NAMES = ["K1 Mee^-1.Dhop.D~", "K2 Mee.p - Dhop.D~", "K3 Mee^-T.D~^T.Dhop^dag", "K4 r -= a(Mee^T.w - D~^T.Dhop^dag)"]
+PREC = {"fp64": 0, "fp32": 1, "fp16s": 2}
+
+
+def site_bytes(prec):
+    """bytes of one 5D site-spinor in a packed field (FP16S: values + scale)."""
+    return {0: 192, 1: 96, 2: 52}[prec]
+
+
+def link_bytes_per_site(prec):
+    """8 links x 9 complex per 4D site, in the storage precision."""
+    return 72 * {0: 16, 1: 8, 2: 4}[prec]
+
+
+def role_bytes(role, prec, Ls, Nh):
+    """Algorithmic (compulsory) bytes of one launch of an inner hop kernel:
+    every input field read once, every output written once, every link once."""
+    E = site_bytes(prec)
+    ER = 192 if prec == 0 else 96  # residual kept in the accumulator precision
+    lk = link_bytes_per_site(prec) / Ls
+    per = {0: 2 * E, 1: 3 * E, 2: 2 * E, 3: 2 * E + 2 * ER}[role] + lk
+    return per * Nh
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_1706_05843_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(workload, prec_name, role):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}_{prec_name}.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch", {}).get(str(role))
+
+
+def cpu_baseline(dims, Ls, eps, m1, gseed, sseed):
+    """The oracle's off-parity operator Dhop D~(m) (FP64, numpy) on the same lattice."""
+    import numpy as np
+    from oracle.dwf import Action, Dtilde_op
+    from oracle.lattice import hop, restrict
+    from paper_1706_05843_amd import synth
+    act = Action(dims, Ls, 1.8, 1.5, 0.5, (1, 1, 1, -1))
+    U = synth.gauge_field(dims, eps, gseed)
+    psi = synth.fermion(dims, Ls, sseed)
+    x = restrict(psi, dims, 1)
+    t0 = time.perf_counter()
+    y = restrict(hop(U, Dtilde_op(act, 1.0, x), act.bc), dims, 0)
+    dt = time.perf_counter() - t0
+    del y
+    Vh = int(np.prod(dims)) // 2
+    byts = (2 * 192 + link_bytes_per_site(0) / Ls) * Vh * Ls
+    return dict(value=byts / dt / 1e9, unit="GB/s", cores=1, kind="oracle",
+                sample=f"one application of the oracle's FP64 off-parity operator Dhop.D~ on the full "
+                       f"{dims[0]}x{dims[1]}x{dims[2]}x{dims[3]} x Ls={Ls} lattice ({dt:.2f} s, numpy, one thread); "
+                       f"bytes counted with the same compulsory-traffic model as the GPU kernel")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--inner", default="fp16s", choices=sorted(PREC))
+    ap.add_argument("--inner-tol", type=float, default=0.0)
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 reference solve")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on a single GPU; --gpus must be 1 (no multi-GPU path here)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1706_05843_amd import eofa, synth
+
+    dims, Ls, eps, m1, gseed, sseed = WORKLOADS[args.workload]
+    m2 = 1.0
+    print(f"bench: workload {args.workload} dims={dims} Ls={Ls} eps={eps}", file=sys.stderr, flush=True)
+    U = torch.from_numpy(synth.gauge_field(dims, eps, gseed)).cuda()
+    phi = torch.from_numpy(synth.fermion(dims, Ls, sseed, nrhs=1)).cuda()
+    psi = torch.zeros_like(phi)
+    ctx = eofa.Context(eofa.make_action(dims, Ls, 1.8, 1.5, 0.5), U)
+    system = [(m2, m1, m2, -1.0, +1)]  # H(m2) - Delta_+(m1, m2) P_+
+    prec = PREC[args.inner]
+    Vh = int(np.prod(dims)) // 2
+    Nh = Vh * Ls
+
+    def solve(p, profile=0):
+        prm = eofa.make_params(tol=1e-10, inner_prec=p, inner_tol=args.inner_tol, profile=profile)
+        rc, st = ctx.eofa_cg_solve(system, phi, psi, prm)
+        if rc != eofa.EOFA_OK:
+            raise RuntimeError(f"solve failed rc={rc} stats={st}")
+        return st[0]
+
+    plain = None
+    if not args.no_plain:
+        solve(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = solve(0)
+        torch.cuda.synchronize()
+        plain = dict(seconds=time.perf_counter() - t0, iters=st["iters"], true_resid=st["true_resid"])
+        print(f"bench: plain FP64 solve {plain}", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        solve(prec, profile=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [solve(prec, profile=1) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = dt * 1e3 / args.steps
+    print(f"bench: {args.steps} steps {ms:.2f} ms/step", file=sys.stderr, flush=True)
+
+    # whole-job Dslash throughput: every inner hop launch's algorithmic bytes / wall time
+    iters = sum(s["iters"] for s in stats)
+    outer = sum(s["outer_iters"] for s in stats)
+    per_iter = sum(role_bytes(k, prec, Ls, Nh) for k in range(4))
+    init_bytes = role_bytes(2, prec, Ls, Nh) + role_bytes(3, prec, Ls, Nh)  # M^dag r at each outer pass
+    total_bytes = iters * per_iter + outer * init_bytes
+    value = total_bytes / dt / 1e9
+
+    # dominant kernel: the hop role with the largest timed share
+    hop_ms = np.sum([s["hop_ms"] for s in stats], axis=0)
+    timed = sum(s["hop_timed"] for s in stats)
+    dom = int(np.argmax(hop_ms))
+    avg_ms = hop_ms[dom] / max(timed, 1)
+    dom_bytes = role_bytes(dom, prec, Ls, Nh)
+    achieved = dom_bytes / (avg_ms * 1e-3) / 1e9
+    traffic = traffic_from_profile(args.workload, args.inner, dom)
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                kernel=ROLE_NAMES[dom], avg_launch_us=round(avg_ms * 1e3, 2),
+                algorithmic_bytes_per_launch=int(dom_bytes),
+                all_roles_avg_us=[round(h / max(timed, 1) * 1e3, 2) for h in hop_ms],
+                all_roles_gbs=[round(role_bytes(k, prec, Ls, Nh) / (hop_ms[k] / max(timed, 1) * 1e-3) / 1e9, 1)
+                               for k in range(4)])
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if prec else "f64", "data": "synthetic",
+        "precision": {"fp16s": "inner CG: FP16 storage + per-site FP32 scale, FP32 arithmetic; FP64 outer defect correction",
+                      "fp32": "inner CG FP32; FP64 outer defect correction",
+                      "fp64": "FP64 throughout"}[args.inner],
+        "config": {"workload": f"{dims[0]}x{dims[1]}x{dims[2]}x{dims[3]} Ls={Ls} Mobius b5=1.5 c5=0.5 M5=1.8, "
+                               f"links exp(i {eps} H), system H(m2)-Delta_+(m1,m2)P_+ m1={m1} m2={m2}, "
+                               f"1 Gaussian RHS, true residual 1e-10",
+                   "lattice": list(dims), "Ls": Ls, "nrhs": 1, "inner": args.inner},
+        "time_to_solution_s": round(ms / 1e3, 5),
+        "iters": stats[-1]["iters"], "outer_iters": stats[-1]["outer_iters"],
+        "true_resid": stats[-1]["true_resid"],
+        "roofline": roof,
+    }
+    if plain is not None:
+        out["plain_fp64"] = dict(time_to_solution_s=round(plain["seconds"], 5), iters=plain["iters"],
+                                 true_resid=plain["true_resid"])
+        out["speedup_vs_plain_fp64"] = round(plain["seconds"] / (ms / 1e3), 3)
+    if not args.no_cpu:
+        print("bench: timing the CPU oracle baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(dims, Ls, eps, m1, gseed, sseed)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

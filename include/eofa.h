@@ -34,12 +34,12 @@
  *   i = (((t*Lz + z)*Ly + y)*Lx + x) / 2,  Vh = Lx*Ly*Lz*Lt / 2,
  * components c = spin*3 + colour grouped in pairs q = c/2 (q = 0..2 is the
  * P_+ half, q = 3..5 the P_- half); element (rhs, q, s, i) at
- *   ((rhs*6 + q)*Ls + s)*Vh + i
+ *   ((rhs*6 + q)*Vh + i)*Ls + s          (s fastest: one site's column is contiguous)
  * with element = two complex numbers:
  *   EOFA_FP64  : 2 x (double re, double im)      32 bytes
  *   EOFA_FP32  : 2 x (float re, float im)        16 bytes
  *   EOFA_FP16S : 2 x (half re, half im)           8 bytes, plus one float
- *                scale per 5D site at ((rhs*Ls + s)*Vh + i) stored after
+ *                scale per 5D site at (rhs*Vh + i)*Ls + s stored after
  *                the values; the site's 24 reals are value * scale with
  *                scale = max |re|, |im| of the site.
  * eofa_packed_bytes() gives the size of one packed half-field block.
@@ -107,8 +107,9 @@ typedef struct {
   int32_t max_iter;    /* total inner CG iterations allowed (all outer passes)                 */
   int32_t max_outer;   /* FP64 defect-correction passes (Sec. VI A); >= 1                      */
   int32_t inner_prec;  /* eofa_prec of the inner CG (FP64: plain solve)                        */
-  double inner_tol;    /* inner CG stop |r_k| <= inner_tol |r_0| on the normal equations;
-                          0 = automatic (0.3*tol for FP64 inner, 1e-4 otherwise)               */
+  double inner_tol;    /* floor of the inner CG stop |r_k| <= t |r_0| on the normal equations;
+                          each pass uses t = max(inner_tol, 0.3 tol |phi| / |outer residual|);
+                          0 = automatic floor (0 for FP64 inner, 1e-4 otherwise)               */
   int32_t fixed_iters; /* > 0: exactly this many inner iterations in one pass, no early stop   */
   int32_t check_every; /* host convergence poll period in iterations (0 = 16)                 */
   int32_t profile;     /* 1: time the inner hop kernels with HIP events (stats.hop_ms)        */

@@ -425,8 +425,10 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
   const bool fixed = prm->fixed_iters > 0;
   const int max_outer = fixed ? 1 : std::max(1, prm->max_outer);
   const int check = prm->check_every > 0 ? prm->check_every : 16;
-  double inner_tol = prm->inner_tol;
-  if (!(inner_tol > 0.0)) inner_tol = S == P64 ? 0.3 * prm->tol : 1e-4;
+  // Each inner pass aims only at the reduction still missing (0.3 safety
+  // factor on the FP64 target), floored at the inner precision's reach.
+  double inner_floor = prm->inner_tol;
+  if (!(inner_floor > 0.0)) inner_floor = S == P64 ? 0.0 : 1e-4;
 
   CHK(upload_systems(C, sys, nrhs, st));
   CHK(stage(C, 64 * (size_t)std::max(nrhs, 16)));
@@ -445,7 +447,7 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
   CHK(ws(C, "wS", bS, &wS));
   CHK(ws(C, "rin", bR, &rin));
   CHK(ws(C, "xin", bR, &xin));
-  const int maxblk = std::max(hop_blocks(P64, g.Vh), std::max(hop_blocks(P32, g.Vh), (g.Ls * g.Vh + 255) / 256));
+  const int maxblk = std::max(hop_blocks(P64, g.Vh, g.Ls), std::max(hop_blocks(P32, g.Vh, g.Ls), (g.Ls * g.Vh + 255) / 256));
   CHK(ws(C, "partial", sizeof(double) * (size_t)maxblk * nrhs, &partial_v));
   double* partial = (double*)partial_v;
   CgState Sst;
@@ -458,7 +460,14 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
   std::vector<double> ne, no, bb(nrhs);
   CHK(norms(C, P64, be, nrhs, partial, Sst, ne, st));
   CHK(norms(C, P64, bo, nrhs, partial, Sst, no, st));
-  for (int r = 0; r < nrhs; ++r) bb[r] = ne[r] + no[r];
+  std::vector<int> done(nrhs, 0), iters(nrhs, 0), outers(nrhs, 0), status(nrhs, EOFA_OK);
+  for (int r = 0; r < nrhs; ++r) {
+    bb[r] = ne[r] + no[r];
+    if (!std::isfinite(bb[r])) {  // NaN / Inf in phi: nothing to iterate on
+      status[r] = EOFA_ERR_BREAKDOWN;
+      done[r] = 1;
+    }
+  }
 
   // Schur source b~_o = b_o - Dhop D~ M_ee^-1 b_e
   launch_smat(P64, g, be, te, C->mats, MAT_MEE_INV, nrhs, st);
@@ -471,15 +480,14 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
   }
   launch_zero(P64, g, x, nrhs, st);
 
-  std::vector<int> done(nrhs, 0), iters(nrhs, 0), outers(nrhs, 0), status(nrhs, EOFA_OK);
   std::vector<double> rro;
   std::vector<int> hbuf(4 * nrhs);
   std::vector<double> hd(2 * nrhs);
   double hop_ms[4] = {0, 0, 0, 0};
   int timed = 0;
-  const int max_timed = 4096;
+  const int max_timed = 256;  // timed iterations per solve (every 8th iteration)
   if (prm->profile && C->events.empty()) {
-    C->events.resize(8 * 64);
+    C->events.resize(8 * max_timed);
     for (auto& ev : C->events) HIPCHK(hipEventCreate(&ev));
   }
 
@@ -510,7 +518,12 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
     bool all = true;
     for (int r = 0; r < nrhs; ++r) {
       if (done[r]) continue;
-      const double res = bb[r] > 0 ? std::sqrt(rro[r] / bb[r]) : 0.0;
+      const double res = bb[r] > 0 ? std::sqrt(rro[r] / bb[r]) : (rro[r] == 0.0 ? 0.0 : INFINITY);
+      if (!std::isfinite(res)) {
+        status[r] = EOFA_ERR_BREAKDOWN;
+        done[r] = 1;
+        continue;
+      }
       if (!fixed && res <= prm->tol) done[r] = 1;
       if (!fixed && iters[r] >= prm->max_iter) done[r] = 1;
       if (!done[r]) all = false;
@@ -523,7 +536,12 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
     std::vector<double> t2(nrhs);
     for (int r = 0; r < nrhs; ++r) {
       mi[r] = done[r] ? 0 : (fixed ? prm->fixed_iters : std::max(0, prm->max_iter - iters[r]));
-      t2[r] = fixed ? 0.0 : inner_tol * inner_tol;
+      double it_r = 0.0;
+      if (!fixed && !done[r]) {
+        const double need = 0.3 * prm->tol * std::sqrt(bb[r] / std::max(rro[r], 1e-300));
+        it_r = std::min(0.5, std::max(inner_floor, need));
+      }
+      t2[r] = it_r * it_r;
       if (!done[r]) outers[r] += 1;
     }
     CHK(put(C, Sst.max_iter, mi.data(), nrhs * sizeof(int), st));
@@ -575,13 +593,13 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
     k4.alpha = Sst.alpha;
     k4.partial = partial;
     k4.halt = Sst.halt;
-    const int nbh = hop_blocks(S, g.Vh);
+    const int nbh = hop_blocks(S, g.Vh, g.Ls);
 
     int it = 0;
     const int cap = fixed ? prm->fixed_iters : prm->max_iter + 1;
     while (true) {
       const bool prof = prm->profile && timed < max_timed && (it % 8 == 0);
-      hipEvent_t* ev = prof ? &C->events[(timed % 64) * 8] : nullptr;
+      hipEvent_t* ev = prof ? &C->events[timed * 8] : nullptr;
       if (prof) HIPCHK(hipEventRecord(ev[0], st));
       CHK(hop(C, S, ROLE_K1, k1, st));
       if (prof) HIPCHK(hipEventRecord(ev[1], st));
@@ -597,15 +615,7 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
       if (prof) HIPCHK(hipEventRecord(ev[7], st));
       launch_finalize(FIN_BETA, partial, nbh, nrhs, Sst, nullptr, st);
       launch_cg_update(S, PR, g, xin, rin, pS, Sst.alpha, Sst.beta, Sst.u2run, nrhs, st);
-      if (prof) {
-        HIPCHK(hipEventSynchronize(ev[7]));
-        float ms;
-        for (int k = 0; k < 4; ++k) {
-          HIPCHK(hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
-          hop_ms[k] += ms;
-        }
-        ++timed;
-      }
+      if (prof) ++timed;
       ++it;
       if (it % check == 0 || it >= cap) {
         CHK(fetch(C, Sst.halt, nrhs * sizeof(int), hbuf.data(), st));
@@ -671,10 +681,17 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
   HIPCHK(hipStreamSynchronize(st));
   HIPCHK(hipGetLastError());
   const double t1 = now_s();
+  for (int j = 0; j < timed; ++j) {  // events are read only after the solve: no mid-solve host stalls
+    float ms;
+    for (int k = 0; k < 4; ++k) {
+      HIPCHK(hipEventElapsedTime(&ms, C->events[j * 8 + 2 * k], C->events[j * 8 + 2 * k + 1]));
+      hop_ms[k] += ms;
+    }
+  }
 
   int worst = EOFA_OK;
   for (int r = 0; r < nrhs; ++r) {
-    const double tr = bb[r] > 0 ? std::sqrt((re[r] + rodd[r]) / bb[r]) : 0.0;
+    const double tr = bb[r] > 0 ? std::sqrt((re[r] + rodd[r]) / bb[r]) : ((re[r] + rodd[r]) == 0.0 ? 0.0 : NAN);
     const bool conv = std::isfinite(tr) && tr <= prm->tol;
     if (status[r] == EOFA_OK && !conv && !fixed) status[r] = std::isfinite(tr) ? EOFA_ERR_NOT_CONVERGED : EOFA_ERR_BREAKDOWN;
     if (stats) {

@@ -93,7 +93,7 @@ struct HopArgs {
 
 // kernel launchers (kernels.hip)
 int launch_hop(int prec, int role, const HopArgs& a, hipStream_t st, int* nblk_out);
-int hop_blocks(int prec, int Vh);
+int hop_blocks(int prec, int Vh, int Ls);
 void launch_pack(int prec, const Geometry& g, const void* full, void* packed, int parity, int nrhs,
                  int g5r5, hipStream_t st);
 void launch_unpack(int prec, const Geometry& g, const void* packed, void* full, int parity, int nrhs,

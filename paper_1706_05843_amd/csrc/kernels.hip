@@ -69,14 +69,16 @@ struct FD {
   int Ls, Vh, nrhs;
 };
 
+// element (r, q, s, i) = r * 6 * Vh * Ls + q * Vh * Ls + (i * Ls + s)
+__device__ __forceinline__ size_t qstride(const FD& f) { return (size_t)f.Vh * f.Ls; }
 __device__ __forceinline__ size_t eidx(const FD& f, int r, int q, int s, int i) {
-  return ((size_t)(r * 6 + q) * f.Ls + s) * f.Vh + i;
+  return (size_t)(r * 6 + q) * qstride(f) + (unsigned)(i * f.Ls + s);
 }
 __device__ __forceinline__ const float* scale_ptr(const void* base, const FD& f) {
-  return (const float*)((const char*)base + (size_t)f.nrhs * 6 * f.Ls * f.Vh * 8);
+  return (const float*)((const char*)base + (size_t)f.nrhs * 6 * qstride(f) * 8);
 }
 __device__ __forceinline__ size_t sidx(const FD& f, int r, int s, int i) {
-  return ((size_t)r * f.Ls + s) * f.Vh + i;
+  return (size_t)r * qstride(f) + (unsigned)(i * f.Ls + s);
 }
 
 template <int P>
@@ -128,11 +130,12 @@ __device__ __forceinline__ void ld_spinor(const void* base, const FD& f, int r, 
                                           int q0 = 0, int q1 = 6) {
   R sc = R(1);
   if constexpr (P == P16) sc = scale_ptr(base, f)[sidx(f, r, s, i)];
+  const size_t e0 = eidx(f, r, 0, s, i), qs = qstride(f);
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
     if (q < q0 || q >= q1) continue;
     cx<R> a, b;
-    ld_pair<P>(base, eidx(f, r, q, s, i), a, b);
+    ld_pair<P>(base, e0 + q * qs, a, b);
     if constexpr (P == P16) {
       a = sc * a;
       b = sc * b;
@@ -149,21 +152,23 @@ __device__ __forceinline__ void st_spinor(void* base, const FD& f, int r, int s,
 #pragma unroll
     for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf((float)v[c].r), fabsf((float)v[c].i)));
     const float inv = m > 0.f ? 1.0f / m : 0.f;
+    const size_t e0 = eidx(f, r, 0, s, i), qs = qstride(f);
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
       cx<float> a = {(float)v[2 * q].r * inv, (float)v[2 * q].i * inv};
       cx<float> b = {(float)v[2 * q + 1].r * inv, (float)v[2 * q + 1].i * inv};
-      st_pair<P16>(base, eidx(f, r, q, s, i), a, b);
+      st_pair<P16>(base, e0 + q * qs, a, b);
     }
     float* sp = (float*)scale_ptr(base, f);
     sp[sidx(f, r, s, i)] = m;
   } else {
     using RS = typename ST<P>::R;
+    const size_t e0 = eidx(f, r, 0, s, i), qs = qstride(f);
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
       cx<RS> a = {(RS)v[2 * q].r, (RS)v[2 * q].i};
       cx<RS> b = {(RS)v[2 * q + 1].r, (RS)v[2 * q + 1].i};
-      st_pair<P>(base, eidx(f, r, q, s, i), a, b);
+      st_pair<P>(base, e0 + q * qs, a, b);
     }
   }
 }
@@ -213,56 +218,100 @@ EOFA_ROLE(ROLE_FULLRES, false, true, A_ID, true, O_ADDZ, true)
 
 constexpr int LSTR = 73;  // padded link stride per site in LDS (complex units)
 constexpr int NSTR = 9;   // padded neighbour stride per site in LDS
+constexpr int MAXW = 4;   // most waves per work-group
 
-template <int P>
-constexpr int sites_per_block() {
-  return P == P64 ? 8 : 16;
+// A wave holds the whole s-columns of G = 64 / Ls consecutive 4D sites
+// (lane = g * Ls + s); a work-group holds W(Ls) waves, at most 20 4D sites,
+// which bounds the LDS staging of links and columns.
+__host__ __device__ inline int sites_per_wave(int Ls) { return 64 / Ls; }
+__host__ __device__ inline int waves_per_block(int Ls) {
+  const int G = sites_per_wave(Ls);
+  return G <= 5 ? MAXW : (16 / G > 1 ? 16 / G : 1);
 }
 
 template <class R>
 struct HopLds {
   // byte sizes of the LDS regions
-  static __host__ __device__ size_t links(int SB) { return (size_t)SB * LSTR * sizeof(cx<R>); }
-  static __host__ __device__ size_t nbr(int SB) { return (size_t)SB * NSTR * 4; }
+  static __host__ __device__ size_t links(int SBk) { return (size_t)SBk * LSTR * sizeof(cx<R>); }
+  static __host__ __device__ size_t nbr(int SBk) { return (((size_t)SBk * NSTR * 4 + 15) / 16) * 16; }
   static __host__ __device__ size_t mat(int Ls) { return (((size_t)2 * Ls * (Ls + 1) * sizeof(R) + 15) / 16) * 16; }
-  static __host__ __device__ size_t col(int SB, int Ls) { return (size_t)SB * (Ls * 6 + 1) * sizeof(cx<R>); }
+  static __host__ __device__ size_t col(int SBk, int Ls) { return (size_t)SBk * (Ls * 6 + 1) * sizeof(cx<R>); }
 };
 
-// Dhop (or g5 Dhop g5 when DAG) applied to D~ in (PRE) at 5D site (s, neighbours of il)
+// Dhop (or g5 Dhop g5 when DAG) applied to D~ in (PRE) at the 5D site (s, i)
+// of local site ls. The D~ premix needs P_+ psi at s-1 and P_- psi at s+1 of
+// the same neighbour: the lanes (g, s-1) and (g, s+1) of this wave hold
+// exactly those spinors for the same direction, so they are exchanged across
+// lanes instead of being loaded again.
 template <int P, bool DAG, bool PRE>
-__device__ __forceinline__ void hop_site(const HopArgs& a, const FD& fin, int r, int s, int il,
+__device__ __forceinline__ void hop_site(const HopArgs& a, const FD& fin, int r, int s, int g, int ls,
                                          const cx<typename ST<P>::R>* s_link, const int* s_nbr,
                                          cx<typename ST<P>::R>* acc) {
   using R = typename ST<P>::R;
   const int Ls = a.Ls;
-  R cpd = R(1), aup = R(0), alo = R(0);
-  int sup = 0, slo = 0;
+  // D~ psi = (c+d) [psi_s + (c-d)/(c+d) (P_+ (L_+ psi)_s + P_- (L_- psi)_s)]: the
+  // overall (c+d) is folded into the final -1/2.
+  R aup = R(0), alo = R(0), post = R(-0.5);
+  int src_up = 0, src_lo = 0;
   if constexpr (PRE) {
-    const R cmd = (R)a.cmd;
+    const R q = (R)(a.cmd / a.cpd);
     const R m = (R)a.mop[r];
-    cpd = (R)a.cpd;
-    sup = s > 0 ? s - 1 : Ls - 1;
-    aup = s > 0 ? cmd : -m * cmd;
-    slo = s < Ls - 1 ? s + 1 : 0;
-    alo = s < Ls - 1 ? cmd : -m * cmd;
+    post = (R)(-0.5 * a.cpd);
+    aup = s > 0 ? q : -m * q;
+    alo = s < Ls - 1 ? q : -m * q;
+    src_up = g * Ls + (s > 0 ? s - 1 : Ls - 1);
+    src_lo = g * Ls + (s < Ls - 1 ? s + 1 : 0);
   }
 #pragma unroll
   for (int c = 0; c < 12; ++c) acc[c] = {R(0), R(0)};
 #pragma unroll
   for (int dir = 0; dir < 8; ++dir) {
+    // scheduling fence: one direction's spinor is live at a time
+    // (occupancy, not deep unrolling, hides the load latency)
+    __builtin_amdgcn_sched_barrier(0);
     const int mu = dir & 3;
     const bool fwd = dir < 4;
-    const int n = s_nbr[il * NSTR + dir];
+    const int n = s_nbr[ls * NSTR + dir];
     cx<R> sp[12];
-    ld_spinor<P>(a.in, fin, r, s, n, sp);
-    if constexpr (PRE) {
-      cx<R> t[12];
-      ld_spinor<P>(a.in, fin, r, sup, n, t, 0, 3);
-      ld_spinor<P>(a.in, fin, r, slo, n, t, 3, 6);
+    if constexpr (P == P16) {
+      // raw half2 words; the neighbours' halves travel as raw words too and
+      // every conversion is folded into a mixed-precision FMA
+      const size_t e0 = eidx(fin, r, 0, s, n), qs = qstride(fin);
+      const float sc = scale_ptr(a.in, fin)[sidx(fin, r, s, n)];
+      unsigned w[12];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) sp[c] = cpd * sp[c] + aup * t[c];
+      for (int q = 0; q < 6; ++q) {
+        const uint2 v = ((const uint2*)a.in)[e0 + q * qs];
+        w[2 * q] = v.x;
+        w[2 * q + 1] = v.y;
+      }
+      if constexpr (PRE) {
+        const float su = __shfl(sc, src_up, 64) * aup, sl = __shfl(sc, src_lo, 64) * alo;
 #pragma unroll
-      for (int c = 6; c < 12; ++c) sp[c] = cpd * sp[c] + alo * t[c];
+        for (int c = 0; c < 12; ++c) {
+          const unsigned t = __shfl((int)w[c], c < 6 ? src_up : src_lo, 64);
+          const h2_t hs = __builtin_bit_cast(h2_t, w[c]), ht = __builtin_bit_cast(h2_t, t);
+          const float f = c < 6 ? su : sl;
+          sp[c] = {fmaf(f, (float)ht.x, sc * (float)hs.x), fmaf(f, (float)ht.y, sc * (float)hs.y)};
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          const h2_t hs = __builtin_bit_cast(h2_t, w[c]);
+          sp[c] = {sc * (float)hs.x, sc * (float)hs.y};
+        }
+      }
+    } else {
+      ld_spinor<P>(a.in, fin, r, s, n, sp);
+      if constexpr (PRE) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          const int src = c < 6 ? src_up : src_lo;
+          const R f = c < 6 ? aup : alo;
+          const cx<R> t = {__shfl(sp[c].r, src, 64), __shfl(sp[c].i, src, 64)};
+          sp[c] = {fma(f, t.r, sp[c].r), fma(f, t.i, sp[c].i)};
+        }
+      }
     }
     // sg = -1 for (1 - g_mu), +1 for (1 + g_mu)
     const R sg = (fwd != DAG) ? R(-1) : R(1);
@@ -284,8 +333,8 @@ __device__ __forceinline__ void hop_site(const HopArgs& a, const FD& fin, int r,
         h[3 + c] = u1 + sg * l1;
       }
     }
-    const cx<R>* U = s_link + il * LSTR + dir * 9;
-    cx<R> g[6];
+    const cx<R>* U = s_link + ls * LSTR + dir * 9;
+    cx<R> gv[6];
 #pragma unroll
     for (int k = 0; k < 2; ++k)
 #pragma unroll
@@ -293,11 +342,13 @@ __device__ __forceinline__ void hop_site(const HopArgs& a, const FD& fin, int r,
         cx<R> v = cmul(U[a3 * 3 + 0], h[k * 3 + 0]);
         v = cfma(U[a3 * 3 + 1], h[k * 3 + 1], v);
         v = cfma(U[a3 * 3 + 2], h[k * 3 + 2], v);
-        g[k * 3 + a3] = v;
+        gv[k * 3 + a3] = v;
       }
 #pragma unroll
+    for (int c = 0; c < 6; ++c) asm volatile("" : "+v"(gv[c].r), "+v"(gv[c].i));
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const cx<R> g0 = g[c], g1 = g[3 + c];
+      const cx<R> g0 = gv[c], g1 = gv[3 + c];
       acc[c] = acc[c] + g0;
       acc[3 + c] = acc[3 + c] + g1;
       if (mu == 0) {  // A^dag g = (i g1, i g0)
@@ -316,7 +367,7 @@ __device__ __forceinline__ void hop_site(const HopArgs& a, const FD& fin, int r,
     }
   }
 #pragma unroll
-  for (int c = 0; c < 12; ++c) acc[c] = R(-0.5) * acc[c];
+  for (int c = 0; c < 12; ++c) acc[c] = post * acc[c];
 }
 
 template <class R>
@@ -349,44 +400,58 @@ __device__ __forceinline__ void col_matvec(const R* M, const cx<R>* col, int Ls,
   for (int c = 0; c < 6; ++c) v[half * 6 + c] = t[c];
 }
 
-template <int P, int PR, int SB, int ROLE>
-__global__ void __launch_bounds__(512) hop_kernel(HopArgs a) {
+// Occupancy target: 4 waves per SIMD for FP32 arithmetic (128 VGPRs),
+// 3 for FP64 (about 168 VGPRs); the stencil hides latency by occupancy.
+template <int P>
+struct HopOcc {
+  static constexpr int waves = P == P64 ? 3 : 4;
+};
+
+template <int P, int PR, int ROLE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HopOcc<P>::waves, 8)))
+hop_kernel(HopArgs a) {
   using RT = RoleT<ROLE>;
   using R = typename ST<P>::R;
   using L = HopLds<R>;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  __shared__ double s_red[16];
+  __shared__ double s_red[MAXW];
 
   const int Ls = a.Ls, Vh = a.Vh;
+  const int G = sites_per_wave(Ls);
+  const int W = waves_per_block(Ls);
+  const int SBk = W * G;  // 4D sites per work-group
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int il = tid % SB;
-  const int s = tid / SB;
-  const int i0 = blockIdx.x * SB;
-  const int i = i0 + il;
-  const bool live = (s < Ls) && (i < Vh);
+  const int wave = tid >> 6, lane = tid & 63;
+  const int g = lane / Ls;
+  const int s = lane - g * Ls;
+  const bool in_col = g < G;  // lanes 64 - 64 % Ls .. 63 are idle
+  const int ls = min(wave * G + g, SBk - 1);
+  const int i0 = blockIdx.x * SBk;
+  const int i = i0 + wave * G + g;
+  const bool live = in_col && (i < Vh);
   const FD fd = {Ls, Vh, a.nrhs};
 
   unsigned char* p = smem;
   cx<R>* s_link = (cx<R>*)p;
-  p += L::links(SB);
+  p += L::links(SBk);
   int* s_nbr = (int*)p;
-  p += L::nbr(SB);
+  p += L::nbr(SBk);
   R* s_mA = (R*)p;
   if (RT::AM == A_MAT) p += L::mat(Ls);
   R* s_mB = (R*)p;
   if (RT::BM) p += L::mat(Ls);
-  cx<R>* s_col = (cx<R>*)p;  // SB x (Ls*6+1) complex: one chirality half of a column
+  cx<R>* s_col = (cx<R>*)p;  // SBk x (Ls*6+1) complex: one chirality half of each column
   const int cstr = Ls * 6 + 1;
 
   // stage the links and neighbour indices of this block's sites
-  for (int j = tid; j < SB * 72; j += nthr) {
-    const int site = j / 72, k = j % 72;
+  for (int j = tid; j < SBk * 72; j += nthr) {
+    const int site = j / 72, k = j - site * 72;
     cx<R> v = {R(0), R(0)};
     if (i0 + site < Vh) v = ld_link<P>(a.links, (size_t)(i0 + site) * 72 + k);
     s_link[site * LSTR + k] = v;
   }
-  for (int j = tid; j < SB * 8; j += nthr) {
-    const int site = j / 8, k = j % 8;
+  for (int j = tid; j < SBk * 8; j += nthr) {
+    const int site = j / 8, k = j - site * 8;
     s_nbr[site * NSTR + k] = (i0 + site < Vh) ? a.nbr[(size_t)(i0 + site) * 8 + k] : 0;
   }
 
@@ -401,12 +466,11 @@ __global__ void __launch_bounds__(512) hop_kernel(HopArgs a) {
     __syncthreads();
 
     cx<R> acc[12];
-    if (live) {
-      hop_site<P, RT::DAG, RT::PRE>(a, fd, r, s, il, s_link, s_nbr, acc);
-    } else {
+    hop_site<P, RT::DAG, RT::PRE>(a, fd, r, s, g, ls, s_link, s_nbr, acc);
+    // an unconditional use: stops the hop arithmetic from being sunk into the
+    // (live-only) store block, away from the per-direction loads and shuffles
 #pragma unroll
-      for (int c = 0; c < 12; ++c) acc[c] = {R(0), R(0)};
-    }
+    for (int c = 0; c < 12; ++c) asm volatile("" : "+v"(acc[c].r), "+v"(acc[c].i));
 
     cx<R> v[12];
     if constexpr (RT::AM == A_NEG) {
@@ -418,24 +482,23 @@ __global__ void __launch_bounds__(512) hop_kernel(HopArgs a) {
     }
     if constexpr (RT::AM == A_MAT || RT::BM) {
       cx<R> y[12];
-      if constexpr (RT::BM) {
-        if (live) ld_spinor<P>(a.y, fd, r, s, i, y);
-      }
+      if constexpr (RT::BM) ld_spinor<P>(a.y, fd, r, s, live ? i : i0 < Vh ? i0 : 0, y);
+      cx<R>* mycol = s_col + ls * cstr;
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
         if constexpr (RT::AM == A_MAT) {
           if (half == 1) __syncthreads();
-          if (live)
-            for (int c = 0; c < 6; ++c) s_col[il * cstr + s * 6 + c] = acc[half * 6 + c];
+          if (in_col)
+            for (int c = 0; c < 6; ++c) mycol[s * 6 + c] = acc[half * 6 + c];
           __syncthreads();
-          if (live) col_matvec<R>(s_mA, s_col + il * cstr, Ls, s, half, v, false);
+          col_matvec<R>(s_mA, mycol, Ls, s, half, v, false);
         }
         if constexpr (RT::BM) {
           __syncthreads();
-          if (live)
-            for (int c = 0; c < 6; ++c) s_col[il * cstr + s * 6 + c] = y[half * 6 + c];
+          if (in_col)
+            for (int c = 0; c < 6; ++c) mycol[s * 6 + c] = y[half * 6 + c];
           __syncthreads();
-          if (live) col_matvec<R>(s_mB, s_col + il * cstr, Ls, s, half, v, true);
+          col_matvec<R>(s_mB, mycol, Ls, s, half, v, true);
         }
       }
     }
@@ -477,11 +540,11 @@ __global__ void __launch_bounds__(512) hop_kernel(HopArgs a) {
     if constexpr (RT::NRM) {
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
-      if ((tid & 63) == 0) s_red[tid >> 6] = nrm;
+      if (lane == 0) s_red[wave] = nrm;
       __syncthreads();
       if (tid == 0) {
         double t = 0.0;
-        for (int w = 0; w < (nthr + 63) / 64; ++w) t += s_red[w];
+        for (int w = 0; w < W; ++w) t += s_red[w];
         a.partial[(size_t)r * gridDim.x + blockIdx.x] = t;
       }
     }
@@ -493,30 +556,35 @@ constexpr int acc_prec() {
   return P == P64 ? P64 : P32;
 }
 
+int hop_blocks(int prec, int Vh, int Ls) {
+  (void)prec;
+  const int SBk = waves_per_block(Ls) * sites_per_wave(Ls);
+  return (Vh + SBk - 1) / SBk;
+}
+
 template <int P, int ROLE>
 int launch_hop_t(const HopArgs& a, hipStream_t st, int* nblk_out) {
   using R = typename ST<P>::R;
   using RT = RoleT<ROLE>;
   using L = HopLds<R>;
-  constexpr int SB = sites_per_block<P>();
   const int Ls = a.Ls;
-  size_t lds = L::links(SB) + L::nbr(SB);
+  const int SBk = waves_per_block(Ls) * sites_per_wave(Ls);
+  size_t lds = L::links(SBk) + L::nbr(SBk);
   if (RT::AM == A_MAT) lds += L::mat(Ls);
   if (RT::BM) lds += L::mat(Ls);
-  if (RT::AM == A_MAT || RT::BM) lds += L::col(SB, Ls);
-  const int threads = ((SB * Ls + 63) / 64) * 64;
-  const int nblk = (a.Vh + SB - 1) / SB;
+  if (RT::AM == A_MAT || RT::BM) lds += L::col(SBk, Ls);
+  const int nblk = hop_blocks(P, a.Vh, Ls);
   const int rb = a.rhs_block > 0 ? a.rhs_block : 1;
   dim3 grid(nblk, (a.nrhs + rb - 1) / rb);
   HopArgs b = a;
   b.rhs_block = rb;
-  auto fn = hop_kernel<P, acc_prec<P>(), SB, ROLE>;
+  auto fn = hop_kernel<P, acc_prec<P>(), ROLE>;
   if (lds > 65536) {
     if (hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
         hipSuccess)
       return EOFA_ERR_HIP;
   }
-  hipLaunchKernelGGL(fn, grid, dim3(threads), lds, st, b);
+  hipLaunchKernelGGL(fn, grid, dim3(64 * waves_per_block(Ls)), lds, st, b);
   if (nblk_out) *nblk_out = nblk;
   return hipGetLastError() == hipSuccess ? EOFA_OK : EOFA_ERR_HIP;
 }
@@ -545,11 +613,6 @@ int launch_hop(int prec, int role, const HopArgs& a, hipStream_t st, int* nblk_o
     case P16: return launch_hop_p<P16>(role, a, st, nblk_out);
   }
   return EOFA_ERR_INVALID;
-}
-
-int hop_blocks(int prec, int Vh) {
-  const int SB = prec == P64 ? sites_per_block<P64>() : sites_per_block<P32>();
-  return (Vh + SB - 1) / SB;
 }
 
 // ---------------------------------------------------------------------------
@@ -652,7 +715,7 @@ __global__ void __launch_bounds__(256) pack_kernel(GeoD g, int parity, int nrhs,
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
   if (idx >= g.Ls * g.Vh) return;
-  const int s = idx / g.Vh, i = idx - s * g.Vh;
+  const int i = idx / g.Ls, s = idx - i * g.Ls;
   int x[4];
   site_coords(g, parity, i, x);
   const size_t V = (size_t)g.L[0] * g.L[1] * g.L[2] * g.L[3];
@@ -675,7 +738,7 @@ __global__ void __launch_bounds__(256) unpack_kernel(GeoD g, int parity, int nrh
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
   if (idx >= g.Ls * g.Vh) return;
-  const int s = idx / g.Vh, i = idx - s * g.Vh;
+  const int i = idx / g.Ls, s = idx - i * g.Ls;
   int x[4];
   site_coords(g, parity, i, x);
   const size_t V = (size_t)g.L[0] * g.L[1] * g.L[2] * g.L[3];
@@ -720,7 +783,7 @@ __global__ void __launch_bounds__(256) smat_kernel(int Ls, int Vh, int nrhs, con
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
   if (idx >= Ls * Vh) return;
-  const int s = idx / Vh, i = idx - s * Vh;
+  const int i = idx / Ls, s = idx - i * Ls;
   const FD f = {Ls, Vh, nrhs};
   const double* M = mats + ((size_t)r * NMAT + mat) * 2 * Ls * Ls;
   cx<R> v[12];
@@ -757,7 +820,7 @@ __global__ void __launch_bounds__(256) convert_kernel(int Ls, int Vh, int nrhs, 
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
   if (idx >= Ls * Vh) return;
-  const int s = idx / Vh, i = idx - s * Vh;
+  const int i = idx / Ls, s = idx - i * Ls;
   const FD f = {Ls, Vh, nrhs};
   cx<double> v[12];
   {
@@ -779,7 +842,7 @@ __global__ void __launch_bounds__(256) axpy64_kernel(int Ls, int Vh, int nrhs, d
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
   if (idx >= Ls * Vh) return;
-  const int s = idx / Vh, i = idx - s * Vh;
+  const int i = idx / Ls, s = idx - i * Ls;
   const FD f = {Ls, Vh, nrhs};
   using RI = typename ST<PI>::R;
   cx<RI> t[12];
@@ -796,7 +859,7 @@ __global__ void __launch_bounds__(256) zero_kernel(int Ls, int Vh, int nrhs, voi
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
   if (idx >= Ls * Vh) return;
-  const int s = idx / Vh, i = idx - s * Vh;
+  const int i = idx / Ls, s = idx - i * Ls;
   const FD f = {Ls, Vh, nrhs};
   using R = typename ST<P>::R;
   cx<R> v[12];
@@ -824,7 +887,7 @@ __global__ void __launch_bounds__(256) norm2_kernel(int Ls, int Vh, int nrhs, co
   const int r = blockIdx.y;
   double n = 0.0;
   if (idx < Ls * Vh) {
-    const int s = idx / Vh, i = idx - s * Vh;
+    const int i = idx / Ls, s = idx - i * Ls;
     const FD f = {Ls, Vh, nrhs};
     using R = typename ST<P>::R;
     cx<R> v[12];
@@ -842,7 +905,7 @@ __global__ void __launch_bounds__(256) cg_update_kernel(int Ls, int Vh, int nrhs
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
   if (idx >= Ls * Vh || u2run[r] == 0) return;
-  const int s = idx / Vh, i = idx - s * Vh;
+  const int i = idx / Ls, s = idx - i * Ls;
   const FD f = {Ls, Vh, nrhs};
   using RR = typename ST<PR>::R;
   using RS = typename ST<PS>::R;
