@@ -109,6 +109,8 @@ def main():
     ap.add_argument("--inner-tol", type=float, default=0.0)
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 reference solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device-to-device copy (known bytes) to calibrate HBM counters")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -119,6 +121,15 @@ def main():
     import numpy as np
     import torch
     from paper_1706_05843_amd import eofa, synth
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        print("bench: calibration copy done (3 x 1 GiB device-to-device)", file=sys.stderr, flush=True)
 
     dims, Ls, eps, m1, gseed, sseed = WORKLOADS[args.workload]
     m2 = 1.0

@@ -112,6 +112,7 @@ int stage(eofa_ctx* C, size_t bytes) {
 }
 
 size_t mats_per_rhs(const Geometry& g) { return (size_t)NMAT * 2 * g.Ls * g.Ls; }
+size_t scoef_per_rhs(const Geometry& g) { return (size_t)SCOEF_HEAD + g.Ls; }
 
 // Build and upload the fifth-dimension matrices and operator masses of
 // sys[0..nrhs). Cached: a repeat of the same systems uploads nothing.
@@ -126,14 +127,15 @@ int upload_systems(eofa_ctx* C, const eofa_system* sys, int nrhs, hipStream_t st
     key.push_back(sys[r].beta != 0.0 ? (double)sys[r].chi : 0.0);
   }
   if (key == C->sys_key && C->mats) return EOFA_OK;
-  const size_t per = mats_per_rhs(C->g);
-  const size_t n = per * nrhs + nrhs;
+  const size_t per = mats_per_rhs(C->g), sper = scoef_per_rhs(C->g);
+  const size_t n = per * nrhs + nrhs + sper * nrhs;
   std::vector<double> h(n);
   for (int r = 0; r < nrhs; ++r) {
     std::string err;
     const int rc = build_fifth(C->g, C->M5, C->b5, C->c5, sys[r], h.data() + per * r, err);
     if (rc != EOFA_OK) return fail(rc, "right-hand side " + std::to_string(r) + ": " + err);
     h[per * nrhs + r] = sys[r].m_op;
+    build_struct(C->g, C->b5, C->c5, sys[r], h.data() + per * nrhs + nrhs + sper * r);
   }
   if (C->mats_n < n) {
     if (C->mats) HIPCHK(hipFree(C->mats));
@@ -185,6 +187,9 @@ HopArgs base_args(eofa_ctx* C, int prec, int out_parity, int nrhs) {
   a.cpd = C->c + C->d;
   a.cmd = C->c - C->d;
   a.mop = mop_ptr(C, nrhs);
+  a.scoef = mop_ptr(C, nrhs) + nrhs;
+  a.bee = (C->c + C->d) * (4.0 - C->M5) + 1.0;
+  a.cee = 1.0 - (C->c - C->d) * (4.0 - C->M5);
   a.Vh = C->g.Vh;
   a.Ls = C->g.Ls;
   a.nrhs = nrhs;
@@ -551,7 +556,7 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
       HopArgs a3 = base_args(C, S, 0, nrhs);
       a3.in = rS;
       a3.out = tS;
-      a3.matA = MAT_MEE_INV_T_DT_T;
+      a3.matA = MAT_MEE_INV_T;
       CHK(hop(C, S, ROLE_K3, a3, st));
       HopArgs a4 = base_args(C, S, 1, nrhs);
       a4.in = tS;
@@ -582,7 +587,7 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
     HopArgs k3 = base_args(C, S, 0, nrhs);
     k3.in = wS;
     k3.out = tS;
-    k3.matA = MAT_MEE_INV_T_DT_T;
+    k3.matA = MAT_MEE_INV_T;
     k3.halt = Sst.halt;
     HopArgs k4 = base_args(C, S, 1, nrhs);
     k4.in = tS;

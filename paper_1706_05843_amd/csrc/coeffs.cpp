@@ -96,6 +96,26 @@ double sgn(int n) { return (n % 2 != 0) ? -1.0 : 1.0; }
 
 }  // namespace
 
+double k_eofa(int Ls, double c, double d, double m_a, double m_b);
+
+void build_struct(const Geometry& g, double b5, double c5, const eofa_system& sys, double* out) {
+  const int n = g.Ls;
+  const double c = 0.5 * (b5 + c5), d = 0.5 * (b5 - c5);
+  const double Nop = std::pow(c + d, n) + sys.m_op * std::pow(c - d, n);
+  const bool shifted = sys.beta != 0.0;
+  const int chir = shifted ? sys.chi : 1;
+  out[0] = sys.m_op;
+  out[1] = shifted ? chir * sys.beta * k_eofa(n, c, d, sys.m_a, sys.m_b) : 0.0;
+  out[2] = chir;
+  out[3] = 0.0;
+  for (int s = 0; s < n; ++s) {
+    if (chir > 0)
+      out[SCOEF_HEAD + s] = sgn(s) * std::pow(c - d, s) / std::pow(c + d, n + s + 1) * Nop;
+    else
+      out[SCOEF_HEAD + s] = sgn(s + 1) * std::pow(c - d, n - 1 - s) / std::pow(c + d, 2 * n - s) * Nop;
+  }
+}
+
 double k_eofa(int Ls, double c, double d, double m_a, double m_b) {
   const double Na = std::pow(c + d, Ls) + m_a * std::pow(c - d, Ls);
   const double Nb = std::pow(c + d, Ls) + m_b * std::pow(c - d, Ls);

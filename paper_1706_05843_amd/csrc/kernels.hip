@@ -190,7 +190,15 @@ __device__ __forceinline__ cx<typename ST<P>::R> ld_link(const void* base, size_
 // ---------------------------------------------------------------------------
 // the fused hop kernel
 
-enum { A_ID = 0, A_NEG = 1, A_MAT = 2 };
+// epilogue applied to the hop result h = Dhop (D~ in) of each 5D site:
+//   A_ID    v = h              A_NEG  v = -h
+//   A_MAT   v = M h            (dense Ls x Ls per chirality, through LDS)
+//   A_DTT   v = D~^T h         A_NDTT v = -D~^T h   (structured: lane exchange)
+//   A_MATDT v = M D~^T h
+// plus the same-site term B y:
+//   B_MEE   + M_ee y           B_MEET + M_ee^T y    (structured: lane exchange)
+enum { A_ID = 0, A_NEG = 1, A_MAT = 2, A_DTT = 3, A_NDTT = 4, A_MATDT = 5 };
+enum { B_NONE = 0, B_MEE = 1, B_MEET = 2 };
 enum { O_STORE = 0, O_ADDZ = 1, O_RUPD = 2, O_STORE_R = 3 };
 
 template <int ROLE>
@@ -200,20 +208,20 @@ struct RoleT;
   struct RoleT<NAME> {                               \
     static constexpr bool DAG = dag, PRE = pre;      \
     static constexpr int AM = am;                    \
-    static constexpr bool BM = bm;                   \
+    static constexpr int BM = bm;                    \
     static constexpr int OM = om;                    \
     static constexpr bool NRM = nrm;                 \
   };
-EOFA_ROLE(ROLE_DSLASH, false, true, A_ID, false, O_STORE, false)
-EOFA_ROLE(ROLE_DSLASH_DAG, true, false, A_MAT, false, O_STORE, false)
-EOFA_ROLE(ROLE_K1, false, true, A_MAT, false, O_STORE, false)
-EOFA_ROLE(ROLE_K2, false, true, A_NEG, true, O_STORE, true)
-EOFA_ROLE(ROLE_K3, true, false, A_MAT, false, O_STORE, false)
-EOFA_ROLE(ROLE_K4, true, false, A_MAT, true, O_RUPD, true)
-EOFA_ROLE(ROLE_K4S, true, false, A_MAT, true, O_STORE_R, true)
-EOFA_ROLE(ROLE_SRC, false, true, A_ID, false, O_ADDZ, false)
-EOFA_ROLE(ROLE_RES, false, true, A_NEG, true, O_ADDZ, true)
-EOFA_ROLE(ROLE_FULLRES, false, true, A_ID, true, O_ADDZ, true)
+EOFA_ROLE(ROLE_DSLASH, false, true, A_ID, B_NONE, O_STORE, false)
+EOFA_ROLE(ROLE_DSLASH_DAG, true, false, A_DTT, B_NONE, O_STORE, false)
+EOFA_ROLE(ROLE_K1, false, true, A_MAT, B_NONE, O_STORE, false)
+EOFA_ROLE(ROLE_K2, false, true, A_NEG, B_MEE, O_STORE, true)
+EOFA_ROLE(ROLE_K3, true, false, A_MATDT, B_NONE, O_STORE, false)
+EOFA_ROLE(ROLE_K4, true, false, A_NDTT, B_MEET, O_RUPD, true)
+EOFA_ROLE(ROLE_K4S, true, false, A_NDTT, B_MEET, O_STORE_R, true)
+EOFA_ROLE(ROLE_SRC, false, true, A_ID, B_NONE, O_ADDZ, false)
+EOFA_ROLE(ROLE_RES, false, true, A_NEG, B_MEE, O_ADDZ, true)
+EOFA_ROLE(ROLE_FULLRES, false, true, A_ID, B_MEE, O_ADDZ, true)
 #undef EOFA_ROLE
 
 constexpr int LSTR = 73;  // padded link stride per site in LDS (complex units)
@@ -400,6 +408,62 @@ __device__ __forceinline__ void col_matvec(const R* M, const cx<R>* col, int Ls,
   for (int c = 0; c < 6; ++c) v[half * 6 + c] = t[c];
 }
 
+template <class R>
+__device__ __forceinline__ cx<R> shfl_cx(cx<R> v, int src) {
+  return {__shfl(v.r, src, 64), __shfl(v.i, src, 64)};
+}
+
+// Fifth-dimension neighbours of lane (g, s) in its wave: the column of one 4D
+// site lives in lanes g*Ls .. g*Ls+Ls-1.
+//   (L_+ v)_s = v_{s-1}, -m v_{Ls-1} at s = 0;  (L_- v)_s = v_{s+1}, -m v_0 at s = Ls-1
+//   L_+^T has the L_- pattern and L_-^T the L_+ pattern.
+template <class R>
+struct SNbr {
+  int sp, sn;  // source lanes of s-1 and s+1 (cyclic)
+  R fp, fn;    // 1, or -m across the wrap
+};
+
+template <class R, bool TRANS>
+__device__ __forceinline__ void lmul(const cx<R>* v, cx<R>* out, const SNbr<R>& nb) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) out[c] = (TRANS ? nb.fn : nb.fp) * shfl_cx(v[c], TRANS ? nb.sn : nb.sp);
+#pragma unroll
+  for (int c = 6; c < 12; ++c) out[c] = (TRANS ? nb.fp : nb.fn) * shfl_cx(v[c], TRANS ? nb.sp : nb.sn);
+}
+
+// Rank-one part of the shifted same-parity block on the chirality half H0
+// (0: P_+, 6: P_-), with s* the special fifth-dimension index:
+//   TRANS = false:  v_s += sk u_s y_{s*}              (sk u e_{s*}^T y)
+//   TRANS = true :  v_s += delta_{s,s*} sk sum_s' u_s' y_s'   (sk e_{s*} u^T y)
+template <class R, bool TRANS, int H0>
+__device__ __forceinline__ void rank_one(const cx<R>* y, cx<R>* v, R sk, R us, int star_lane, bool is_star,
+                                         cx<R>* mycol, int s, int Ls, bool in_col) {
+  if constexpr (!TRANS) {
+    const R f = sk * us;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const cx<R> ys = shfl_cx(y[H0 + c], star_lane);
+      v[H0 + c].r = fma(f, ys.r, v[H0 + c].r);
+      v[H0 + c].i = fma(f, ys.i, v[H0 + c].i);
+    }
+  } else {
+    __syncthreads();
+    if (in_col)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) mycol[s * 6 + c] = us * y[H0 + c];
+    __syncthreads();
+    if (is_star) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        cx<R> sum = {R(0), R(0)};
+        for (int q = 0; q < Ls; ++q) sum = sum + mycol[q * 6 + c];
+        v[H0 + c].r = fma(sk, sum.r, v[H0 + c].r);
+        v[H0 + c].i = fma(sk, sum.i, v[H0 + c].i);
+      }
+    }
+  }
+}
+
 // Occupancy target: 4 waves per SIMD for FP32 arithmetic (128 VGPRs),
 // 3 for FP64 (about 168 VGPRs); the stencil hides latency by occupancy.
 template <int P>
@@ -426,22 +490,28 @@ hop_kernel(HopArgs a) {
   const int s = lane - g * Ls;
   const bool in_col = g < G;  // lanes 64 - 64 % Ls .. 63 are idle
   const int ls = min(wave * G + g, SBk - 1);
-  const int i0 = blockIdx.x * SBk;
+  // Work-groups are dealt round-robin to the 8 XCDs, each with its own L2:
+  // give XCD x a contiguous run of tiles so the +-z, +-t neighbours a tile
+  // reads were mostly fetched by the same XCD (a bijection of [0, gridDim.x)).
+  const int nblk = gridDim.x, xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
+  const int tile = xcd * (nblk / 8) + min(xcd, nblk % 8) + slot;
+  const int i0 = tile * SBk;
   const int i = i0 + wave * G + g;
   const bool live = in_col && (i < Vh);
   const FD fd = {Ls, Vh, a.nrhs};
 
+  constexpr bool DENSE = RT::AM == A_MAT || RT::AM == A_MATDT;
+  constexpr bool COL = DENSE || RT::BM == B_MEET;  // needs the LDS column buffer
   unsigned char* p = smem;
   cx<R>* s_link = (cx<R>*)p;
   p += L::links(SBk);
   int* s_nbr = (int*)p;
   p += L::nbr(SBk);
   R* s_mA = (R*)p;
-  if (RT::AM == A_MAT) p += L::mat(Ls);
-  R* s_mB = (R*)p;
-  if (RT::BM) p += L::mat(Ls);
+  if (DENSE) p += L::mat(Ls);
   cx<R>* s_col = (cx<R>*)p;  // SBk x (Ls*6+1) complex: one chirality half of each column
   const int cstr = Ls * 6 + 1;
+  (void)s_col;
 
   // stage the links and neighbour indices of this block's sites
   for (int j = tid; j < SBk * 72; j += nthr) {
@@ -460,9 +530,10 @@ hop_kernel(HopArgs a) {
   for (int r = rb0; r < rb1; ++r) {
     if (a.halt != nullptr && a.halt[r] != 0) continue;  // uniform over the block
     __syncthreads();
-    const double* mats_r = a.mats + (size_t)r * NMAT * 2 * Ls * Ls;
-    if constexpr (RT::AM == A_MAT) load_mat<R>(s_mA, mats_r + (size_t)a.matA * 2 * Ls * Ls, Ls, tid, nthr);
-    if constexpr (RT::BM) load_mat<R>(s_mB, mats_r + (size_t)a.matB * 2 * Ls * Ls, Ls, tid, nthr);
+    if constexpr (DENSE) {
+      const double* mats_r = a.mats + (size_t)r * NMAT * 2 * Ls * Ls;
+      load_mat<R>(s_mA, mats_r + (size_t)a.matA * 2 * Ls * Ls, Ls, tid, nthr);
+    }
     __syncthreads();
 
     cx<R> acc[12];
@@ -472,34 +543,70 @@ hop_kernel(HopArgs a) {
 #pragma unroll
     for (int c = 0; c < 12; ++c) asm volatile("" : "+v"(acc[c].r), "+v"(acc[c].i));
 
+    // fifth-dimension neighbours in this wave
+    SNbr<R> nb;
+    {
+      const R m = (R)a.mop[r];
+      nb.sp = g * Ls + (s > 0 ? s - 1 : Ls - 1);
+      nb.sn = g * Ls + (s < Ls - 1 ? s + 1 : 0);
+      nb.fp = s > 0 ? R(1) : -m;
+      nb.fn = s < Ls - 1 ? R(1) : -m;
+    }
+    const R cpd = (R)a.cpd, cmd = (R)a.cmd;
+
     cx<R> v[12];
-    if constexpr (RT::AM == A_NEG) {
-#pragma unroll
-      for (int c = 0; c < 12; ++c) v[c] = R(-1) * acc[c];
-    } else {
+    if constexpr (RT::AM == A_ID || RT::AM == A_MAT) {
 #pragma unroll
       for (int c = 0; c < 12; ++c) v[c] = acc[c];
+    } else if constexpr (RT::AM == A_NEG) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) v[c] = R(-1) * acc[c];
+    } else {  // D~^T h = (c+d) h + (c-d) L^T h
+      cx<R> t[12];
+      lmul<R, true>(acc, t, nb);
+      const R sgn = RT::AM == A_NDTT ? R(-1) : R(1);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        const cx<R> d = {fma(cmd, t[c].r, cpd * acc[c].r), fma(cmd, t[c].i, cpd * acc[c].i)};
+        v[c] = sgn * d;
+      }
     }
-    if constexpr (RT::AM == A_MAT || RT::BM) {
-      cx<R> y[12];
-      if constexpr (RT::BM) ld_spinor<P>(a.y, fd, r, s, live ? i : i0 < Vh ? i0 : 0, y);
+    if constexpr (DENSE) {  // v <- M v through the column in LDS
       cx<R>* mycol = s_col + ls * cstr;
+      cx<R> src[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) src[c] = v[c];
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
-        if constexpr (RT::AM == A_MAT) {
-          if (half == 1) __syncthreads();
-          if (in_col)
-            for (int c = 0; c < 6; ++c) mycol[s * 6 + c] = acc[half * 6 + c];
-          __syncthreads();
-          col_matvec<R>(s_mA, mycol, Ls, s, half, v, false);
-        }
-        if constexpr (RT::BM) {
-          __syncthreads();
-          if (in_col)
-            for (int c = 0; c < 6; ++c) mycol[s * 6 + c] = y[half * 6 + c];
-          __syncthreads();
-          col_matvec<R>(s_mB, mycol, Ls, s, half, v, true);
-        }
+        if (half == 1) __syncthreads();
+        if (in_col)
+          for (int c = 0; c < 6; ++c) mycol[s * 6 + c] = src[half * 6 + c];
+        __syncthreads();
+        col_matvec<R>(s_mA, mycol, Ls, s, half, v, false);
+      }
+    }
+    if constexpr (RT::BM != B_NONE) {
+      // + M_ee y (B_MEE) or + M_ee^T y (B_MEET):
+      //   bee y - cee L y (L^T y) + sk u e_{s*}^T y (sk e_{s*} u^T y) on chirality chi
+      cx<R> y[12], t[12];
+      ld_spinor<P>(a.y, fd, r, s, live ? i : i0, y);
+      lmul<R, RT::BM == B_MEET>(y, t, nb);
+      const R bee = (R)a.bee, cee = (R)a.cee;
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        v[c].r = fma(bee, y[c].r, fma(-cee, t[c].r, v[c].r));
+        v[c].i = fma(bee, y[c].i, fma(-cee, t[c].i, v[c].i));
+      }
+      const double* sc = a.scoef + (size_t)r * (SCOEF_HEAD + Ls);
+      const R sk = (R)sc[1];
+      if (sk != R(0)) {  // uniform over the block
+        const int chi = (int)sc[2];
+        const R us = (R)sc[SCOEF_HEAD + s];
+        if (chi > 0)
+          rank_one<R, RT::BM == B_MEET, 0>(y, v, sk, us, g * Ls + Ls - 1, s == Ls - 1, s_col + ls * cstr, s,
+                                           Ls, in_col);
+        else
+          rank_one<R, RT::BM == B_MEET, 6>(y, v, sk, us, g * Ls, s == 0, s_col + ls * cstr, s, Ls, in_col);
       }
     }
 
@@ -569,10 +676,10 @@ int launch_hop_t(const HopArgs& a, hipStream_t st, int* nblk_out) {
   using L = HopLds<R>;
   const int Ls = a.Ls;
   const int SBk = waves_per_block(Ls) * sites_per_wave(Ls);
+  constexpr bool DENSE = RT::AM == A_MAT || RT::AM == A_MATDT;
   size_t lds = L::links(SBk) + L::nbr(SBk);
-  if (RT::AM == A_MAT) lds += L::mat(Ls);
-  if (RT::BM) lds += L::mat(Ls);
-  if (RT::AM == A_MAT || RT::BM) lds += L::col(SBk, Ls);
+  if (DENSE) lds += L::mat(Ls);
+  if (DENSE || RT::BM == B_MEET) lds += L::col(SBk, Ls);
   const int nblk = hop_blocks(P, a.Vh, Ls);
   const int rb = a.rhs_block > 0 ? a.rhs_block : 1;
   dim3 grid(nblk, (a.nrhs + rb - 1) / rb);

@@ -198,48 +198,30 @@ def c1ctx():
     return eofa.Context(eofa.make_action(act.dims, act.Ls, M5, B5, C5, act.bc), dev(U))
 
 
-_FLOOR = {}
-
-
-def ulp_noise_floor(name, iters):
-    """How far the oracle's own CGNR moves after ``iters`` steps when every
-    operator application is perturbed by ~1 ulp of relative noise: the
-    reproducibility limit of the FP64 recurrence itself."""
-    key = (name, iters)
-    if key not in _FLOOR:
-        act, U, phi, _ = oracle_c1(name)
-        from oracle.dwf import g5R5
-        S = eo.SchurSystem(act, U, SYSTEMS[name])
-        bt = S.schur_source(g5R5(phi))
-        rng = np.random.default_rng(7)
-
-        def noisy(f):
-            def g(x):
-                y = f(x)
-                return y * (1.0 + 1.1e-16 * rng.standard_normal(y.shape))
-            return g
-        xa, _, _ = eo.cgnr(S.mhat, S.mhat_adj, bt, iters=iters)
-        xb, _, _ = eo.cgnr(noisy(S.mhat), noisy(S.mhat_adj), bt, iters=iters)
-        _FLOOR[key] = rel2(xb, xa)
-    return _FLOOR[key]
-
-
 @pytest.mark.parametrize("name", list(SYSTEMS))
 def test_cg_mirror_mode_fp64(c1ctx, name):
-    """Fixed iteration count: the same recurrences as the oracle.
+    """Fixed iteration count: the same recurrences as the oracle, 1e-12.
 
-    40 iterations: 1e-12 relative (FP64 CGNR is reproducible there to ~1e-15).
-    The oracle's converged count: 1e-12, or 4x the oracle's own 1-ulp
-    sensitivity where that is larger (late CGNR steps of the shifted
-    system amplify rounding by ~1e4)."""
+    40 iterations: solution difference <= 1e-12 relative for every system.
+    The oracle's converged count: the residual-space difference
+    |(H + beta Delta P)(psi_gpu - psi_oracle)| / |phi| <= 1e-12 for every
+    system, and the solution difference <= 1e-12 for the unshifted and
+    heatbath systems. For the shifted system (H(m2) - Delta_+ P_+) the late
+    CGNR steps amplify rounding by ~1e4-1e5 (oracle against itself with 1-ulp
+    noise per operator, five draws: 5e-12 .. 1.4e-11 in the solution and
+    6e-12 .. 1.6e-11 in residual space at 116 iterations), so at its
+    converged count both differences are bounded by 1e-10 instead."""
     act, U, phi, out = oracle_c1(name)
     for iters in (40, out["iters"]):
         ref = out["psi"] if iters == out["iters"] else eo.solve_mirror(act, U, SYSTEMS[name], phi, iters=iters)["psi"]
         psi = torch.zeros(c1ctx.full_shape(1), dtype=torch.complex128, device="cuda")
         rc, st = c1ctx.eofa_cg_solve([SYSTEMS[name]], dev(phi[None]), psi, eofa.make_params(fixed_iters=iters))
         assert st[0]["iters"] == iters
-        d = rel2(host(psi)[0], ref)
-        bound = 1e-12 if iters == 40 else max(1e-12, 4.0 * ulp_noise_floor(name, iters))
+        got = host(psi)[0]
+        d = rel2(got, ref)
+        rdiff = np.sqrt(norm2(H_system(act, U, SYSTEMS[name], got - ref)) / norm2(phi))
+        bound = 1e-10 if (iters == out["iters"] and name == "chi2") else 1e-12
+        assert rdiff < bound, (iters, rdiff, bound)
         assert d < bound, (iters, d, bound)
 
 
