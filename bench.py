@@ -99,12 +99,96 @@ def cpu_baseline(dims, Ls, eps, m1, gseed, sseed):
                        f"bytes counted with the same compulsory-traffic model as the GPU kernel")
 
 
+def bench_batched(args, eofa, synth, torch, np):
+    """Batched multi-right-hand-side workload: 24^3 x 64, Ls = 12, m1 = 0.01,
+    12 Gaussian right-hand sides (6 on H(m1), 6 on H(m2) - Delta_+(m1,m2) P_+),
+    FP32 inner / FP64 outer. Times (a) one 12-RHS Dslash launch against 12
+    single-RHS launches, (b) a fixed number of batched inner CG iterations
+    (HIP graph, autotuned launch shape) against 12 single-RHS solves."""
+    dims, Ls, eps, m1, m2, nrhs = (24, 24, 24, 64), 12, 0.5, 0.01, 1.0, 12
+    print(f"bench: batched workload dims={dims} Ls={Ls} nrhs={nrhs}", file=sys.stderr, flush=True)
+    U = torch.from_numpy(synth.gauge_field(dims, eps, 1003)).cuda()
+    ctx = eofa.Context(eofa.make_action(dims, Ls, 1.8, 1.5, 0.5), U)
+    phi = synth.fermion_torch(dims, Ls, seed=2003, nrhs=nrhs)
+    Vh = int(np.prod(dims)) // 2
+    Nh = Vh * Ls
+    prec = eofa.FP32
+    sysl = [(m1, m1, m2, 0.0, -1)] * (nrhs // 2) + [(m2, m1, m2, -1.0, +1)] * (nrhs - nrhs // 2)
+    # autotune the launch shape on a short batched solve first; the Dslash
+    # entry point then uses the same tuned shape
+    iters = args.batched_iters
+    psi = torch.zeros_like(phi)
+    prm = eofa.make_params(fixed_iters=iters, inner_prec=prec, use_graph=1, check_every=16)
+    _, st = ctx.eofa_cg_solve(sysl, phi, psi, prm)
+    tuned = (st[0]["waves"], st[0]["rhs_block"])
+    # (a) Dslash: one launch over all right-hand sides vs one launch each
+    pin, pout = ctx.new_packed(prec, nrhs), ctx.new_packed(prec, nrhs)
+    ctx.eofa_pack(phi, pin, 1, prec, nrhs)
+    reps = 10
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ctx.eofa_dslash(sysl, pin, pout, 0, 0, prec, nrhs)
+    ev[0].record()
+    for _ in range(reps):
+        ctx.eofa_dslash(sysl, pin, pout, 0, 0, prec, nrhs)
+    ev[1].record()
+    one_in, one_out = ctx.new_packed(prec, 1), ctx.new_packed(prec, 1)
+    ctx.eofa_pack(phi[:1], one_in, 1, prec, 1)
+    ctx.eofa_dslash(sysl[:1], one_in, one_out, 0, 0, prec, 1)
+    ev[2].record()
+    for _ in range(reps):
+        for r in range(nrhs):
+            ctx.eofa_dslash(sysl[r:r + 1], one_in, one_out, 0, 0, prec, 1)
+    ev[3].record()
+    torch.cuda.synchronize()
+    t_multi = ev[0].elapsed_time(ev[1]) / reps * 1e-3
+    t_single = ev[2].elapsed_time(ev[3]) / reps * 1e-3
+    alg = (2 * site_bytes(prec) * Nh * nrhs + link_bytes_per_site(prec) * Vh)
+    alg1 = (2 * site_bytes(prec) * Nh + link_bytes_per_site(prec) * Vh) * nrhs
+    del pin, pout
+    # (b) batched inner iterations
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rc, st = ctx.eofa_cg_solve(sysl, phi, psi, prm)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / args.steps
+    ph1, ps1 = phi[:1].clone(), torch.zeros_like(phi[:1])
+    ctx.eofa_cg_solve(sysl[:1], ph1, ps1, prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(nrhs):
+        ph1.copy_(phi[r:r + 1])
+        ctx.eofa_cg_solve(sysl[r:r + 1], ph1, ps1, prm)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    out = {
+        "metric": METRIC, "value": round(alg / t_multi / 1e9, 1), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": round(t_batch * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{dims[0]}x{dims[1]}x{dims[2]}x{dims[3]} Ls={Ls} m1={m1} m2={m2}, {nrhs} Gaussian RHS "
+                               f"(6 on H(m1), 6 on H(m2)-Delta_+P_+), FP32 inner, {iters} batched CG iterations "
+                               f"per step in a HIP graph", "lattice": list(dims), "Ls": Ls, "nrhs": nrhs},
+        "dslash_multi_rhs": {"seconds_per_launch": t_multi, "algorithmic_GBs": round(alg / t_multi / 1e9, 1),
+                             "frac_hbm": round(alg / t_multi / 1e9 / HBM_PEAK_GBS, 4),
+                             "single_rhs_launches_seconds": t_single,
+                             "single_rhs_algorithmic_GBs": round(alg1 / t_single / 1e9, 1),
+                             "speedup_one_launch_vs_12": round(t_single / t_multi, 3),
+                             "tuned_waves_rhs_block": list(tuned)},
+        "batched_cg": {"iters": iters, "seconds_batched": t_batch, "seconds_12_single": t_seq,
+                       "speedup": round(t_seq / t_batch, 3),
+                       "per_rhs_iteration_ms": round(t_batch / nrhs / iters * 1e3, 4)},
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["batched"])
+    ap.add_argument("--batched-iters", type=int, default=64)
     ap.add_argument("--inner", default="fp16s", choices=sorted(PREC))
     ap.add_argument("--inner-tol", type=float, default=0.0)
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 reference solve")
@@ -130,6 +214,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         print("bench: calibration copy done (3 x 1 GiB device-to-device)", file=sys.stderr, flush=True)
+
+    if args.workload == "batched":
+        bench_batched(args, eofa, synth, torch, np)
+        return
 
     dims, Ls, eps, m1, gseed, sseed = WORKLOADS[args.workload]
     m2 = 1.0

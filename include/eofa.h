@@ -112,7 +112,12 @@ typedef struct {
                           0 = automatic floor (0 for FP64 inner, 1e-4 otherwise)               */
   int32_t fixed_iters; /* > 0: exactly this many inner iterations in one pass, no early stop   */
   int32_t check_every; /* host convergence poll period in iterations (0 = 16)                 */
-  int32_t profile;     /* 1: time the inner hop kernels with HIP events (stats.hop_ms)        */
+  int32_t profile;     /* 1: time the inner hop kernels with HIP events (stats.hop_ms);
+                          ignored when use_graph = 1                                          */
+  int32_t use_graph;   /* 1: capture check_every inner iterations in a HIP graph and replay it */
+  int32_t rhs_block;   /* right-hand sides per work-group in the hop kernels (links staged once
+                          per work-group serve all of them); 0 = autotune                     */
+  int32_t waves;       /* waves per work-group in the hop kernels (1, 2, 4); 0 = autotune     */
 } eofa_solver_params;
 
 typedef struct {
@@ -126,6 +131,8 @@ typedef struct {
                            hop kernels: [0] M_ee^-1 Dhop D~, [1] M_ee - Dhop D~,
                            [2] M_ee^-T D~^T Dhop^dag, [3] residual update       */
   int32_t hop_timed;    /* profile=1: inner iterations whose kernels were timed */
+  int32_t waves;        /* launch shape the inner hop kernels used: waves and   */
+  int32_t rhs_block;    /* right-hand sides per work-group (autotuned or given) */
   int32_t pad;
 } eofa_solver_stats;
 

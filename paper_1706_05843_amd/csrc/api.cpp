@@ -80,6 +80,10 @@ struct eofa_ctx {
   double* host_stage = nullptr;  // pinned
   size_t host_stage_n = 0;
   std::vector<hipEvent_t> events;
+  // autotuned (waves per work-group, right-hand sides per work-group) of the
+  // inner hop kernels, keyed by precision * 4096 + nrhs
+  std::map<int, std::pair<int, int>> tuned;
+  hipStream_t cap_stream = nullptr;  // non-blocking stream for HIP graph capture
 };
 
 namespace {
@@ -194,6 +198,12 @@ HopArgs base_args(eofa_ctx* C, int prec, int out_parity, int nrhs) {
   a.Ls = C->g.Ls;
   a.nrhs = nrhs;
   a.rhs_block = nrhs;
+  a.W = default_waves(C->g.Ls);
+  auto it = C->tuned.find(prec * 4096 + nrhs);
+  if (it != C->tuned.end()) {
+    a.W = it->second.first;
+    a.rhs_block = it->second.second;
+  }
   return a;
 }
 
@@ -283,6 +293,7 @@ int eofa_destroy(eofa_ctx* C) {
   if (C->mats) (void)hipFree(C->mats);
   if (C->host_stage) (void)hipHostFree(C->host_stage);
   for (auto ev : C->events) (void)hipEventDestroy(ev);
+  if (C->cap_stream) (void)hipStreamDestroy(C->cap_stream);
   delete C;
   return EOFA_OK;
 }
@@ -421,6 +432,79 @@ int put(eofa_ctx* C, void* dev, const void* host, size_t bytes, hipStream_t st) 
   return EOFA_OK;
 }
 
+// One inner CGNR iteration: K1, K2, alpha, K3, K4, beta, x/p update.
+int inner_iteration(eofa_ctx* C, int S, int PR, const HopArgs& k1, const HopArgs& k2, const HopArgs& k3,
+                    const HopArgs& k4, int nbh, int nrhs, CgState Sst, double* partial, void* xin, void* rin,
+                    void* pS, hipStream_t st, hipEvent_t* ev) {
+  const Geometry& g = C->g;
+  if (ev) HIPCHK(hipEventRecord(ev[0], st));
+  CHK(hop(C, S, ROLE_K1, k1, st));
+  if (ev) HIPCHK(hipEventRecord(ev[1], st));
+  if (ev) HIPCHK(hipEventRecord(ev[2], st));
+  CHK(hop(C, S, ROLE_K2, k2, st));
+  if (ev) HIPCHK(hipEventRecord(ev[3], st));
+  launch_finalize(FIN_ALPHA, partial, nbh, nrhs, Sst, nullptr, st);
+  if (ev) HIPCHK(hipEventRecord(ev[4], st));
+  CHK(hop(C, S, ROLE_K3, k3, st));
+  if (ev) HIPCHK(hipEventRecord(ev[5], st));
+  if (ev) HIPCHK(hipEventRecord(ev[6], st));
+  CHK(hop(C, S, ROLE_K4, k4, st));
+  if (ev) HIPCHK(hipEventRecord(ev[7], st));
+  launch_finalize(FIN_BETA, partial, nbh, nrhs, Sst, nullptr, st);
+  launch_cg_update(S, PR, g, xin, rin, pS, Sst.alpha, Sst.beta, Sst.u2run, nrhs, st);
+  return EOFA_OK;
+}
+
+// Autotuner: time the four inner hop kernels for each (waves per
+// work-group, right-hand sides per work-group) candidate on the solve's own
+// buffers (halt flags off, before the CG state exists) and keep the fastest.
+int autotune(eofa_ctx* C, int S, int nrhs, HopArgs k1, HopArgs k2, HopArgs k3, HopArgs k4, hipStream_t st) {
+  const int key = S * 4096 + nrhs;
+  if (C->tuned.count(key)) return EOFA_OK;
+  const int Ls = C->g.Ls;
+  std::vector<int> waves, blocks;
+  for (int w : {1, 2, 4}) {
+    bool fits = true;
+    for (int role : {ROLE_K1, ROLE_K2, ROLE_K3, ROLE_K4})
+      fits = fits && hop_lds_bytes(S, role, Ls, w) <= 65536;
+    if (fits) waves.push_back(w);
+  }
+  for (int rb = 1; rb <= nrhs; ++rb)
+    if (rb == nrhs || (nrhs + rb - 1) / rb != (nrhs + rb) / (rb + 1)) blocks.push_back(rb);
+  if (waves.empty()) waves.push_back(default_waves(Ls));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  double best = 1e30;
+  std::pair<int, int> pick(default_waves(Ls), nrhs);
+  for (int w : waves)
+    for (int rb : blocks) {
+      HopArgs a[4] = {k1, k2, k3, k4};
+      for (auto& x : a) {
+        x.W = w;
+        x.rhs_block = rb;
+        x.halt = nullptr;
+      }
+      const int roles[4] = {ROLE_K1, ROLE_K2, ROLE_K3, ROLE_K4};
+      for (int k = 0; k < 4; ++k) CHK(hop(C, S, roles[k], a[k], st));  // warm-up
+      HIPCHK(hipEventRecord(e0, st));
+      for (int rep = 0; rep < 2; ++rep)
+        for (int k = 0; k < 4; ++k) CHK(hop(C, S, roles[k], a[k], st));
+      HIPCHK(hipEventRecord(e1, st));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        pick = {w, rb};
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  C->tuned[key] = pick;
+  return EOFA_OK;
+}
+
 int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, void* psi,
                 const eofa_solver_params* prm, eofa_solver_stats* stats, hipStream_t st) {
   const double t0 = now_s();
@@ -452,7 +536,7 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
   CHK(ws(C, "wS", bS, &wS));
   CHK(ws(C, "rin", bR, &rin));
   CHK(ws(C, "xin", bR, &xin));
-  const int maxblk = std::max(hop_blocks(P64, g.Vh, g.Ls), std::max(hop_blocks(P32, g.Vh, g.Ls), (g.Ls * g.Vh + 255) / 256));
+  const int maxblk = std::max(hop_blocks(P64, g.Vh, g.Ls, 1), (g.Ls * g.Vh + 255) / 256);  // W = 1 has the most blocks
   CHK(ws(C, "partial", sizeof(double) * (size_t)maxblk * nrhs, &partial_v));
   double* partial = (double*)partial_v;
   CgState Sst;
@@ -494,6 +578,41 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
   if (prm->profile && C->events.empty()) {
     C->events.resize(8 * max_timed);
     for (auto& ev : C->events) HIPCHK(hipEventCreate(&ev));
+  }
+
+  HopArgs k1 = base_args(C, S, 0, nrhs);
+  k1.in = pS;
+  k1.out = tS;
+  k1.matA = MAT_MEE_INV;
+  k1.halt = Sst.halt;
+  HopArgs k2 = base_args(C, S, 1, nrhs);
+  k2.in = tS;
+  k2.y = pS;
+  k2.out = wS;
+  k2.matB = MAT_MEE;
+  k2.partial = partial;
+  k2.halt = Sst.halt;
+  HopArgs k3 = base_args(C, S, 0, nrhs);
+  k3.in = wS;
+  k3.out = tS;
+  k3.matA = MAT_MEE_INV_T;
+  k3.halt = Sst.halt;
+  HopArgs k4 = base_args(C, S, 1, nrhs);
+  k4.in = tS;
+  k4.y = wS;
+  k4.r = rin;
+  k4.matA = MAT_NEG_DT_T;
+  k4.matB = MAT_MEE_T;
+  k4.alpha = Sst.alpha;
+  k4.partial = partial;
+  k4.halt = Sst.halt;
+  if (prm->rhs_block <= 0 && prm->waves <= 0) {
+    CHK(autotune(C, S, nrhs, k1, k2, k3, k4, st));
+    const auto pick = C->tuned[S * 4096 + nrhs];
+    for (HopArgs* x : {&k1, &k2, &k3, &k4}) {
+      x->W = pick.first;
+      x->rhs_block = pick.second;
+    }
   }
 
   for (int outer = 0; outer < max_outer; ++outer) {
@@ -572,61 +691,70 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
     launch_convert(PR, S, g, rin, pS, nrhs, st);
     launch_zero(PR, g, xin, nrhs, st);
 
-    HopArgs k1 = base_args(C, S, 0, nrhs);
-    k1.in = pS;
-    k1.out = tS;
-    k1.matA = MAT_MEE_INV;
-    k1.halt = Sst.halt;
-    HopArgs k2 = base_args(C, S, 1, nrhs);
-    k2.in = tS;
-    k2.y = pS;
-    k2.out = wS;
-    k2.matB = MAT_MEE;
-    k2.partial = partial;
-    k2.halt = Sst.halt;
-    HopArgs k3 = base_args(C, S, 0, nrhs);
-    k3.in = wS;
-    k3.out = tS;
-    k3.matA = MAT_MEE_INV_T;
-    k3.halt = Sst.halt;
-    HopArgs k4 = base_args(C, S, 1, nrhs);
-    k4.in = tS;
-    k4.y = wS;
-    k4.r = rin;
-    k4.matA = MAT_NEG_DT_T;
-    k4.matB = MAT_MEE_T;
-    k4.alpha = Sst.alpha;
-    k4.partial = partial;
-    k4.halt = Sst.halt;
-    const int nbh = hop_blocks(S, g.Vh, g.Ls);
+    if (prm->rhs_block > 0 || prm->waves > 0) {
+      const int w = prm->waves > 0 ? prm->waves : default_waves(g.Ls);
+      const int rb = prm->rhs_block > 0 ? std::min(prm->rhs_block, nrhs) : nrhs;
+      for (HopArgs* x : {&k1, &k2, &k3, &k4}) {
+        x->W = w;
+        x->rhs_block = rb;
+      }
+    }
+    const int nbh = hop_blocks(S, g.Vh, g.Ls, k1.W);
 
     int it = 0;
     const int cap = fixed ? prm->fixed_iters : prm->max_iter + 1;
-    while (true) {
-      const bool prof = prm->profile && timed < max_timed && (it % 8 == 0);
-      hipEvent_t* ev = prof ? &C->events[timed * 8] : nullptr;
-      if (prof) HIPCHK(hipEventRecord(ev[0], st));
-      CHK(hop(C, S, ROLE_K1, k1, st));
-      if (prof) HIPCHK(hipEventRecord(ev[1], st));
-      if (prof) HIPCHK(hipEventRecord(ev[2], st));
-      CHK(hop(C, S, ROLE_K2, k2, st));
-      if (prof) HIPCHK(hipEventRecord(ev[3], st));
-      launch_finalize(FIN_ALPHA, partial, nbh, nrhs, Sst, nullptr, st);
-      if (prof) HIPCHK(hipEventRecord(ev[4], st));
-      CHK(hop(C, S, ROLE_K3, k3, st));
-      if (prof) HIPCHK(hipEventRecord(ev[5], st));
-      if (prof) HIPCHK(hipEventRecord(ev[6], st));
-      CHK(hop(C, S, ROLE_K4, k4, st));
-      if (prof) HIPCHK(hipEventRecord(ev[7], st));
-      launch_finalize(FIN_BETA, partial, nbh, nrhs, Sst, nullptr, st);
-      launch_cg_update(S, PR, g, xin, rin, pS, Sst.alpha, Sst.beta, Sst.u2run, nrhs, st);
-      if (prof) ++timed;
-      ++it;
-      if (it % check == 0 || it >= cap) {
-        CHK(fetch(C, Sst.halt, nrhs * sizeof(int), hbuf.data(), st));
+    if (prm->use_graph) {
+      // capture check_every iterations once per pass on a non-blocking stream
+      // ordered after the caller's stream, then replay; converged right-hand
+      // sides are skipped inside the kernels through their halt flags
+      if (!C->cap_stream) HIPCHK(hipStreamCreateWithFlags(&C->cap_stream, hipStreamNonBlocking));
+      hipStream_t cs = C->cap_stream;
+      hipEvent_t join;
+      HIPCHK(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+      HIPCHK(hipEventRecord(join, st));
+      HIPCHK(hipStreamWaitEvent(cs, join, 0));
+      hipGraph_t graph;
+      hipGraphExec_t exec;
+      HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      for (int k = 0; k < check; ++k) {
+        const int rc = inner_iteration(C, S, PR, k1, k2, k3, k4, nbh, nrhs, Sst, partial, xin, rin, pS, cs, nullptr);
+        if (rc != EOFA_OK) {
+          hipGraph_t dead;
+          (void)hipStreamEndCapture(cs, &dead);
+          if (dead) (void)hipGraphDestroy(dead);
+          return rc;
+        }
+      }
+      HIPCHK(hipStreamEndCapture(cs, &graph));
+      HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+      while (true) {
+        HIPCHK(hipGraphLaunch(exec, cs));
+        it += check;
+        HIPCHK(hipMemcpyAsync(C->host_stage, Sst.halt, nrhs * sizeof(int), hipMemcpyDeviceToHost, cs));
+        HIPCHK(hipStreamSynchronize(cs));
+        std::memcpy(hbuf.data(), C->host_stage, nrhs * sizeof(int));
         bool stop = true;
         for (int r = 0; r < nrhs; ++r) stop = stop && hbuf[r] != 0;
         if (stop || it >= cap) break;
+      }
+      HIPCHK(hipGraphExecDestroy(exec));
+      HIPCHK(hipGraphDestroy(graph));
+      HIPCHK(hipEventRecord(join, cs));
+      HIPCHK(hipStreamWaitEvent(st, join, 0));
+      HIPCHK(hipEventDestroy(join));
+    } else {
+      while (true) {
+        const bool prof = prm->profile && timed < max_timed && (it % 8 == 0);
+        hipEvent_t* ev = prof ? &C->events[timed * 8] : nullptr;
+        CHK(inner_iteration(C, S, PR, k1, k2, k3, k4, nbh, nrhs, Sst, partial, xin, rin, pS, st, ev));
+        if (prof) ++timed;
+        ++it;
+        if (it % check == 0 || it >= cap) {
+          CHK(fetch(C, Sst.halt, nrhs * sizeof(int), hbuf.data(), st));
+          bool stop = true;
+          for (int r = 0; r < nrhs; ++r) stop = stop && hbuf[r] != 0;
+          if (stop || it >= cap) break;
+        }
       }
     }
     HIPCHK(hipGetLastError());
@@ -710,6 +838,8 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
       o.seconds = t1 - t0;
       for (int k = 0; k < 4; ++k) o.hop_ms[k] = hop_ms[k];
       o.hop_timed = timed;
+      o.waves = k1.W;
+      o.rhs_block = k1.rhs_block;
     }
     if (status[r] != EOFA_OK && (worst == EOFA_OK || status[r] == EOFA_ERR_BREAKDOWN)) worst = status[r];
   }

@@ -98,11 +98,16 @@ struct HopArgs {
   const int* halt;    // may be null
   double* partial;    // [nrhs][gridDim.x]
   int Vh, Ls, nrhs, rhs_block;
+  int W;              // waves per work-group (1, 2 or 4)
 };
 
 // kernel launchers (kernels.hip)
 int launch_hop(int prec, int role, const HopArgs& a, hipStream_t st, int* nblk_out);
-int hop_blocks(int prec, int Vh, int Ls);
+int hop_blocks(int prec, int Vh, int Ls, int W);
+// default waves per work-group for Ls (at most 20 4D sites per work-group)
+int default_waves(int Ls);
+// LDS bytes the hop kernel of this role needs, for the precision and shape
+size_t hop_lds_bytes(int prec, int role, int Ls, int W);
 void launch_pack(int prec, const Geometry& g, const void* full, void* packed, int parity, int nrhs,
                  int g5r5, hipStream_t st);
 void launch_unpack(int prec, const Geometry& g, const void* packed, void* full, int parity, int nrhs,

@@ -232,7 +232,8 @@ constexpr int MAXW = 4;   // most waves per work-group
 // (lane = g * Ls + s); a work-group holds W(Ls) waves, at most 20 4D sites,
 // which bounds the LDS staging of links and columns.
 __host__ __device__ inline int sites_per_wave(int Ls) { return 64 / Ls; }
-__host__ __device__ inline int waves_per_block(int Ls) {
+
+int default_waves(int Ls) {
   const int G = sites_per_wave(Ls);
   return G <= 5 ? MAXW : (16 / G > 1 ? 16 / G : 1);
 }
@@ -482,7 +483,7 @@ hop_kernel(HopArgs a) {
 
   const int Ls = a.Ls, Vh = a.Vh;
   const int G = sites_per_wave(Ls);
-  const int W = waves_per_block(Ls);
+  const int W = a.W;
   const int SBk = W * G;  // 4D sites per work-group
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -663,35 +664,64 @@ constexpr int acc_prec() {
   return P == P64 ? P64 : P32;
 }
 
-int hop_blocks(int prec, int Vh, int Ls) {
+int hop_blocks(int prec, int Vh, int Ls, int W) {
   (void)prec;
-  const int SBk = waves_per_block(Ls) * sites_per_wave(Ls);
+  const int SBk = W * sites_per_wave(Ls);
   return (Vh + SBk - 1) / SBk;
 }
 
 template <int P, int ROLE>
-int launch_hop_t(const HopArgs& a, hipStream_t st, int* nblk_out) {
+size_t hop_lds_t(int Ls, int W) {
   using R = typename ST<P>::R;
   using RT = RoleT<ROLE>;
   using L = HopLds<R>;
-  const int Ls = a.Ls;
-  const int SBk = waves_per_block(Ls) * sites_per_wave(Ls);
+  const int SBk = W * sites_per_wave(Ls);
   constexpr bool DENSE = RT::AM == A_MAT || RT::AM == A_MATDT;
   size_t lds = L::links(SBk) + L::nbr(SBk);
   if (DENSE) lds += L::mat(Ls);
   if (DENSE || RT::BM == B_MEET) lds += L::col(SBk, Ls);
-  const int nblk = hop_blocks(P, a.Vh, Ls);
+  return lds;
+}
+
+template <int P>
+size_t hop_lds_p(int role, int Ls, int W) {
+  switch (role) {
+    case ROLE_DSLASH: return hop_lds_t<P, ROLE_DSLASH>(Ls, W);
+    case ROLE_DSLASH_DAG: return hop_lds_t<P, ROLE_DSLASH_DAG>(Ls, W);
+    case ROLE_K1: return hop_lds_t<P, ROLE_K1>(Ls, W);
+    case ROLE_K2: return hop_lds_t<P, ROLE_K2>(Ls, W);
+    case ROLE_K3: return hop_lds_t<P, ROLE_K3>(Ls, W);
+    case ROLE_K4: return hop_lds_t<P, ROLE_K4>(Ls, W);
+    case ROLE_K4S: return hop_lds_t<P, ROLE_K4S>(Ls, W);
+    case ROLE_SRC: return hop_lds_t<P, ROLE_SRC>(Ls, W);
+    case ROLE_RES: return hop_lds_t<P, ROLE_RES>(Ls, W);
+    case ROLE_FULLRES: return hop_lds_t<P, ROLE_FULLRES>(Ls, W);
+  }
+  return 0;
+}
+
+size_t hop_lds_bytes(int prec, int role, int Ls, int W) {
+  return prec == P64 ? hop_lds_p<P64>(role, Ls, W) : hop_lds_p<P32>(role, Ls, W);
+}
+
+template <int P, int ROLE>
+int launch_hop_t(const HopArgs& a, hipStream_t st, int* nblk_out) {
+  const int Ls = a.Ls;
+  const int W = a.W >= 1 && a.W <= MAXW ? a.W : default_waves(Ls);
+  const size_t lds = hop_lds_t<P, ROLE>(Ls, W);
+  const int nblk = hop_blocks(P, a.Vh, Ls, W);
   const int rb = a.rhs_block > 0 ? a.rhs_block : 1;
   dim3 grid(nblk, (a.nrhs + rb - 1) / rb);
   HopArgs b = a;
   b.rhs_block = rb;
+  b.W = W;
   auto fn = hop_kernel<P, acc_prec<P>(), ROLE>;
   if (lds > 65536) {
     if (hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
         hipSuccess)
       return EOFA_ERR_HIP;
   }
-  hipLaunchKernelGGL(fn, grid, dim3(64 * waves_per_block(Ls)), lds, st, b);
+  hipLaunchKernelGGL(fn, grid, dim3(64 * W), lds, st, b);
   if (nblk_out) *nblk_out = nblk;
   return hipGetLastError() == hipSuccess ? EOFA_OK : EOFA_ERR_HIP;
 }

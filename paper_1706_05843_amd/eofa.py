@@ -39,18 +39,21 @@ class SolverParams(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("max_outer", ctypes.c_int32),
                 ("inner_prec", ctypes.c_int32), ("inner_tol", ctypes.c_double),
                 ("fixed_iters", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("profile", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("rhs_block", ctypes.c_int32),
+                ("waves", ctypes.c_int32)]
 
 
 class SolverStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("outer_iters", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("status", ctypes.c_int32), ("true_resid", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("hop_ms", ctypes.c_double * 4), ("hop_timed", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("hop_ms", ctypes.c_double * 4), ("hop_timed", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("rhs_block", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
     def as_dict(self):
         return dict(iters=self.iters, outer_iters=self.outer_iters, converged=self.converged,
                     status=self.status, true_resid=self.true_resid, seconds=self.seconds,
-                    hop_ms=list(self.hop_ms), hop_timed=self.hop_timed)
+                    hop_ms=list(self.hop_ms), hop_timed=self.hop_timed, waves=self.waves,
+                    rhs_block=self.rhs_block)
 
 
 _LIB = None
@@ -126,10 +129,11 @@ def make_systems(systems):
 
 
 def make_params(tol=1e-10, max_iter=100000, max_outer=20, inner_prec=FP64, inner_tol=0.0,
-                fixed_iters=0, check_every=16, profile=0):
+                fixed_iters=0, check_every=16, profile=0, use_graph=0, rhs_block=0, waves=0):
     p = SolverParams()
     p.tol, p.max_iter, p.max_outer, p.inner_prec = tol, max_iter, max_outer, inner_prec
     p.inner_tol, p.fixed_iters, p.check_every, p.profile = inner_tol, fixed_iters, check_every, profile
+    p.use_graph, p.rhs_block, p.waves = use_graph, rhs_block, waves
     return p
 
 

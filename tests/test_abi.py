@@ -44,7 +44,7 @@ def test_struct_layout_matches_c():
 #include "eofa.h"
 int main(void) {
   printf("%zu %zu %zu %zu\n", sizeof(eofa_action), sizeof(eofa_system), sizeof(eofa_solver_params), sizeof(eofa_solver_stats));
-  printf("%zu %zu %zu %zu\n", offsetof(eofa_action, M5), offsetof(eofa_action, bc), offsetof(eofa_solver_params, inner_tol), offsetof(eofa_solver_stats, hop_ms));
+  printf("%zu %zu %zu %zu %zu\n", offsetof(eofa_action, M5), offsetof(eofa_action, bc), offsetof(eofa_solver_params, inner_tol), offsetof(eofa_solver_stats, hop_ms), offsetof(eofa_solver_params, waves));
   return 0;
 }
 '''
@@ -58,7 +58,8 @@ int main(void) {
     assert sizes[:4] == [ctypes.sizeof(eofa.Action), ctypes.sizeof(eofa.System),
                          ctypes.sizeof(eofa.SolverParams), ctypes.sizeof(eofa.SolverStats)]
     assert sizes[4:] == [eofa.Action.M5.offset, eofa.Action.bc.offset,
-                         eofa.SolverParams.inner_tol.offset, eofa.SolverStats.hop_ms.offset]
+                         eofa.SolverParams.inner_tol.offset, eofa.SolverStats.hop_ms.offset,
+                         eofa.SolverParams.waves.offset]
 
 
 @pytest.mark.parametrize("bad", [
