@@ -84,6 +84,7 @@ typedef enum {
 typedef enum { EOFA_FP64 = 0, EOFA_FP32 = 1, EOFA_FP16S = 2 } eofa_prec;
 
 typedef struct eofa_ctx eofa_ctx;
+typedef struct eofa_net eofa_net;
 
 /* Mobius domain-wall action (Sec. II, eqn Ddwf; Table "ensembles" for bc). */
 typedef struct {
@@ -118,6 +119,11 @@ typedef struct {
   int32_t rhs_block;   /* right-hand sides per work-group in the hop kernels (links staged once
                           per work-group serve all of them); 0 = autotune                     */
   int32_t waves;       /* waves per work-group in the hop kernels (1, 2, 4); 0 = autotune     */
+  int32_t precond;     /* 0: CGNR as above; 1: flexible CG on the normal equations in FP64 with
+                          the learned preconditioner `net` (NULL = identity), one right-hand
+                          side at a time, falling back to CGNR on breakdown or stagnation     */
+  int32_t pad0;
+  const eofa_net* net; /* precond = 1: network (eofa_net_create), evaluated in FP32             */
 } eofa_solver_params;
 
 typedef struct {
@@ -133,7 +139,7 @@ typedef struct {
   int32_t hop_timed;    /* profile=1: inner iterations whose kernels were timed */
   int32_t waves;        /* launch shape the inner hop kernels used: waves and   */
   int32_t rhs_block;    /* right-hand sides per work-group (autotuned or given) */
-  int32_t pad;
+  int32_t fell_back;    /* precond = 1: 1 if the solve fell back to CGNR        */
 } eofa_solver_stats;
 
 /* Create a context: validates the action, packs the gauge field (device
@@ -192,6 +198,59 @@ int eofa_cg_solve(eofa_ctx* ctx, const eofa_system* sys, const void* phi, void* 
 int eofa_heatbath_solve(eofa_ctx* ctx, double m1, double m2, int32_t n_poles, const double* alpha,
                         const double* beta, const void* eta, void* phi,
                         const eofa_solver_params* params, eofa_solver_stats* stats, void* stream);
+
+/* Training pairs for the learned preconditioner (not in the paper). Runs
+ * FP64 CG on the normal equations A x = M^dag b~ (A = M^dag M, odd Schur
+ * system of sys, one right-hand side phi in the canonical layout) from
+ * x = 0, records at iterations k = first, first+stride, ... the residual
+ * r_k = M^dag b~ - A x_k and the error e_k = x* - x_k, where x* is the same
+ * CG continued to |r| <= tol |r_0| (x_k is kept in FP64 until x* is known).
+ * r_out, e_out: device, npairs consecutive packed FP32 odd half-fields
+ * (eofa_packed_bytes(ctx, EOFA_FP32, 1) bytes each). *recorded (host) is
+ * the number of pairs written (fewer than npairs if CG converges first);
+ * *iters (host, may be NULL) the CG iterations to x*.
+ * EOFA_ERR_NOT_CONVERGED if max_iter iterations do not reach tol.        */
+int eofa_cg_pairs(eofa_ctx* ctx, const eofa_system* sys, const void* phi, int32_t npairs, int32_t first,
+                  int32_t stride, double tol, int32_t max_iter, void* r_out, void* e_out, int32_t* recorded,
+                  int32_t* iters, void* stream);
+
+/* Learned preconditioner (not in the paper): a stack of n_layers gauge-
+ * covariant parallel-transport layers with channels channels[0..n_layers]
+ * (channels[0] = channels[n_layers] = 1, each 1..8). Layer l maps C_in to
+ * C_out channels on every s-slice of the full lattice:
+ *   y_c(x) = sum_c' W[0][c][c'] X_c'(x) + sum_mu W[1+mu][c][c'] U_mu(x) X_c'(x+mu)
+ *          + sum_mu W[5+mu][c][c'] U_mu(x-mu)^dag X_c'(x-mu)
+ * (fermion boundary phases on edge hops), W complex scalars, so spin is
+ * untouched and colour is parallel transported. The input is an odd
+ * packed FP32 half-field embedded with zero even sites; the output is the
+ * odd half of the last layer. Weights: FP32 master copy (Adam state beside
+ * it), used as bfloat16 in the kernels, FP32 arithmetic. Weights are
+ * stored layer by layer as W[9][C_out][C_in] complex (re, im).
+ * A network holds device memory only; it may be used with any context
+ * whose lattice matches the one it was last applied on (buffers are
+ * resized otherwise). Initial weights: N(0, s^2) real and imaginary parts,
+ * s = init_scale / sqrt(9 C_in), from `seed`.                            */
+int eofa_net_create(eofa_ctx* ctx, int32_t n_layers, const int32_t* channels, uint64_t seed,
+                    double init_scale, eofa_net** out);
+int eofa_net_destroy(eofa_net* net);
+/* complex weights in total; get/set exchange 2 * that many doubles (host) */
+size_t eofa_net_num_weights(const eofa_net* net);
+int eofa_net_get_weights(const eofa_net* net, double* out);
+int eofa_net_set_weights(eofa_net* net, const double* in); /* also resets Adam */
+/* out = N(in): packed FP32 odd half-fields (one right-hand side), no alias */
+int eofa_net_apply(eofa_ctx* ctx, eofa_net* net, const void* in, void* out, void* stream);
+/* Loss sum_p |N(r_p) - e_p|^2 / |e_p|^2 over npairs consecutive packed FP32
+ * odd half-fields r, e (device), and its gradient dL/dW* (Wirtinger; the
+ * gradient in (Re W, Im W) is twice its real and imaginary parts) as
+ * host grad[2 * num_weights] (may be NULL); loss: host (may be NULL).     */
+int eofa_net_loss_grad(eofa_ctx* ctx, eofa_net* net, const void* r, const void* e, int32_t npairs,
+                       double* loss, double* grad, void* stream);
+/* Adam training (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on the
+ * pairs, in order, in mini-batches of `batch`; one step per mini-batch on
+ * the batch-mean loss. loss_per_epoch: host [epochs] mean loss per pair over
+ * the epoch, measured during it (may be NULL).                          */
+int eofa_net_train(eofa_ctx* ctx, eofa_net* net, const void* r, const void* e, int32_t npairs,
+                   int32_t epochs, int32_t batch, double lr, double* loss_per_epoch, void* stream);
 
 /* Host only (no device work): the fifth-dimension matrix `mat` that the
  * library builds for one system, as out[2][Ls][Ls] (row-major; [0] acts on

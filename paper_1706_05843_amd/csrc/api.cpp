@@ -34,6 +34,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "nn_internal.h"
 
 using namespace eofa;
 
@@ -58,33 +59,9 @@ int fail(int code, const std::string& msg) {
     if (c_ != EOFA_OK) return c_; \
   } while (0)
 
-struct Buf {
-  void* p = nullptr;
-  size_t n = 0;
-};
-
 }  // namespace
 
-struct eofa_ctx {
-  Geometry g;
-  double M5, b5, c5, c, d;
-  int bc[4];
-  int device;
-  void* links[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
-  int* nbr[2] = {nullptr, nullptr};
-  std::map<std::string, Buf> pool;
-  // fifth-dimension matrices of the last systems uploaded
-  std::vector<double> sys_key;
-  double* mats = nullptr;  // [nrhs][NMAT][2][Ls][Ls] then mop[nrhs]
-  size_t mats_n = 0;
-  double* host_stage = nullptr;  // pinned
-  size_t host_stage_n = 0;
-  std::vector<hipEvent_t> events;
-  // autotuned (waves per work-group, right-hand sides per work-group) of the
-  // inner hop kernels, keyed by precision * 4096 + nrhs
-  std::map<int, std::pair<int, int>> tuned;
-  hipStream_t cap_stream = nullptr;  // non-blocking stream for HIP graph capture
-};
+int eofa::set_error(int code, const std::string& msg) { return fail(code, msg); }
 
 namespace {
 
@@ -505,6 +482,58 @@ int autotune(eofa_ctx* C, int S, int nrhs, HopArgs k1, HopArgs k2, HopArgs k3, H
   return EOFA_OK;
 }
 
+// psi'_e = M_ee^-1 (b_e - Dhop D~ x_o), the FP64 true residual of the
+// Cayley system per parity (re, rodd: |.|^2 per rhs), psi = D~ psi' unpacked
+// to the canonical layout. Overwrites te, tmp, ro; synchronises.
+int reconstruct(eofa_ctx* C, int nrhs, void* x, void* be, void* bo, void* te, void* tmp, void* ro,
+                double* partial, CgState Sst, void* psi, std::vector<double>& re, std::vector<double>& rodd,
+                hipStream_t st) {
+  const Geometry& g = C->g;
+  re.assign(nrhs, 0.0);
+  rodd.assign(nrhs, 0.0);
+  // reconstruct psi'_e = M_ee^-1 (b_e - Dhop D~ x_o)
+  {
+    HopArgs a = base_args(C, P64, 0, nrhs);
+    a.in = x;
+    a.z = be;
+    a.out = tmp;
+    CHK(hop(C, P64, ROLE_SRC, a, st));
+  }
+  launch_smat(P64, g, tmp, te, C->mats, MAT_MEE_INV, nrhs, st);
+  // FP64 true residual of the Cayley system on both parities
+  {
+    HopArgs a = base_args(C, P64, 0, nrhs);
+    a.in = x;
+    a.y = te;
+    a.z = be;
+    a.out = tmp;
+    a.matB = MAT_MEE;
+    a.partial = partial;
+    int nb = 0;
+    CHK(hop(C, P64, ROLE_FULLRES, a, st, &nb));
+    launch_finalize(FIN_NORM, partial, nb, nrhs, Sst, Sst.norm, st);
+    CHK(fetch(C, Sst.norm, nrhs * sizeof(double), re.data(), st));
+    HopArgs b = base_args(C, P64, 1, nrhs);
+    b.in = te;
+    b.y = x;
+    b.z = bo;
+    b.out = ro;
+    b.matB = MAT_MEE;
+    b.partial = partial;
+    CHK(hop(C, P64, ROLE_FULLRES, b, st, &nb));
+    launch_finalize(FIN_NORM, partial, nb, nrhs, Sst, Sst.norm, st);
+    CHK(fetch(C, Sst.norm, nrhs * sizeof(double), rodd.data(), st));
+  }
+  // psi = D~ psi'
+  launch_smat(P64, g, te, tmp, C->mats, MAT_DT, nrhs, st);
+  launch_unpack(P64, g, tmp, psi, 0, nrhs, st);
+  launch_smat(P64, g, x, ro, C->mats, MAT_DT, nrhs, st);
+  launch_unpack(P64, g, ro, psi, 1, nrhs, st);
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+  return EOFA_OK;
+}
+
 int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, void* psi,
                 const eofa_solver_params* prm, eofa_solver_stats* stats, hipStream_t st) {
   const double t0 = now_s();
@@ -772,47 +801,8 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
     }
   }
 
-  // reconstruct psi'_e = M_ee^-1 (b_e - Dhop D~ x_o)
-  {
-    HopArgs a = base_args(C, P64, 0, nrhs);
-    a.in = x;
-    a.z = be;
-    a.out = tmp;
-    CHK(hop(C, P64, ROLE_SRC, a, st));
-  }
-  launch_smat(P64, g, tmp, te, C->mats, MAT_MEE_INV, nrhs, st);
-  // FP64 true residual of the Cayley system on both parities
-  std::vector<double> re(nrhs), rodd(nrhs);
-  {
-    HopArgs a = base_args(C, P64, 0, nrhs);
-    a.in = x;
-    a.y = te;
-    a.z = be;
-    a.out = tmp;
-    a.matB = MAT_MEE;
-    a.partial = partial;
-    int nb = 0;
-    CHK(hop(C, P64, ROLE_FULLRES, a, st, &nb));
-    launch_finalize(FIN_NORM, partial, nb, nrhs, Sst, Sst.norm, st);
-    CHK(fetch(C, Sst.norm, nrhs * sizeof(double), re.data(), st));
-    HopArgs b = base_args(C, P64, 1, nrhs);
-    b.in = te;
-    b.y = x;
-    b.z = bo;
-    b.out = ro;
-    b.matB = MAT_MEE;
-    b.partial = partial;
-    CHK(hop(C, P64, ROLE_FULLRES, b, st, &nb));
-    launch_finalize(FIN_NORM, partial, nb, nrhs, Sst, Sst.norm, st);
-    CHK(fetch(C, Sst.norm, nrhs * sizeof(double), rodd.data(), st));
-  }
-  // psi = D~ psi'
-  launch_smat(P64, g, te, tmp, C->mats, MAT_DT, nrhs, st);
-  launch_unpack(P64, g, tmp, psi, 0, nrhs, st);
-  launch_smat(P64, g, x, ro, C->mats, MAT_DT, nrhs, st);
-  launch_unpack(P64, g, ro, psi, 1, nrhs, st);
-  HIPCHK(hipStreamSynchronize(st));
-  HIPCHK(hipGetLastError());
+  std::vector<double> re, rodd;
+  CHK(reconstruct(C, nrhs, x, be, bo, te, tmp, ro, partial, Sst, psi, re, rodd, st));
   const double t1 = now_s();
   for (int j = 0; j < timed; ++j) {  // events are read only after the solve: no mid-solve host stalls
     float ms;
@@ -853,10 +843,336 @@ int check_params(const eofa_solver_params* prm) {
   CHK(check_prec(prm->inner_prec));
   if (prm->fixed_iters <= 0 && !(prm->tol > 0.0)) return fail(EOFA_ERR_INVALID, "tol must be > 0");
   if (prm->fixed_iters <= 0 && prm->max_iter < 1) return fail(EOFA_ERR_INVALID, "max_iter must be >= 1");
+  if (prm->precond != 0 && prm->precond != 1) return fail(EOFA_ERR_INVALID, "precond must be 0 or 1");
+  if (prm->precond == 1 && prm->fixed_iters > 0)
+    return fail(EOFA_ERR_INVALID, "fixed_iters applies to CGNR only (precond = 0)");
   return EOFA_OK;
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// flexible CG on the normal equations (learned preconditioner) and the
+// training-pair generator
+
+namespace {
+
+// Device scalars of the flexible-CG recurrence (doubles), then one int flag.
+enum FgScalar { FG_WW = 0, FG_QZ = 2, FG_PR = 4, FG_ALPHA = 6, FG_BETA = 8, FG_NRM = 10, FG_N = 12 };
+
+// One right-hand side, FP64 throughout, on the odd Schur system:
+//   s = b~ - M^ x (Schur residual), r = M^dag s (normal residual),
+//   z = N(r); p = z - (<A p_old, z>/<p_old, A p_old>) p_old; w = M^ p; q = M^dag w;
+//   alpha = <p, r>/|w|^2; x += alpha p; r -= alpha q; s -= alpha w
+// (Notay's flexible CG with one-term truncation, A = M^dag M).
+struct Fgcg {
+  eofa_ctx* C = nullptr;
+  hipStream_t st = nullptr;
+  void *be, *bo, *bt, *x, *s, *r, *p, *q, *w, *z, *te, *tmp, *r32, *z32;
+  double* partial = nullptr;
+  double* sc = nullptr;
+  int* bad = nullptr;
+  CgState Sst;
+  int n = 0;  // complex numbers in one FP64 odd half-field
+  double bb = 0.0;
+  bool first = true;
+
+  int init(const eofa_system* sys, const void* phi) {
+    const Geometry& g = C->g;
+    CHK(upload_systems(C, sys, 1, st));
+    CHK(stage(C, 1024));
+    const size_t b64 = packed_bytes(P64, g, 1), b32 = packed_bytes(P32, g, 1);
+    const char* names[12] = {"fg_be", "fg_bo", "fg_bt", "fg_x", "fg_s", "fg_r",
+                             "fg_p", "fg_q", "fg_w", "fg_z", "fg_te", "fg_tmp"};
+    void** bufs[12] = {&be, &bo, &bt, &x, &s, &r, &p, &q, &w, &z, &te, &tmp};
+    for (int k = 0; k < 12; ++k) CHK(ws(C, names[k], b64, bufs[k]));
+    CHK(ws(C, "fg_r32", b32, &r32));
+    CHK(ws(C, "fg_z32", b32, &z32));
+    const int maxblk = std::max({hop_blocks(P64, g.Vh, g.Ls, 1), (g.Ls * g.Vh + 255) / 256, 2048});
+    void* pv;
+    CHK(ws(C, "fg_partial", sizeof(double) * 2 * (size_t)maxblk, &pv));
+    partial = (double*)pv;
+    void* sv;
+    CHK(ws(C, "fg_scalars", sizeof(double) * FG_N + 64, &sv));
+    sc = (double*)sv;
+    bad = (int*)(sc + FG_N);
+    CHK(alloc_state(C, 1, Sst));
+    n = (int)(b64 / 16);
+    HIPCHK(hipMemsetAsync(sv, 0, sizeof(double) * FG_N + 64, st));
+    launch_pack(P64, g, phi, be, 0, 1, 1, st);
+    launch_pack(P64, g, phi, bo, 1, 1, 1, st);
+    HIPCHK(hipGetLastError());
+    std::vector<double> ne, no;
+    CHK(norms(C, P64, be, 1, partial, Sst, ne, st));
+    CHK(norms(C, P64, bo, 1, partial, Sst, no, st));
+    bb = ne[0] + no[0];
+    launch_smat(P64, g, be, te, C->mats, MAT_MEE_INV, 1, st);
+    HopArgs a = base_args(C, P64, 1, 1);
+    a.in = te;
+    a.z = bo;
+    a.out = bt;
+    CHK(hop(C, P64, ROLE_SRC, a, st));
+    launch_zero(P64, g, x, 1, st);
+    launch_convert(P64, P64, g, bt, s, 1, st);
+    return normal_residual();
+  }
+
+  // r = M^dag s, |r|^2 -> sc[FG_NRM]; the next iteration starts a new recurrence
+  int normal_residual() {
+    HopArgs a3 = base_args(C, P64, 0, 1);
+    a3.in = s;
+    a3.out = te;
+    a3.matA = MAT_MEE_INV_T;
+    CHK(hop(C, P64, ROLE_K3, a3, st));
+    HopArgs a4 = base_args(C, P64, 1, 1);
+    a4.in = te;
+    a4.y = s;
+    a4.r = r;
+    a4.matA = MAT_NEG_DT_T;
+    a4.matB = MAT_MEE_T;
+    a4.partial = partial;
+    int nb = 0;
+    CHK(hop(C, P64, ROLE_K4S, a4, st, &nb));
+    launch_finalize(FIN_NORM, partial, nb, 1, Sst, sc + FG_NRM, st);
+    first = true;
+    return EOFA_OK;
+  }
+
+  // s = b~ - M^ x recomputed in FP64; returns |s|^2 on the host
+  int true_schur(double* out) {
+    HopArgs a1 = base_args(C, P64, 0, 1);
+    a1.in = x;
+    a1.out = te;
+    a1.matA = MAT_MEE_INV;
+    CHK(hop(C, P64, ROLE_K1, a1, st));
+    HopArgs a2 = base_args(C, P64, 1, 1);
+    a2.in = te;
+    a2.y = x;
+    a2.z = bt;
+    a2.out = s;
+    a2.matB = MAT_MEE;
+    a2.partial = partial;
+    int nb = 0;
+    CHK(hop(C, P64, ROLE_RES, a2, st, &nb));
+    launch_finalize(FIN_NORM, partial, nb, 1, Sst, sc + FG_NRM + 1, st);
+    return fetch(C, sc + FG_NRM + 1, sizeof(double), out, st);
+  }
+
+  int iterate(eofa_net* net) {
+    const Geometry& g = C->g;
+    if (net) {
+      launch_convert(P64, P32, g, r, r32, 1, st);
+      CHK(net_apply_internal(C, net, r32, z32, st));
+      launch_convert(P32, P64, g, z32, z, 1, st);
+    } else {
+      launch_convert(P64, P64, g, r, z, 1, st);
+    }
+    if (first) {
+      launch_convert(P64, P64, g, z, p, 1, st);
+    } else {
+      launch_cdot(n, q, z, partial, sc + FG_QZ, st);
+      launch_fgcg_ratio(sc + FG_QZ, sc + FG_WW, -1.0, sc + FG_BETA, bad, st);
+      launch_cxpby_dev(n, z, sc + FG_BETA, p, st);
+    }
+    first = false;
+    HopArgs k1 = base_args(C, P64, 0, 1);
+    k1.in = p;
+    k1.out = te;
+    k1.matA = MAT_MEE_INV;
+    CHK(hop(C, P64, ROLE_K1, k1, st));
+    HopArgs k2 = base_args(C, P64, 1, 1);
+    k2.in = te;
+    k2.y = p;
+    k2.out = w;
+    k2.matB = MAT_MEE;
+    k2.partial = partial;
+    int nb = 0;
+    CHK(hop(C, P64, ROLE_K2, k2, st, &nb));
+    launch_finalize(FIN_NORM, partial, nb, 1, Sst, sc + FG_WW, st);
+    HopArgs k3 = base_args(C, P64, 0, 1);
+    k3.in = w;
+    k3.out = te;
+    k3.matA = MAT_MEE_INV_T;
+    CHK(hop(C, P64, ROLE_K3, k3, st));
+    HopArgs k4 = base_args(C, P64, 1, 1);
+    k4.in = te;
+    k4.y = w;
+    k4.r = q;
+    k4.matA = MAT_NEG_DT_T;
+    k4.matB = MAT_MEE_T;
+    k4.partial = partial;
+    CHK(hop(C, P64, ROLE_K4S, k4, st, &nb));
+    launch_cdot(n, p, r, partial, sc + FG_PR, st);
+    launch_fgcg_ratio(sc + FG_PR, sc + FG_WW, 1.0, sc + FG_ALPHA, bad, st);
+    nb = launch_fgcg_update(n, sc + FG_ALPHA, x, r, s, p, q, w, partial, st);
+    launch_finalize(FIN_NORM, partial, nb, 2, Sst, sc + FG_NRM, st);
+    HIPCHK(hipGetLastError());
+    return EOFA_OK;
+  }
+
+  // host read of |r|^2, |s|^2 and the breakdown flag
+  int poll(double* rr, double* ss, int* flag) {
+    double h[FG_N + 8];
+    CHK(fetch(C, sc, sizeof(double) * FG_N + sizeof(int), h, st));
+    *rr = h[FG_NRM];
+    *ss = h[FG_NRM + 1];
+    std::memcpy(flag, h + FG_N, sizeof(int));
+    return EOFA_OK;
+  }
+};
+
+int fgcg_one(eofa_ctx* C, const eofa_system* sys, const void* phi, void* psi, const eofa_solver_params* prm,
+             eofa_solver_stats* out, hipStream_t st) {
+  const double t0 = now_s();
+  eofa_net* net = const_cast<eofa_net*>(prm->net);
+  Fgcg F;
+  F.C = C;
+  F.st = st;
+  CHK(F.init(sys, phi));
+  const int check = prm->check_every > 0 ? prm->check_every : 16;
+  const int max_restart = std::max(1, prm->max_outer);
+  const int stall = std::max(256, 16 * check);  // iterations without a 0.7x gain in |s| before falling back
+  int status = EOFA_OK, it = 0, restarts = 0;
+  bool fallback = !std::isfinite(F.bb);
+  bool converged = false;
+  double best = INFINITY;
+  int best_it = 0;
+  if (F.bb == 0.0) converged = true;
+  while (!fallback && !converged) {
+    CHK(F.iterate(net));
+    ++it;
+    if (it % check != 0 && it < prm->max_iter) continue;
+    double rr, ss;
+    int flag;
+    CHK(F.poll(&rr, &ss, &flag));
+    const double res = std::sqrt(ss / F.bb);
+    if (flag || !std::isfinite(res) || !std::isfinite(rr)) {
+      fallback = true;
+      break;
+    }
+    if (res < 0.7 * best) {
+      best = res;
+      best_it = it;
+    }
+    if (res <= 0.5 * prm->tol || it >= prm->max_iter) {
+      double st2;
+      CHK(F.true_schur(&st2));
+      const double tres = std::sqrt(st2 / F.bb);
+      if (tres <= prm->tol) {
+        converged = true;
+        break;
+      }
+      if (it >= prm->max_iter) {
+        status = EOFA_ERR_NOT_CONVERGED;
+        break;
+      }
+      if (++restarts >= max_restart) {
+        fallback = true;
+        break;
+      }
+      CHK(F.normal_residual());  // restart from the true residual
+      best = tres;
+      best_it = it;
+      continue;
+    }
+    if (it - best_it >= stall) fallback = true;
+  }
+  if (fallback) {
+    eofa_solver_params p2 = *prm;
+    p2.precond = 0;
+    p2.net = nullptr;
+    p2.max_iter = std::max(1, prm->max_iter - it);
+    const int rc = solve_batch(C, sys, 1, phi, psi, &p2, out, st);
+    if (out) {
+      out->fell_back = 1;
+      out->iters += it;
+      out->seconds = now_s() - t0;
+    }
+    return rc;
+  }
+  std::vector<double> re, rodd;
+  CHK(reconstruct(C, 1, F.x, F.be, F.bo, F.te, F.tmp, F.s, F.partial, F.Sst, psi, re, rodd, st));
+  const double tr = F.bb > 0 ? std::sqrt((re[0] + rodd[0]) / F.bb) : ((re[0] + rodd[0]) == 0.0 ? 0.0 : NAN);
+  const bool conv = std::isfinite(tr) && tr <= prm->tol;
+  if (status == EOFA_OK && !conv) status = std::isfinite(tr) ? EOFA_ERR_NOT_CONVERGED : EOFA_ERR_BREAKDOWN;
+  if (out) {
+    std::memset(out, 0, sizeof(*out));
+    out->iters = it;
+    out->outer_iters = restarts + 1;
+    out->converged = conv ? 1 : 0;
+    out->status = status;
+    out->true_resid = tr;
+    out->seconds = now_s() - t0;
+  }
+  if (status == EOFA_ERR_NOT_CONVERGED) g_err = "flexible CG did not reach the requested true residual";
+  if (status == EOFA_ERR_BREAKDOWN) g_err = "flexible CG breakdown (non-finite residual)";
+  return status;
+}
+
+}  // namespace
+
+extern "C" int eofa_cg_pairs(eofa_ctx* C, const eofa_system* sys, const void* phi, int32_t npairs, int32_t first,
+                             int32_t stride, double tol, int32_t max_iter, void* r_out, void* e_out,
+                             int32_t* recorded, int32_t* iters, void* stream) {
+  if (!C || !phi || !r_out || !e_out || !recorded) return fail(EOFA_ERR_INVALID, "eofa_cg_pairs: NULL argument");
+  if (npairs < 1 || first < 0 || stride < 1 || !(tol > 0.0) || max_iter < 1)
+    return fail(EOFA_ERR_INVALID, "eofa_cg_pairs: need npairs >= 1, first >= 0, stride >= 1, tol > 0, max_iter >= 1");
+  CHK(check_systems(sys, 1));
+  hipStream_t st = (hipStream_t)stream;
+  const Geometry& g = C->g;
+  Fgcg F;
+  F.C = C;
+  F.st = st;
+  CHK(F.init(sys, phi));
+  if (!std::isfinite(F.bb)) return fail(EOFA_ERR_BREAKDOWN, "eofa_cg_pairs: non-finite source");
+  const size_t b64 = packed_bytes(P64, g, 1), b32 = packed_bytes(P32, g, 1);
+  void* xs = nullptr;
+  if (hipMalloc(&xs, b64 * (size_t)npairs) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(EOFA_ERR_OOM, "eofa_cg_pairs: hipMalloc failed for the stored iterates");
+  }
+  auto run = [&]() -> int {
+    double rr0, ss, rr;
+    int flag;
+    CHK(F.poll(&rr0, &ss, &flag));
+    int j = 0, it = 0;
+    const int check = 16;
+    while (true) {
+      if (j < npairs && it == first + j * stride) {
+        launch_convert(P64, P32, g, F.r, (char*)r_out + b32 * j, 1, st);
+        launch_convert(P64, P64, g, F.x, (char*)xs + b64 * j, 1, st);
+        ++j;
+      }
+      if (it >= max_iter) {
+        *recorded = j;
+        if (iters) *iters = it;
+        return fail(EOFA_ERR_NOT_CONVERGED, "eofa_cg_pairs: CG did not reach tol within max_iter");
+      }
+      CHK(F.iterate(nullptr));
+      ++it;
+      if (it % check == 0) {
+        CHK(F.poll(&rr, &ss, &flag));
+        if (flag || !std::isfinite(rr)) return fail(EOFA_ERR_BREAKDOWN, "eofa_cg_pairs: CG breakdown");
+        if (rr <= tol * tol * rr0) break;
+      }
+    }
+    // e_j = x* - x_j in FP64, stored in FP32
+    for (int k = 0; k < j; ++k) {
+      launch_convert(P64, P64, g, F.x, F.tmp, 1, st);
+      launch_caxpy(F.n, -1.0, 0.0, (char*)xs + b64 * k, F.tmp, st);
+      launch_convert(P64, P32, g, F.tmp, (char*)e_out + b32 * k, 1, st);
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipGetLastError());
+    *recorded = j;
+    if (iters) *iters = it;
+    return EOFA_OK;
+  };
+  const int rc = run();
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(xs);
+  return rc;
+}
 
 extern "C" int eofa_cg_solve(eofa_ctx* C, const eofa_system* sys, const void* phi, void* psi, int32_t nrhs,
                              const eofa_solver_params* prm, eofa_solver_stats* stats, void* stream) {
@@ -864,7 +1180,16 @@ extern "C" int eofa_cg_solve(eofa_ctx* C, const eofa_system* sys, const void* ph
   if (phi == psi) return fail(EOFA_ERR_INVALID, "eofa_cg_solve: phi and psi alias");
   CHK(check_systems(sys, nrhs));
   CHK(check_params(prm));
-  return solve_batch(C, sys, nrhs, phi, psi, prm, stats, (hipStream_t)stream);
+  if (prm->precond == 0) return solve_batch(C, sys, nrhs, phi, psi, prm, stats, (hipStream_t)stream);
+  const size_t fbytes = (size_t)C->g.Ls * C->g.V * 12 * 16;
+  int worst = EOFA_OK;
+  for (int k = 0; k < nrhs; ++k) {
+    const int rc = fgcg_one(C, sys + k, (const char*)phi + fbytes * k, (char*)psi + fbytes * k, prm,
+                            stats ? stats + k : nullptr, (hipStream_t)stream);
+    if (rc == EOFA_ERR_INVALID || rc == EOFA_ERR_HIP || rc == EOFA_ERR_OOM) return rc;
+    if (rc != EOFA_OK && (worst == EOFA_OK || rc == EOFA_ERR_BREAKDOWN)) worst = rc;
+  }
+  return worst;
 }
 
 extern "C" int eofa_fifth_matrix(const eofa_action* act, const eofa_system* sys, int32_t mat, double* out) {

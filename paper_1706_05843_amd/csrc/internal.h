@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -137,4 +138,44 @@ void launch_heatbath_combine(const Geometry& g, const void* eta, const void* sol
 size_t packed_bytes(int prec, const Geometry& g, int nrhs);
 size_t link_bytes(int prec, const Geometry& g);
 
+}  // namespace eofa
+
+namespace eofa {
+struct Buf {
+  void* p = nullptr;
+  size_t n = 0;
+};
+
+// records the message returned by eofa_last_error() and passes the code on
+int set_error(int code, const std::string& msg);
+
+}  // namespace eofa
+
+// the context behind the opaque eofa_ctx handle
+struct eofa_ctx {
+  using Geometry = eofa::Geometry;
+  using Buf = eofa::Buf;
+  Geometry g;
+  double M5, b5, c5, c, d;
+  int bc[4];
+  int device;
+  void* links[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+  int* nbr[2] = {nullptr, nullptr};
+  std::map<std::string, Buf> pool;
+  // fifth-dimension matrices of the last systems uploaded
+  std::vector<double> sys_key;
+  double* mats = nullptr;  // [nrhs][NMAT][2][Ls][Ls] then mop[nrhs]
+  size_t mats_n = 0;
+  double* host_stage = nullptr;  // pinned
+  size_t host_stage_n = 0;
+  std::vector<hipEvent_t> events;
+  // autotuned (waves per work-group, right-hand sides per work-group) of the
+  // inner hop kernels, keyed by precision * 4096 + nrhs
+  std::map<int, std::pair<int, int>> tuned;
+  hipStream_t cap_stream = nullptr;  // non-blocking stream for HIP graph capture
+};
+
+namespace eofa {
+// z = N(r) for packed FP32 odd half-fields of one right-hand side (net.cpp)
+int net_apply_internal(eofa_ctx* C, eofa_net* N, const void* in, void* out, hipStream_t st);
 }  // namespace eofa

@@ -1,0 +1,47 @@
+// Internal interface of the parallel-transport network kernels (nn.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+
+namespace eofa {
+
+constexpr int NET_MAXC = 8;  // most channels per layer
+
+struct NetLayerArgs {
+  const float* xin[2];       // packed FP32 activations of both parities, Cin channels
+  float* yout;               // packed FP32 output of parity `parity`, Cout channels
+  const unsigned short* w;   // bfloat16 (re, im) [9][Cout_fwd][Cin_fwd] of the forward layer
+  const float* links;        // FP32 links of the output parity [Vh][8][9] complex
+  const int* nbr;            // [Vh][8] neighbour index in the other parity
+  int Vh, Ls, Cin, Cout;     // of this (forward or adjoint) application
+  int parity;
+};
+
+struct NetGradArgs {
+  const float* x[2];         // layer input, both parities, Cin channels
+  const float* g[2];         // dL/dy* at the layer output, both parities, Cout channels
+  const float* links[2];
+  const int* nbr[2];
+  double* partial;           // [9*Cin][2][Cout][nblk][2]
+  int Vh, Ls, Cin, Cout;
+};
+
+void launch_pt_layer(const NetLayerArgs& a, bool adj, hipStream_t st);
+void launch_pt_wgrad(const NetGradArgs& a, int nblk, int accumulate, double* gw, hipStream_t st);
+int launch_net_loss(int Vh, int Ls, const float* y, const float* e, float* g, const double* enorm, double* partial,
+                    hipStream_t st);
+void launch_net_adam(int n, float* w, float* m, float* v, const double* gw, double scale, float lr, float b1,
+                     float b2, float eps, int step, unsigned short* wb, hipStream_t st);
+void launch_net_to_bf16(int n, const float* w, unsigned short* wb, hipStream_t st);
+void launch_cdot(int n, const void* a, const void* b, double* partial, double* out, hipStream_t st);
+void launch_caxpy(int n, double ar, double ai, const void* x, void* y, hipStream_t st);
+void launch_cxpby(int n, const void* z, double br, double bi, void* p, hipStream_t st);
+void launch_sub_from(size_t n, const float* xs, float* e, hipStream_t st);
+void launch_fgcg_ratio(const double* num, const double* den, double sign, double* out, int* bad, hipStream_t st);
+void launch_cxpby_dev(int n, const void* z, const double* beta, void* p, hipStream_t st);
+// returns the number of blocks; partial holds [2][nblk] (|r|^2 then |s|^2)
+int launch_fgcg_update(int n, const double* alpha, void* x, void* r, void* s, const void* p, const void* q,
+                       const void* w, double* partial, hipStream_t st);
+
+}  // namespace eofa

@@ -40,20 +40,21 @@ class SolverParams(ctypes.Structure):
                 ("inner_prec", ctypes.c_int32), ("inner_tol", ctypes.c_double),
                 ("fixed_iters", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("rhs_block", ctypes.c_int32),
-                ("waves", ctypes.c_int32)]
+                ("waves", ctypes.c_int32), ("precond", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("net", ctypes.c_void_p)]
 
 
 class SolverStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("outer_iters", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("status", ctypes.c_int32), ("true_resid", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("hop_ms", ctypes.c_double * 4), ("hop_timed", ctypes.c_int32), ("waves", ctypes.c_int32),
-                ("rhs_block", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("rhs_block", ctypes.c_int32), ("fell_back", ctypes.c_int32)]
 
     def as_dict(self):
         return dict(iters=self.iters, outer_iters=self.outer_iters, converged=self.converged,
                     status=self.status, true_resid=self.true_resid, seconds=self.seconds,
                     hop_ms=list(self.hop_ms), hop_timed=self.hop_timed, waves=self.waves,
-                    rhs_block=self.rhs_block)
+                    rhs_block=self.rhs_block, fell_back=self.fell_back)
 
 
 _LIB = None
@@ -86,6 +87,17 @@ def lib():
                                  ctypes.POINTER(SolverStats), _P], _I),
         "eofa_fifth_matrix": ([ctypes.POINTER(Action), ctypes.POINTER(System), _I,
                                ctypes.POINTER(ctypes.c_double)], _I),
+        "eofa_cg_pairs": ([_P, ctypes.POINTER(System), _P, _I, _I, _I, ctypes.c_double, _I, _P, _P,
+                           ctypes.POINTER(_I), ctypes.POINTER(_I), _P], _I),
+        "eofa_net_create": ([_P, _I, ctypes.POINTER(_I), ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(_P)], _I),
+        "eofa_net_destroy": ([_P], _I),
+        "eofa_net_num_weights": ([_P], ctypes.c_size_t),
+        "eofa_net_get_weights": ([_P, ctypes.POINTER(ctypes.c_double)], _I),
+        "eofa_net_set_weights": ([_P, ctypes.POINTER(ctypes.c_double)], _I),
+        "eofa_net_apply": ([_P, _P, _P, _P, _P], _I),
+        "eofa_net_loss_grad": ([_P, _P, _P, _P, _I, ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_double), _P], _I),
+        "eofa_net_train": ([_P, _P, _P, _P, _I, _I, _I, ctypes.c_double, ctypes.POINTER(ctypes.c_double), _P], _I),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -129,11 +141,16 @@ def make_systems(systems):
 
 
 def make_params(tol=1e-10, max_iter=100000, max_outer=20, inner_prec=FP64, inner_tol=0.0,
-                fixed_iters=0, check_every=16, profile=0, use_graph=0, rhs_block=0, waves=0):
+                fixed_iters=0, check_every=16, profile=0, use_graph=0, rhs_block=0, waves=0,
+                precond=0, net=None):
+    """Solver parameters; ``net`` (a Net, or None for the identity) is used when precond = 1."""
     p = SolverParams()
     p.tol, p.max_iter, p.max_outer, p.inner_prec = tol, max_iter, max_outer, inner_prec
     p.inner_tol, p.fixed_iters, p.check_every, p.profile = inner_tol, fixed_iters, check_every, profile
     p.use_graph, p.rhs_block, p.waves = use_graph, rhs_block, waves
+    p.precond = precond
+    p.net = net._h.value if net is not None else None
+    p._net_ref = net  # keeps the network alive as long as the parameters
     return p
 
 
@@ -229,6 +246,85 @@ class Context:
         if rc in (EOFA_ERR_INVALID, EOFA_ERR_HIP, EOFA_ERR_OOM):
             _check(rc)
         return rc, [s.as_dict() for s in stats]
+
+    def eofa_cg_pairs(self, system, phi, npairs, first, stride, tol, max_iter, r_out, e_out, stream=None):
+        """Training pairs (r_k, e_k) into r_out, e_out (uint8 tensors of npairs packed FP32 odd
+        half-fields); returns (rc, recorded, iterations)."""
+        rec, its = _I(0), _I(0)
+        rc = lib().eofa_cg_pairs(self._h, make_systems([system]), _p(phi), npairs, first, stride, tol, max_iter,
+                                 _p(r_out), _p(e_out), ctypes.byref(rec), ctypes.byref(its), _stream(stream))
+        if rc in (EOFA_ERR_INVALID, EOFA_ERR_HIP, EOFA_ERR_OOM, EOFA_ERR_BREAKDOWN):
+            _check(rc)
+        return rc, rec.value, its.value
+
+
+class Net:
+    """An eofa_net: the gauge-covariant parallel-transport network (device weights)."""
+
+    def __init__(self, ctx, channels, seed=0, init_scale=1.0):
+        self.channels = [int(c) for c in channels]
+        ch = (_I * len(self.channels))(*self.channels)
+        self._h = ctypes.c_void_p()
+        _check(lib().eofa_net_create(ctx._h, len(self.channels) - 1, ch, seed, init_scale, ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            lib().eofa_net_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def num_weights(self):
+        return int(lib().eofa_net_num_weights(self._h))
+
+    def get_weights(self):
+        """Complex weights as a list of [9, C_out, C_in] arrays (FP32 master values)."""
+        n = self.num_weights()
+        buf = (ctypes.c_double * (2 * n))()
+        _check(lib().eofa_net_get_weights(self._h, buf))
+        flat = np.frombuffer(buf, dtype=np.float64).copy()
+        flat = flat[0::2] + 1j * flat[1::2]
+        out, k = [], 0
+        for ci, co in zip(self.channels[:-1], self.channels[1:]):
+            out.append(flat[k:k + 9 * co * ci].reshape(9, co, ci))
+            k += 9 * co * ci
+        return out
+
+    def set_weights(self, weights):
+        flat = np.concatenate([np.asarray(w, dtype=np.complex128).ravel() for w in weights])
+        assert flat.size == self.num_weights()
+        buf = np.empty(2 * flat.size)
+        buf[0::2], buf[1::2] = flat.real, flat.imag
+        _check(lib().eofa_net_set_weights(self._h, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+
+    def apply(self, ctx, inp, out, stream=None):
+        _check(lib().eofa_net_apply(ctx._h, self._h, _p(inp), _p(out), _stream(stream)))
+
+    def loss_grad(self, ctx, r, e, npairs, stream=None):
+        """(loss, [dL/dW* per layer]) over npairs packed FP32 pairs."""
+        n = self.num_weights()
+        loss = ctypes.c_double()
+        g = (ctypes.c_double * (2 * n))()
+        _check(lib().eofa_net_loss_grad(ctx._h, self._h, _p(r), _p(e), npairs, ctypes.byref(loss), g,
+                                        _stream(stream)))
+        flat = np.frombuffer(g, dtype=np.float64).copy()
+        flat = flat[0::2] + 1j * flat[1::2]
+        out, k = [], 0
+        for ci, co in zip(self.channels[:-1], self.channels[1:]):
+            out.append(flat[k:k + 9 * co * ci].reshape(9, co, ci))
+            k += 9 * co * ci
+        return loss.value, out
+
+    def train(self, ctx, r, e, npairs, epochs, batch, lr, stream=None):
+        """Adam on the pairs; returns the mean loss per pair of every epoch."""
+        hist = (ctypes.c_double * epochs)()
+        _check(lib().eofa_net_train(ctx._h, self._h, _p(r), _p(e), npairs, epochs, batch, lr, hist,
+                                    _stream(stream)))
+        return list(hist)
 
 
 def _p(t):

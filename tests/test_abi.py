@@ -45,6 +45,7 @@ def test_struct_layout_matches_c():
 int main(void) {
   printf("%zu %zu %zu %zu\n", sizeof(eofa_action), sizeof(eofa_system), sizeof(eofa_solver_params), sizeof(eofa_solver_stats));
   printf("%zu %zu %zu %zu %zu\n", offsetof(eofa_action, M5), offsetof(eofa_action, bc), offsetof(eofa_solver_params, inner_tol), offsetof(eofa_solver_stats, hop_ms), offsetof(eofa_solver_params, waves));
+  printf("%zu %zu %zu\n", offsetof(eofa_solver_params, precond), offsetof(eofa_solver_params, net), offsetof(eofa_solver_stats, fell_back));
   return 0;
 }
 '''
@@ -59,7 +60,8 @@ int main(void) {
                          ctypes.sizeof(eofa.SolverParams), ctypes.sizeof(eofa.SolverStats)]
     assert sizes[4:] == [eofa.Action.M5.offset, eofa.Action.bc.offset,
                          eofa.SolverParams.inner_tol.offset, eofa.SolverStats.hop_ms.offset,
-                         eofa.SolverParams.waves.offset]
+                         eofa.SolverParams.waves.offset, eofa.SolverParams.precond.offset,
+                         eofa.SolverParams.net.offset, eofa.SolverStats.fell_back.offset]
 
 
 @pytest.mark.parametrize("bad", [
@@ -116,3 +118,29 @@ def test_fifth_matrix_breakdown():
     with pytest.raises(eofa.EofaError) as e:
         eofa.eofa_fifth_matrix(act, (m_op, m_a, m_b, beta, chi), "mee_inv")
     assert e.value.code == eofa.EOFA_ERR_BREAKDOWN
+
+
+def test_network_rejects_bad_channels():
+    """Channel lists must run 1 -> ... -> 1 with 1..8 channels (checked before any device call)."""
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(16)  # never dereferenced: validation fails first
+    for chans in ([1, 9, 1], [2, 4, 1], [1, 4, 2], [1]):
+        arr = (ctypes.c_int32 * len(chans))(*chans)
+        rc = eofa.lib().eofa_net_create(dummy, len(chans) - 1, arr, 0, 1.0, ctypes.byref(h))
+        assert rc == eofa.EOFA_ERR_INVALID, chans
+
+
+def test_pairs_and_solver_params_validation():
+    dummy = ctypes.c_void_p(16)
+    rec, its = ctypes.c_int32(), ctypes.c_int32()
+    sysl = eofa.make_systems([(0.1, 0.0, 0.0, 0.0, 1)])
+    rc = eofa.lib().eofa_cg_pairs(dummy, sysl, dummy, 0, 0, 1, 1e-8, 10, dummy, dummy, ctypes.byref(rec),
+                                  ctypes.byref(its), None)
+    assert rc == eofa.EOFA_ERR_INVALID
+    prm = eofa.make_params(precond=2)
+    rc = eofa.lib().eofa_cg_solve(dummy, sysl, dummy, ctypes.c_void_p(32), 1, ctypes.byref(prm), None, None)
+    assert rc == eofa.EOFA_ERR_INVALID
+    prm = eofa.make_params(precond=1, fixed_iters=5)
+    rc = eofa.lib().eofa_cg_solve(dummy, sysl, dummy, ctypes.c_void_p(32), 1, ctypes.byref(prm), None, None)
+    assert rc == eofa.EOFA_ERR_INVALID
+
