@@ -182,17 +182,138 @@ def bench_batched(args, eofa, synth, torch, np):
     print(json.dumps(out), flush=True)
 
 
+def bench_learned(args, eofa, synth, torch, np):
+    """Learned preconditioner workload: 16^3 x 32, Ls = 16, eps = 0.5, the
+    shifted system H(m2) - Delta_+(m1, m2) P_+ (m1 = 0.04, m2 = 1.0). Training
+    pairs (r_k, e_k = x* - x_k) from FP64 CG on the normal equations of
+    args.train_fields seeded gauge fields (args.pairs_per_field each, spread
+    over the CG run); a 1 -> 8 -> 8 -> 8 -> 1 parallel-transport network
+    trained with Adam on the GPU; then, on args.held_fields held-out fields,
+    time to an FP64 true residual of 1e-10 for plain FP64 CGNR, FP16S/FP64
+    mixed CGNR, flexible CG with the identity, and flexible CG with the
+    trained network (network in FP32, operator in FP64). The loss is the
+    residual loss |A N(r) - r|^2/|r|^2 (A = M^dag M) unless --loss error."""
+    dims, Ls, eps, m1, m2 = (16, 16, 16, 32), 16, 0.5, 0.04, 1.0
+    system = (m2, m1, m2, -1.0, +1)
+    chans = [1, 8, 8, 8, 1]
+    act = eofa.make_action(dims, Ls, 1.8, 1.5, 0.5)
+    log = lambda m: print(f"bench: {m}", file=sys.stderr, flush=True)
+    log(f"learned workload dims={dims} Ls={Ls}, {args.train_fields} training + {args.held_fields} held-out fields")
+    ctxs, data = [], []
+    t0 = time.perf_counter()
+    stride = None
+    npf = args.pairs_per_field
+    for f in range(args.train_fields):
+        ctx = eofa.Context(act, torch.from_numpy(synth.gauge_field(dims, eps, 3000 + f)).cuda())
+        phi = synth.fermion_torch(dims, Ls, seed=3100 + f, nrhs=1)
+        b = ctx.packed_bytes(eofa.FP32)
+        if stride is None:  # spread the pairs over the CG run of the first field
+            r1 = torch.empty(b, dtype=torch.uint8, device="cuda")
+            _, _, its = ctx.eofa_cg_pairs(system, phi, 1, 0, 1, 1e-12, 50000, r1, r1.clone())
+            stride = max(1, its // npf)
+            log(f"training CG runs {its} iterations to 1e-12; pair stride {stride}")
+        r = torch.empty(npf * b, dtype=torch.uint8, device="cuda")
+        e = torch.empty(npf * b, dtype=torch.uint8, device="cuda")
+        rc, rec, its = ctx.eofa_cg_pairs(system, phi, npf, 0, stride, 1e-12, 50000, r, e)
+        ctxs.append(ctx)
+        data.append((r, e, rec))
+        log(f"field {f}: {rec} pairs, CG {its} iterations")
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t0
+    npairs = sum(d[2] for d in data)
+    net = eofa.Net(ctxs[0], chans, seed=7, init_scale=0.5)
+    # loss of the untrained network
+    lsys = system if args.loss == "residual" else None
+    loss0 = sum(net.loss_grad(c, d[0], d[1], d[2], system=lsys)[0] for c, d in zip(ctxs, data)) / npairs
+    t0 = time.perf_counter()
+    hist = []
+    for ep in range(args.epochs):
+        tot = 0.0
+        for c, (r, e, rec) in zip(ctxs, data):
+            tot += net.train(c, r, e, rec, epochs=1, batch=args.batch, lr=args.lr, system=lsys)[0] * rec
+        hist.append(tot / npairs)
+        log(f"epoch {ep}: mean loss per pair {hist[-1]:.4f}")
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    for c in ctxs:
+        c.close()
+    del data
+    torch.cuda.empty_cache()
+
+    def timed(ctx, phi, prm):
+        psi = torch.zeros_like(phi)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rc, st = ctx.eofa_cg_solve([system], phi, psi, prm)
+        torch.cuda.synchronize()
+        return dict(seconds=time.perf_counter() - t, iters=st[0]["iters"], true_resid=st[0]["true_resid"],
+                    converged=st[0]["converged"], fell_back=st[0]["fell_back"], rc=rc)
+
+    modes = {
+        "plain_fp64": eofa.make_params(tol=1e-10, inner_prec=eofa.FP64),
+        "mixed_fp16s": eofa.make_params(tol=1e-10, inner_prec=eofa.FP16S),
+        "fgcg_identity": eofa.make_params(tol=1e-10, precond=1),
+        "fgcg_learned": eofa.make_params(tol=1e-10, precond=1, net=net),
+    }
+    res = {k: [] for k in modes}
+    for f in range(args.held_fields):
+        ctx = eofa.Context(act, torch.from_numpy(synth.gauge_field(dims, eps, 4000 + f)).cuda())
+        phi = synth.fermion_torch(dims, Ls, seed=4100 + f, nrhs=1)
+        if f == 0:
+            for prm in modes.values():  # warm-up (autotune, workspace)
+                timed(ctx, phi, prm)
+        for k, prm in modes.items():
+            res[k].append(timed(ctx, phi, prm))
+        log(f"held-out field {f}: " + ", ".join(f"{k} {v[-1]['iters']} it {v[-1]['seconds']:.3f} s" for k, v in res.items()))
+        ctx.close()
+    summ = {}
+    for k, v in res.items():
+        summ[k] = dict(mean_seconds=round(float(np.mean([x["seconds"] for x in v])), 5),
+                       mean_iters=round(float(np.mean([x["iters"] for x in v])), 1),
+                       max_true_resid=float(max(x["true_resid"] for x in v)),
+                       all_converged=all(x["converged"] == 1 for x in v),
+                       fell_back=sum(x["fell_back"] for x in v))
+    plain = summ["plain_fp64"]["mean_seconds"]
+    out = {
+        "metric": METRIC, "value": summ["fgcg_learned"]["mean_seconds"], "unit": "s", "n_gpus": 1,
+        "steps": args.held_fields, "warmup": 1, "ms_per_step": round(summ["fgcg_learned"]["mean_seconds"] * 1e3, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{dims[0]}x{dims[1]}x{dims[2]}x{dims[3]} Ls={Ls}, system H(m2)-Delta_+(m1,m2)P_+ "
+                               f"m1={m1} m2={m2}; network {chans}, bfloat16 weights, FP32 arithmetic; "
+                               f"{npairs} training pairs from {args.train_fields} fields, {args.epochs} epochs; "
+                               f"FGCG to true residual 1e-10 on {args.held_fields} held-out fields",
+                   "lattice": list(dims), "Ls": Ls},
+        "modes": summ,
+        "time_ratio_vs_plain_fp64": {k: round(v["mean_seconds"] / plain, 3) for k, v in summ.items()},
+        "iteration_ratio_learned_vs_identity": round(summ["fgcg_learned"]["mean_iters"] /
+                                                     summ["fgcg_identity"]["mean_iters"], 3),
+        "training": {"pairs": npairs, "pair_stride": stride, "seconds_pairs": round(t_pairs, 2),
+                     "seconds_training": round(t_train, 2), "loss_untrained": loss0, "loss_per_epoch": hist,
+                     "epochs": args.epochs, "batch": args.batch, "lr": args.lr, "loss": args.loss},
+    }
+    net.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["batched"])
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["batched", "learned"])
     ap.add_argument("--batched-iters", type=int, default=64)
     ap.add_argument("--inner", default="fp16s", choices=sorted(PREC))
     ap.add_argument("--inner-tol", type=float, default=0.0)
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 reference solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--train-fields", type=int, default=8)
+    ap.add_argument("--held-fields", type=int, default=8)
+    ap.add_argument("--pairs-per-field", type=int, default=64)
+    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--loss", default="residual", choices=["residual", "error"],
+                    help="network loss: |A N(r) - r|^2/|r|^2 (residual) or |N(r) - e|^2/|e|^2 (error)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (known bytes) to calibrate HBM counters")
     args = ap.parse_args()
@@ -217,6 +338,9 @@ def main():
 
     if args.workload == "batched":
         bench_batched(args, eofa, synth, torch, np)
+        return
+    if args.workload == "learned":
+        bench_learned(args, eofa, synth, torch, np)
         return
 
     dims, Ls, eps, m1, gseed, sseed = WORKLOADS[args.workload]

@@ -122,7 +122,8 @@ typedef struct {
   int32_t precond;     /* 0: CGNR as above; 1: flexible CG on the normal equations in FP64 with
                           the learned preconditioner `net` (NULL = identity), one right-hand
                           side at a time, falling back to CGNR on breakdown or stagnation     */
-  int32_t pad0;
+  int32_t fcg_window;  /* precond = 1: previous directions each new one is A-orthogonalised
+                          against (1..32; 0 = 8 with a network, 1 without)                     */
   const eofa_net* net; /* precond = 1: network (eofa_net_create), evaluated in FP32             */
 } eofa_solver_params;
 
@@ -239,18 +240,24 @@ int eofa_net_get_weights(const eofa_net* net, double* out);
 int eofa_net_set_weights(eofa_net* net, const double* in); /* also resets Adam */
 /* out = N(in): packed FP32 odd half-fields (one right-hand side), no alias */
 int eofa_net_apply(eofa_ctx* ctx, eofa_net* net, const void* in, void* out, void* stream);
-/* Loss sum_p |N(r_p) - e_p|^2 / |e_p|^2 over npairs consecutive packed FP32
- * odd half-fields r, e (device), and its gradient dL/dW* (Wirtinger; the
- * gradient in (Re W, Im W) is twice its real and imaginary parts) as
- * host grad[2 * num_weights] (may be NULL); loss: host (may be NULL).     */
-int eofa_net_loss_grad(eofa_ctx* ctx, eofa_net* net, const void* r, const void* e, int32_t npairs,
-                       double* loss, double* grad, void* stream);
+/* Loss over npairs consecutive packed FP32 odd half-fields (device) and its
+ * gradient dL/dW* (Wirtinger; the gradient in (Re W, Im W) is twice its real
+ * and imaginary parts) as host grad[2 * num_weights] (may be NULL); loss:
+ * host (may be NULL). Two losses:
+ *   sys == NULL: error loss     sum_p |N(r_p) - e_p|^2 / |e_p|^2  (pairs r, e);
+ *   sys != NULL: residual loss  sum_p |A N(r_p) - r_p|^2 / |r_p|^2 with
+ *                A = M^dag M of the odd Schur system of sys (applied by the
+ *                hop kernels in FP32); e is not used and may be NULL.    */
+int eofa_net_loss_grad(eofa_ctx* ctx, eofa_net* net, const eofa_system* sys, const void* r, const void* e,
+                       int32_t npairs, double* loss, double* grad, void* stream);
 /* Adam training (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on the
  * pairs, in order, in mini-batches of `batch`; one step per mini-batch on
- * the batch-mean loss. loss_per_epoch: host [epochs] mean loss per pair over
- * the epoch, measured during it (may be NULL).                          */
-int eofa_net_train(eofa_ctx* ctx, eofa_net* net, const void* r, const void* e, int32_t npairs,
-                   int32_t epochs, int32_t batch, double lr, double* loss_per_epoch, void* stream);
+ * the batch-mean loss (sys selects the loss as above). loss_per_epoch: host
+ * [epochs] mean loss per pair over the epoch, measured during it (may be
+ * NULL).                                                                 */
+int eofa_net_train(eofa_ctx* ctx, eofa_net* net, const eofa_system* sys, const void* r, const void* e,
+                   int32_t npairs, int32_t epochs, int32_t batch, double lr, double* loss_per_epoch,
+                   void* stream);
 
 /* Host only (no device work): the fifth-dimension matrix `mat` that the
  * library builds for one system, as out[2][Ls][Ls] (row-major; [0] acts on

@@ -15,7 +15,11 @@ transported, so the layer is gauge covariant. The network is a stack of
 layers; its input is the odd-sublattice residual embedded in the full lattice
 (even sites zero) and its output is read back on the odd sites.
 
-Loss over pairs (r, e): sum_p |N(r_p)_odd - e_p|^2 / |e_p|^2.
+Losses (project decisions):
+* error loss over pairs (r, e):   sum_p |N(r_p)_odd - e_p|^2 / |e_p|^2;
+* residual loss over vectors r:   sum_p |A N(r_p)_odd - r_p|^2 / |r_p|^2 for a
+  Hermitian operator A on the odd sublattice (here A = M^dag M of the Schur
+  system), so that A N approximates the identity.
 Gradients are dL/dW* (Wirtinger); dL/dRe W = 2 Re(dL/dW*), dL/dIm W = 2 Im(dL/dW*).
 """
 import numpy as np
@@ -89,6 +93,27 @@ def loss_and_grads(U, Ws, pairs, dims, bc):
             grads[k] += weight_grad(U, X[k], G, bc)
             if k > 0:
                 G = layer_adjoint(U, Ws[k], G, bc)
+    return L, grads
+
+
+def _backprop(U, Ws, X, G, grads, bc):
+    for k in range(len(Ws) - 1, -1, -1):
+        grads[k] += weight_grad(U, X[k], G, bc)
+        if k > 0:
+            G = layer_adjoint(U, Ws[k], G, bc)
+
+
+def residual_loss_and_grads(U, Ws, rs, A, dims, bc):
+    """L = sum_p |A y_p - r_p|^2 / |r_p|^2 with y_p = N(r_p) on the odd sites, A
+    Hermitian; dL/dy* = A (A y - r) / |r|^2, then the same back-propagation."""
+    L = 0.0
+    grads = [np.zeros_like(W) for W in Ws]
+    for r in rs:
+        y, X = forward(U, Ws, r, dims, bc)
+        nr = norm2(r)
+        d = A(y) - r
+        L += norm2(d) / nr
+        _backprop(U, Ws, X, (A(d) / nr)[None], grads, bc)
     return L, grads
 
 

@@ -162,6 +162,7 @@ HopArgs base_args(eofa_ctx* C, int prec, int out_parity, int nrhs) {
   std::memset(&a, 0, sizeof(a));
   a.links = C->links[prec][out_parity];
   a.nbr = C->nbr[out_parity];
+  a.order = C->order;
   a.mats = C->mats;
   a.matA = 0;
   a.matB = 0;
@@ -244,6 +245,19 @@ int eofa_create(const eofa_action* act, const void* gauge, void* stream, eofa_ct
       eofa_destroy(C);
       return fail(EOFA_ERR_OOM, "hipMalloc failed for neighbour table");
     }
+  if (hipMalloc((void**)&C->order, (size_t)C->g.Vh * sizeof(int)) != hipSuccess) {
+    (void)hipGetLastError();
+    eofa_destroy(C);
+    return fail(EOFA_ERR_OOM, "hipMalloc failed for the traversal order");
+  }
+  {
+    std::vector<int> ord(C->g.Vh);
+    site_order(C->g, ord.data());
+    if (hipMemcpy(C->order, ord.data(), ord.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+      eofa_destroy(C);
+      return fail(EOFA_ERR_HIP, "traversal order upload failed");
+    }
+  }
   void* l64[2] = {C->links[P64][0], C->links[P64][1]};
   void* l32[2] = {C->links[P32][0], C->links[P32][1]};
   void* l16[2] = {C->links[P16][0], C->links[P16][1]};
@@ -265,6 +279,7 @@ int eofa_destroy(eofa_ctx* C) {
       if (C->links[p][par]) (void)hipFree(C->links[p][par]);
   for (int par = 0; par < 2; ++par)
     if (C->nbr[par]) (void)hipFree(C->nbr[par]);
+  if (C->order) (void)hipFree(C->order);
   for (auto& kv : C->pool)
     if (kv.second.p) (void)hipFree(kv.second.p);
   if (C->mats) (void)hipFree(C->mats);
@@ -773,7 +788,9 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
       HIPCHK(hipEventDestroy(join));
     } else {
       while (true) {
-        const bool prof = prm->profile && timed < max_timed && (it % 8 == 0);
+        // timed iterations sit between host polls (which drain the queue), so the
+        // events bracket the kernels and not host launch latency
+        const bool prof = prm->profile && timed < max_timed && (it % 8 == 4);
         hipEvent_t* ev = prof ? &C->events[timed * 8] : nullptr;
         CHK(inner_iteration(C, S, PR, k1, k2, k3, k4, nbh, nrhs, Sst, partial, xin, rin, pS, st, ev));
         if (prof) ++timed;
@@ -851,6 +868,46 @@ int check_params(const eofa_solver_params* prm) {
 
 }  // namespace
 
+// A = M^dag M of the odd Schur system of sys on packed FP32 odd half-fields of
+// one right-hand side: out = A in, FP32 arithmetic (K1, K2, K3, K4S). The
+// network's residual loss uses it; workspace comes from the context pool.
+int eofa::normal_op_fp32(eofa_ctx* C, const eofa_system* sys, const void* in, void* out, hipStream_t st) {
+  const Geometry& g = C->g;
+  CHK(upload_systems(C, sys, 1, st));
+  const size_t b32 = packed_bytes(P32, g, 1);
+  void *te, *w, *pv;
+  CHK(ws(C, "na_te", b32, &te));
+  CHK(ws(C, "na_w", b32, &w));
+  const int maxblk = std::max(hop_blocks(P32, g.Vh, g.Ls, 1), (g.Ls * g.Vh + 255) / 256);
+  CHK(ws(C, "na_partial", sizeof(double) * (size_t)maxblk, &pv));
+  HopArgs k1 = base_args(C, P32, 0, 1);
+  k1.in = in;
+  k1.out = te;
+  k1.matA = MAT_MEE_INV;
+  CHK(hop(C, P32, ROLE_K1, k1, st));
+  HopArgs k2 = base_args(C, P32, 1, 1);
+  k2.in = te;
+  k2.y = in;
+  k2.out = w;
+  k2.matB = MAT_MEE;
+  k2.partial = (double*)pv;
+  CHK(hop(C, P32, ROLE_K2, k2, st));
+  HopArgs k3 = base_args(C, P32, 0, 1);
+  k3.in = w;
+  k3.out = te;
+  k3.matA = MAT_MEE_INV_T;
+  CHK(hop(C, P32, ROLE_K3, k3, st));
+  HopArgs k4 = base_args(C, P32, 1, 1);
+  k4.in = te;
+  k4.y = w;
+  k4.r = out;
+  k4.matA = MAT_NEG_DT_T;
+  k4.matB = MAT_MEE_T;
+  k4.partial = (double*)pv;
+  CHK(hop(C, P32, ROLE_K4S, k4, st));
+  return EOFA_OK;
+}
+
 // ---------------------------------------------------------------------------
 // flexible CG on the normal equations (learned preconditioner) and the
 // training-pair generator
@@ -858,17 +915,24 @@ int check_params(const eofa_solver_params* prm) {
 namespace {
 
 // Device scalars of the flexible-CG recurrence (doubles), then one int flag.
-enum FgScalar { FG_WW = 0, FG_QZ = 2, FG_PR = 4, FG_ALPHA = 6, FG_BETA = 8, FG_NRM = 10, FG_N = 12 };
+// FG_WWS + j: <p_j, A p_j> of window slot j.
+constexpr int FG_MAXW = 32;  // most previous directions kept
+enum FgScalar { FG_WW = 0, FG_QZ = 2, FG_PR = 4, FG_ALPHA = 6, FG_BETA = 8, FG_NRM = 10, FG_WWS = 12,
+                FG_N = FG_WWS + FG_MAXW + 2 };
 
 // One right-hand side, FP64 throughout, on the odd Schur system:
 //   s = b~ - M^ x (Schur residual), r = M^dag s (normal residual),
-//   z = N(r); p = z - (<A p_old, z>/<p_old, A p_old>) p_old; w = M^ p; q = M^dag w;
-//   alpha = <p, r>/|w|^2; x += alpha p; r -= alpha q; s -= alpha w
-// (Notay's flexible CG with one-term truncation, A = M^dag M).
+//   z = N(r); p = z - sum_j (<A p_j, z>/<p_j, A p_j>) p_j over the last m
+//   directions; w = M^ p; q = M^dag w; alpha = <p, r>/|w|^2;
+//   x += alpha p; r -= alpha q; s -= alpha w
+// (Notay's flexible CG, A = M^dag M, truncated to m previous directions;
+// m = 1 is the one-term recurrence, which for N = 1 is CG).
 struct Fgcg {
   eofa_ctx* C = nullptr;
   hipStream_t st = nullptr;
   void *be, *bo, *bt, *x, *s, *r, *p, *q, *w, *z, *te, *tmp, *r32, *z32;
+  std::vector<void*> ps, qs;  // window slots (m >= 2)
+  int m = 1, nvalid = 0, cur = 0;
   double* partial = nullptr;
   double* sc = nullptr;
   int* bad = nullptr;
@@ -876,6 +940,19 @@ struct Fgcg {
   int n = 0;  // complex numbers in one FP64 odd half-field
   double bb = 0.0;
   bool first = true;
+
+  int set_window(int mw) {
+    m = std::max(1, std::min(mw, FG_MAXW));
+    if (m == 1) return EOFA_OK;
+    const size_t b64 = packed_bytes(P64, C->g, 1);
+    ps.assign(m + 1, nullptr);
+    qs.assign(m + 1, nullptr);
+    for (int j = 0; j <= m; ++j) {
+      CHK(ws(C, ("fg_wp" + std::to_string(j)).c_str(), b64, &ps[j]));
+      CHK(ws(C, ("fg_wq" + std::to_string(j)).c_str(), b64, &qs[j]));
+    }
+    return EOFA_OK;
+  }
 
   int init(const eofa_system* sys, const void* phi) {
     const Geometry& g = C->g;
@@ -935,6 +1012,7 @@ struct Fgcg {
     CHK(hop(C, P64, ROLE_K4S, a4, st, &nb));
     launch_finalize(FIN_NORM, partial, nb, 1, Sst, sc + FG_NRM, st);
     first = true;
+    nvalid = 0;
     return EOFA_OK;
   }
 
@@ -967,12 +1045,29 @@ struct Fgcg {
     } else {
       launch_convert(P64, P64, g, r, z, 1, st);
     }
-    if (first) {
-      launch_convert(P64, P64, g, z, p, 1, st);
+    double* ww = sc + FG_WW;
+    if (m == 1) {
+      if (first) {
+        launch_convert(P64, P64, g, z, p, 1, st);
+      } else {
+        launch_cdot(n, q, z, partial, sc + FG_QZ, st);
+        launch_fgcg_ratio(sc + FG_QZ, sc + FG_WW, -1.0, sc + FG_BETA, bad, st);
+        launch_cxpby_dev(n, z, sc + FG_BETA, p, st);
+      }
     } else {
-      launch_cdot(n, q, z, partial, sc + FG_QZ, st);
-      launch_fgcg_ratio(sc + FG_QZ, sc + FG_WW, -1.0, sc + FG_BETA, bad, st);
-      launch_cxpby_dev(n, z, sc + FG_BETA, p, st);
+      // new direction in slot cur, A-orthogonal to the previous nvalid ones
+      // (classical Gram-Schmidt: every coefficient from z)
+      if (first) nvalid = 0;
+      p = ps[cur];
+      q = qs[cur];
+      ww = sc + FG_WWS + cur;
+      launch_convert(P64, P64, g, z, p, 1, st);
+      for (int k = 1; k <= nvalid; ++k) {
+        const int j = (cur - k + m + 1) % (m + 1);
+        launch_cdot(n, qs[j], z, partial, sc + FG_QZ, st);
+        launch_fgcg_ratio(sc + FG_QZ, sc + FG_WWS + j, -1.0, sc + FG_BETA, bad, st);
+        launch_caxpy_dev(n, sc + FG_BETA, ps[j], p, st);
+      }
     }
     first = false;
     HopArgs k1 = base_args(C, P64, 0, 1);
@@ -988,7 +1083,7 @@ struct Fgcg {
     k2.partial = partial;
     int nb = 0;
     CHK(hop(C, P64, ROLE_K2, k2, st, &nb));
-    launch_finalize(FIN_NORM, partial, nb, 1, Sst, sc + FG_WW, st);
+    launch_finalize(FIN_NORM, partial, nb, 1, Sst, ww, st);
     HopArgs k3 = base_args(C, P64, 0, 1);
     k3.in = w;
     k3.out = te;
@@ -1003,16 +1098,20 @@ struct Fgcg {
     k4.partial = partial;
     CHK(hop(C, P64, ROLE_K4S, k4, st, &nb));
     launch_cdot(n, p, r, partial, sc + FG_PR, st);
-    launch_fgcg_ratio(sc + FG_PR, sc + FG_WW, 1.0, sc + FG_ALPHA, bad, st);
+    launch_fgcg_ratio(sc + FG_PR, ww, 1.0, sc + FG_ALPHA, bad, st);
     nb = launch_fgcg_update(n, sc + FG_ALPHA, x, r, s, p, q, w, partial, st);
     launch_finalize(FIN_NORM, partial, nb, 2, Sst, sc + FG_NRM, st);
+    if (m > 1) {
+      nvalid = std::min(nvalid + 1, m);
+      cur = (cur + 1) % (m + 1);
+    }
     HIPCHK(hipGetLastError());
     return EOFA_OK;
   }
 
   // host read of |r|^2, |s|^2 and the breakdown flag
   int poll(double* rr, double* ss, int* flag) {
-    double h[FG_N + 8];
+    double h[FG_N + 2];
     CHK(fetch(C, sc, sizeof(double) * FG_N + sizeof(int), h, st));
     *rr = h[FG_NRM];
     *ss = h[FG_NRM + 1];
@@ -1029,6 +1128,7 @@ int fgcg_one(eofa_ctx* C, const eofa_system* sys, const void* phi, void* psi, co
   F.C = C;
   F.st = st;
   CHK(F.init(sys, phi));
+  CHK(F.set_window(prm->fcg_window > 0 ? prm->fcg_window : (net ? 8 : 1)));
   const int check = prm->check_every > 0 ? prm->check_every : 16;
   const int max_restart = std::max(1, prm->max_outer);
   const int stall = std::max(256, 16 * check);  // iterations without a 0.7x gain in |s| before falling back

@@ -209,4 +209,24 @@ int build_fifth(const Geometry& g, double M5, double b5, double c5, const eofa_s
   return EOFA_OK;
 }
 
+// x-rows (y, z, t) in blocks of by x bz x bt rows (4 where the extent allows,
+// else 2 or 1), blocks in lexicographic order (y fastest), rows inside a block
+// likewise; each row contributes its Lx/2 sites of one parity in x order.
+void site_order(const Geometry& g, int* out) {
+  auto blk = [](int L) { return L % 4 == 0 ? 4 : (L % 2 == 0 ? 2 : 1); };
+  const int Lxh = g.L[0] / 2, Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
+  const int by = blk(Ly), bz = blk(Lz), bt = blk(Lt);
+  size_t k = 0;
+  for (int tc = 0; tc < Lt / bt; ++tc)
+    for (int zc = 0; zc < Lz / bz; ++zc)
+      for (int yc = 0; yc < Ly / by; ++yc)
+        for (int tt = 0; tt < bt; ++tt)
+          for (int zz = 0; zz < bz; ++zz)
+            for (int yy = 0; yy < by; ++yy) {
+              const int t = tc * bt + tt, z = zc * bz + zz, y = yc * by + yy;
+              const int row = (t * Lz + z) * Ly + y;
+              for (int xh = 0; xh < Lxh; ++xh) out[k++] = row * Lxh + xh;
+            }
+}
+
 }  // namespace eofa

@@ -31,6 +31,10 @@ __device__ __forceinline__ cx<T> cfma(cx<T> a, cx<T> b, cx<T> c) {  // a*b + c
 }
 template <class T>
 __device__ __forceinline__ cx<T> mul_i(cx<T> a) { return {-a.i, a.r}; }  // i a
+template <class T>
+__device__ __forceinline__ cx<T> cfma_r(T s, cx<T> a, cx<T> c) {  // s*a + c, s real
+  return {fma(s, a.r, c.r), fma(s, a.i, c.i)};
+}
 
 template <int P>
 struct ST;

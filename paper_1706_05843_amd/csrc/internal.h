@@ -89,6 +89,7 @@ struct HopArgs {
   void* r;            // packed, parity p, accumulator precision (K4/K4S)
   const void* links;  // [Vh][8][9] complex for output parity p
   const int* nbr;     // [Vh][8] checkerboard index in parity 1-p
+  const int* order;   // [Vh] traversal position -> checkerboard index (a permutation)
   const double* mats; // [nrhs][NMAT][2][Ls][Ls]
   int matA, matB;
   double cpd, cmd;    // c+d, c-d (premix)
@@ -136,6 +137,9 @@ void launch_heatbath_combine(const Geometry& g, const void* eta, const void* sol
                              const double* coef, const double* om, const int* chir, int nsys, hipStream_t st);
 
 size_t packed_bytes(int prec, const Geometry& g, int nrhs);
+// traversal order of the hop kernels (host): position k -> checkerboard index
+// i = row * Lx/2 + xh, x-rows visited in (y, z, t) blocks of up to 4^3
+void site_order(const Geometry& g, int* out);
 size_t link_bytes(int prec, const Geometry& g);
 
 }  // namespace eofa
@@ -161,6 +165,7 @@ struct eofa_ctx {
   int device;
   void* links[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
   int* nbr[2] = {nullptr, nullptr};
+  int* order = nullptr;  // hop-kernel traversal order (site_order), [Vh]
   std::map<std::string, Buf> pool;
   // fifth-dimension matrices of the last systems uploaded
   std::vector<double> sys_key;
@@ -178,4 +183,7 @@ struct eofa_ctx {
 namespace eofa {
 // z = N(r) for packed FP32 odd half-fields of one right-hand side (net.cpp)
 int net_apply_internal(eofa_ctx* C, eofa_net* N, const void* in, void* out, hipStream_t st);
+// out = M^dag M in for the odd Schur system of sys, packed FP32 odd half-fields
+// of one right-hand side, FP32 arithmetic (api.cpp)
+int normal_op_fp32(eofa_ctx* C, const eofa_system* sys, const void* in, void* out, hipStream_t st);
 }  // namespace eofa

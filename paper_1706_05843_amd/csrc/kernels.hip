@@ -90,6 +90,34 @@ struct HopLds {
 // the same neighbour: the lanes (g, s-1) and (g, s+1) of this wave hold
 // exactly those spinors for the same direction, so they are exchanged across
 // lanes instead of being loaded again.
+// One direction's neighbour spinor as loaded: FP16S keeps the raw half2
+// words and the site scale (decoded inside the arithmetic), else the values.
+template <int P>
+struct DirIn {
+  cx<typename ST<P>::R> v[12];
+};
+template <>
+struct DirIn<P16> {
+  unsigned w[12];
+  float sc;
+};
+
+template <int P>
+__device__ __forceinline__ void load_dir(const void* in, const FD& fin, int r, int s, int n, DirIn<P>& b) {
+  if constexpr (P == P16) {
+    const size_t e0 = eidx(fin, r, 0, s, n), qs = qstride(fin);
+    b.sc = scale_ptr(in, fin)[sidx(fin, r, s, n)];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const uint2 v = ((const uint2*)in)[e0 + q * qs];
+      b.w[2 * q] = v.x;
+      b.w[2 * q + 1] = v.y;
+    }
+  } else {
+    ld_spinor<P>(in, fin, r, s, n, b.v);
+  }
+}
+
 template <int P, bool DAG, bool PRE>
 __device__ __forceinline__ void hop_site(const HopArgs& a, const FD& fin, int r, int s, int g, int ls,
                                          const cx<typename ST<P>::R>* s_link, const int* s_nbr,
@@ -111,45 +139,56 @@ __device__ __forceinline__ void hop_site(const HopArgs& a, const FD& fin, int r,
   }
 #pragma unroll
   for (int c = 0; c < 12; ++c) acc[c] = {R(0), R(0)};
+  // Below FP64 the next direction's loads are issued before this
+  // direction's arithmetic (two directions in registers), so each wave keeps
+  // memory requests in flight while it computes; FP64 keeps one direction
+  // live (its register budget) and relies on occupancy.
+  constexpr bool PF = P != P64;
+  DirIn<P> b0, b1;
+  if constexpr (PF) load_dir<P>(a.in, fin, r, s, s_nbr[ls * NSTR], b0);
 #pragma unroll
   for (int dir = 0; dir < 8; ++dir) {
-    // scheduling fence: one direction's spinor is live at a time
-    // (occupancy, not deep unrolling, hides the load latency)
+    // scheduling fence per direction: bounds the live registers
     __builtin_amdgcn_sched_barrier(0);
+    if constexpr (PF) {
+      if (dir < 7) load_dir<P>(a.in, fin, r, s, s_nbr[ls * NSTR + dir + 1], (dir & 1) ? b0 : b1);
+    } else {
+      load_dir<P>(a.in, fin, r, s, s_nbr[ls * NSTR + dir], b0);
+    }
+    const DirIn<P>& b = (PF && (dir & 1)) ? b1 : b0;
     const int mu = dir & 3;
     const bool fwd = dir < 4;
-    const int n = s_nbr[ls * NSTR + dir];
     cx<R> sp[12];
+    unsigned raw[12];  // FP16S without premix: the raw half2 words, projected directly
+    (void)raw;
+    // the spinor of this direction is scl * sp (scl = 1 unless FP16S); scl
+    // is applied in the accumulation below, as FMAs
+    R scl = R(1);
     if constexpr (P == P16) {
       // raw half2 words; the neighbours' halves travel as raw words too and
-      // every conversion is folded into a mixed-precision FMA
-      const size_t e0 = eidx(fin, r, 0, s, n), qs = qstride(fin);
-      const float sc = scale_ptr(a.in, fin)[sidx(fin, r, s, n)];
-      unsigned w[12];
-#pragma unroll
-      for (int q = 0; q < 6; ++q) {
-        const uint2 v = ((const uint2*)a.in)[e0 + q * qs];
-        w[2 * q] = v.x;
-        w[2 * q + 1] = v.y;
-      }
+      // every conversion is folded into a mixed-precision FMA:
+      //   (D~ psi)_s = sc h_s + f_up su h_{s-1} (+ f_lo sl h_{s+1})
+      //              = scl (h_s + (f su / scl) h_{s-1}),  scl = sc (1 if sc = 0, where h_s = 0)
+      const float sc = b.sc;
+      const unsigned* w = b.w;
+      scl = sc != 0.f ? sc : 1.f;
       if constexpr (PRE) {
-        const float su = __shfl(sc, src_up, 64) * aup, sl = __shfl(sc, src_lo, 64) * alo;
+        const float inv = __builtin_amdgcn_rcpf(scl);
+        const float su = __shfl(sc, src_up, 64) * aup * inv, sl = __shfl(sc, src_lo, 64) * alo * inv;
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
           const unsigned t = __shfl((int)w[c], c < 6 ? src_up : src_lo, 64);
           const h2_t hs = __builtin_bit_cast(h2_t, w[c]), ht = __builtin_bit_cast(h2_t, t);
           const float f = c < 6 ? su : sl;
-          sp[c] = {fmaf(f, (float)ht.x, sc * (float)hs.x), fmaf(f, (float)ht.y, sc * (float)hs.y)};
+          sp[c] = {fmaf(f, (float)ht.x, (float)hs.x), fmaf(f, (float)ht.y, (float)hs.y)};
         }
       } else {
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-          const h2_t hs = __builtin_bit_cast(h2_t, w[c]);
-          sp[c] = {sc * (float)hs.x, sc * (float)hs.y};
-        }
+        for (int c = 0; c < 12; ++c) raw[c] = w[c];
       }
     } else {
-      ld_spinor<P>(a.in, fin, r, s, n, sp);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) sp[c] = b.v[c];
       if constexpr (PRE) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
@@ -163,6 +202,32 @@ __device__ __forceinline__ void hop_site(const HopArgs& a, const FD& fin, int r,
     // sg = -1 for (1 - g_mu), +1 for (1 + g_mu)
     const R sg = (fwd != DAG) ? R(-1) : R(1);
     cx<R> h[6];
+    if constexpr (P == P16 && !PRE) {
+      // (1 + sg g_mu) projection straight from the halves: each component is
+      // one mixed-precision FMA with both conversions folded in
+      // +-1 kept opaque so that the conversions fold into v_fma_mix instead
+      // of becoming separate conversions and adds
+      float k = sg;
+      asm volatile("" : "+s"(k));
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const h2_t u0 = __builtin_bit_cast(h2_t, raw[c]), u1 = __builtin_bit_cast(h2_t, raw[3 + c]);
+        const h2_t l0 = __builtin_bit_cast(h2_t, raw[6 + c]), l1 = __builtin_bit_cast(h2_t, raw[9 + c]);
+        if (mu == 0) {  // u0 - sg i l1, u1 - sg i l0
+          h[c] = {fmaf(k, (float)l1.y, (float)u0.x), fmaf(-k, (float)l1.x, (float)u0.y)};
+          h[3 + c] = {fmaf(k, (float)l0.y, (float)u1.x), fmaf(-k, (float)l0.x, (float)u1.y)};
+        } else if (mu == 1) {  // u0 - sg l1, u1 + sg l0
+          h[c] = {fmaf(-k, (float)l1.x, (float)u0.x), fmaf(-k, (float)l1.y, (float)u0.y)};
+          h[3 + c] = {fmaf(k, (float)l0.x, (float)u1.x), fmaf(k, (float)l0.y, (float)u1.y)};
+        } else if (mu == 2) {  // u0 - sg i l0, u1 + sg i l1
+          h[c] = {fmaf(k, (float)l0.y, (float)u0.x), fmaf(-k, (float)l0.x, (float)u0.y)};
+          h[3 + c] = {fmaf(-k, (float)l1.y, (float)u1.x), fmaf(k, (float)l1.x, (float)u1.y)};
+        } else {  // u0 + sg l0, u1 + sg l1
+          h[c] = {fmaf(k, (float)l0.x, (float)u0.x), fmaf(k, (float)l0.y, (float)u0.y)};
+          h[3 + c] = {fmaf(k, (float)l1.x, (float)u1.x), fmaf(k, (float)l1.y, (float)u1.y)};
+        }
+      }
+    } else
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const cx<R> u0 = sp[c], u1 = sp[3 + c], l0 = sp[6 + c], l1 = sp[9 + c];
@@ -193,23 +258,25 @@ __device__ __forceinline__ void hop_site(const HopArgs& a, const FD& fin, int r,
       }
 #pragma unroll
     for (int c = 0; c < 6; ++c) asm volatile("" : "+v"(gv[c].r), "+v"(gv[c].i));
+    // acc += scl * [g ; sg A^dag g]
+    const R ps = scl, ms = sg * scl;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const cx<R> g0 = gv[c], g1 = gv[3 + c];
-      acc[c] = acc[c] + g0;
-      acc[3 + c] = acc[3 + c] + g1;
+      acc[c] = cfma_r(ps, g0, acc[c]);
+      acc[3 + c] = cfma_r(ps, g1, acc[3 + c]);
       if (mu == 0) {  // A^dag g = (i g1, i g0)
-        acc[6 + c] = acc[6 + c] + sg * mul_i(g1);
-        acc[9 + c] = acc[9 + c] + sg * mul_i(g0);
+        acc[6 + c] = cfma_r(ms, mul_i(g1), acc[6 + c]);
+        acc[9 + c] = cfma_r(ms, mul_i(g0), acc[9 + c]);
       } else if (mu == 1) {  // A^dag g = (g1, -g0)
-        acc[6 + c] = acc[6 + c] + sg * g1;
-        acc[9 + c] = acc[9 + c] - sg * g0;
+        acc[6 + c] = cfma_r(ms, g1, acc[6 + c]);
+        acc[9 + c] = cfma_r(-ms, g0, acc[9 + c]);
       } else if (mu == 2) {  // A^dag g = (i g0, -i g1)
-        acc[6 + c] = acc[6 + c] + sg * mul_i(g0);
-        acc[9 + c] = acc[9 + c] - sg * mul_i(g1);
+        acc[6 + c] = cfma_r(ms, mul_i(g0), acc[6 + c]);
+        acc[9 + c] = cfma_r(-ms, mul_i(g1), acc[9 + c]);
       } else {
-        acc[6 + c] = acc[6 + c] + sg * g0;
-        acc[9 + c] = acc[9 + c] + sg * g1;
+        acc[6 + c] = cfma_r(ms, g0, acc[6 + c]);
+        acc[9 + c] = cfma_r(ms, g1, acc[9 + c]);
       }
     }
   }
@@ -334,9 +401,14 @@ hop_kernel(HopArgs a) {
   // reads were mostly fetched by the same XCD (a bijection of [0, gridDim.x)).
   const int nblk = gridDim.x, xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
   const int tile = xcd * (nblk / 8) + min(xcd, nblk % 8) + slot;
-  const int i0 = tile * SBk;
-  const int i = i0 + wave * G + g;
-  const bool live = in_col && (i < Vh);
+  // the tile's sites are positions k0 .. k0+SBk-1 of the traversal order
+  // (a.order: position -> checkerboard index), which visits the lattice in
+  // small (y, z, t) blocks of x-rows so that the neighbours a tile reads were
+  // fetched recently by the same XCD
+  const int k0 = tile * SBk;
+  const int kk = k0 + wave * G + g;
+  const bool live = in_col && (kk < Vh);
+  const int i = a.order[live ? kk : k0];
   const FD fd = {Ls, Vh, a.nrhs};
 
   constexpr bool DENSE = RT::AM == A_MAT || RT::AM == A_MATDT;
@@ -356,12 +428,12 @@ hop_kernel(HopArgs a) {
   for (int j = tid; j < SBk * 72; j += nthr) {
     const int site = j / 72, k = j - site * 72;
     cx<R> v = {R(0), R(0)};
-    if (i0 + site < Vh) v = ld_link<P>(a.links, (size_t)(i0 + site) * 72 + k);
+    if (k0 + site < Vh) v = ld_link<P>(a.links, (size_t)a.order[k0 + site] * 72 + k);
     s_link[site * LSTR + k] = v;
   }
   for (int j = tid; j < SBk * 8; j += nthr) {
     const int site = j / 8, k = j - site * 8;
-    s_nbr[site * NSTR + k] = (i0 + site < Vh) ? a.nbr[(size_t)(i0 + site) * 8 + k] : 0;
+    s_nbr[site * NSTR + k] = (k0 + site < Vh) ? a.nbr[(size_t)a.order[k0 + site] * 8 + k] : 0;
   }
 
   const int rb0 = blockIdx.y * a.rhs_block;
@@ -428,7 +500,7 @@ hop_kernel(HopArgs a) {
       // + M_ee y (B_MEE) or + M_ee^T y (B_MEET):
       //   bee y - cee L y (L^T y) + sk u e_{s*}^T y (sk e_{s*} u^T y) on chirality chi
       cx<R> y[12], t[12];
-      ld_spinor<P>(a.y, fd, r, s, live ? i : i0, y);
+      ld_spinor<P>(a.y, fd, r, s, i, y);
       lmul<R, RT::BM == B_MEET>(y, t, nb);
       const R bee = (R)a.bee, cee = (R)a.cee;
 #pragma unroll

@@ -36,6 +36,8 @@ struct eofa_net {
   std::vector<void*> act;
   void* gbuf[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   void* zero = nullptr;      // an all-zero one-channel half field
+  void* ay = nullptr;        // residual loss: A y, then (A y - r)/|r|^2 (one channel)
+  void* dg = nullptr;
   double* partial = nullptr;
   size_t partial_n = 0;
   double* dev_scalars = nullptr;  // |e|^2 per pair
@@ -84,8 +86,11 @@ void free_acts(eofa_net* N) {
         (void)hipFree(b);
         b = nullptr;
       }
-  if (N->zero) (void)hipFree(N->zero);
-  N->zero = nullptr;
+  for (void** b : {&N->zero, &N->ay, &N->dg})
+    if (*b) {
+      (void)hipFree(*b);
+      *b = nullptr;
+    }
   N->sized_for = 0;
 }
 
@@ -101,6 +106,8 @@ int ensure_acts(eofa_ctx* C, eofa_net* N, hipStream_t st) {
   for (auto& a : N->gbuf)
     for (auto& b : a) NCHK(dmalloc(&b, half_bytes(C->g, cmax)));
   NCHK(dmalloc(&N->zero, half_bytes(C->g, 1)));
+  NCHK(dmalloc(&N->ay, half_bytes(C->g, 1)));
+  NCHK(dmalloc(&N->dg, half_bytes(C->g, 1)));
   NHIP(hipMemsetAsync(N->zero, 0, half_bytes(C->g, 1), st));
   const size_t pn = WGRAD_PARTIAL;
   const size_t ln = (size_t)(C->g.Vh * C->g.Ls + 255) / 256;
@@ -160,20 +167,30 @@ int net_apply_internal(eofa_ctx* C, eofa_net* N, const void* in, void* out, hipS
 namespace {
 
 // forward + backward of one pair; gradients accumulated into N->gw; the
-// pair's |y - e|^2 partial sums land in N->partial (reduced by the caller)
-int pair_grad(eofa_ctx* C, eofa_net* N, const void* r, const void* e, const double* enorm, bool first,
-              double* loss_dst, hipStream_t st) {
+// pair's unnormalised loss lands in loss_dst (device). sys == nullptr: error
+// loss |y - e|^2/|e|^2 (enorm = |e|^2); else residual loss |A y - r|^2/|r|^2
+// with A = M^dag M of sys (enorm = |r|^2, e unused).
+int pair_grad(eofa_ctx* C, eofa_net* N, const eofa_system* sys, const void* r, const void* e,
+              const double* enorm, bool first, double* loss_dst, hipStream_t st) {
   const Geometry& g = C->g;
   const size_t hb = half_bytes(g, 1);
   NHIP(hipMemcpyAsync(N->act[1], r, hb, hipMemcpyDeviceToDevice, st));
   NHIP(hipMemcpyAsync(N->act[0], N->zero, hb, hipMemcpyDeviceToDevice, st));
   forward(C, N, st, false);
-  // seed: G_L = (y - e)/|e|^2 on odd, 0 on even
   int cur = 0;
   NHIP(hipMemcpyAsync(N->gbuf[cur][0], N->zero, hb, hipMemcpyDeviceToDevice, st));
-  const int nb = launch_net_loss(g.Vh, g.Ls, (const float*)N->act[2 * N->L + 1], (const float*)e,
-                                 (float*)N->gbuf[cur][1], enorm, loss_partial(N), st);
-  // loss = sum of partials / |e|^2, reduced on the device into loss_dst
+  const float* y = (const float*)N->act[2 * N->L + 1];
+  int nb;
+  if (!sys) {
+    // seed: G_L = (y - e)/|e|^2 on odd, 0 on even
+    nb = launch_net_loss(g.Vh, g.Ls, y, (const float*)e, (float*)N->gbuf[cur][1], enorm, loss_partial(N), st);
+  } else {
+    // seed: G_L = A (A y - r)/|r|^2 on odd, 0 on even
+    NCHK(normal_op_fp32(C, sys, y, N->ay, st));
+    nb = launch_net_loss(g.Vh, g.Ls, (const float*)N->ay, (const float*)r, (float*)N->dg, enorm, loss_partial(N), st);
+    NCHK(normal_op_fp32(C, sys, N->dg, N->gbuf[cur][1], st));
+  }
+  // loss = sum of partials, reduced on the device into loss_dst
   launch_finalize(FIN_NORM, loss_partial(N), nb, 1, CgState{}, loss_dst, st);
   for (int l = N->L - 1; l >= 0; --l) {
     NetGradArgs ga;
@@ -332,18 +349,19 @@ int eofa_net_apply(eofa_ctx* C, eofa_net* N, const void* in, void* out, void* st
   return net_apply_internal(C, N, in, out, (hipStream_t)stream);
 }
 
-int eofa_net_loss_grad(eofa_ctx* C, eofa_net* N, const void* r, const void* e, int32_t npairs, double* loss,
-                       double* grad, void* stream) {
-  if (!C || !N || !r || !e || npairs < 1) return nfail(EOFA_ERR_INVALID, "eofa_net_loss_grad: bad argument");
+int eofa_net_loss_grad(eofa_ctx* C, eofa_net* N, const eofa_system* sys, const void* r, const void* e,
+                       int32_t npairs, double* loss, double* grad, void* stream) {
+  if (!C || !N || !r || (!e && !sys) || npairs < 1)
+    return nfail(EOFA_ERR_INVALID, "eofa_net_loss_grad: bad argument");
   hipStream_t st = (hipStream_t)stream;
   NCHK(ensure_acts(C, N, st));
-  NCHK(pair_norms(C, N, e, npairs, st));
+  NCHK(pair_norms(C, N, sys ? r : e, npairs, st));
   const size_t hb = half_bytes(C->g, 1);
   double* losses;
   NCHK(dmalloc((void**)&losses, sizeof(double) * npairs));
   for (int k = 0; k < npairs; ++k) {
-    const int rc = pair_grad(C, N, (const char*)r + k * hb, (const char*)e + k * hb, N->dev_scalars + k, k == 0,
-                             losses + k, st);
+    const int rc = pair_grad(C, N, sys, (const char*)r + k * hb, sys ? nullptr : (const char*)e + k * hb,
+                             N->dev_scalars + k, k == 0, losses + k, st);
     if (rc != EOFA_OK) {
       (void)hipFree(losses);
       return rc;
@@ -362,13 +380,13 @@ int eofa_net_loss_grad(eofa_ctx* C, eofa_net* N, const void* r, const void* e, i
   return EOFA_OK;
 }
 
-int eofa_net_train(eofa_ctx* C, eofa_net* N, const void* r, const void* e, int32_t npairs, int32_t epochs,
-                   int32_t batch, double lr, double* loss_per_epoch, void* stream) {
-  if (!C || !N || !r || !e || npairs < 1 || epochs < 1 || batch < 1 || !(lr > 0.0))
+int eofa_net_train(eofa_ctx* C, eofa_net* N, const eofa_system* sys, const void* r, const void* e, int32_t npairs,
+                   int32_t epochs, int32_t batch, double lr, double* loss_per_epoch, void* stream) {
+  if (!C || !N || !r || (!e && !sys) || npairs < 1 || epochs < 1 || batch < 1 || !(lr > 0.0))
     return nfail(EOFA_ERR_INVALID, "eofa_net_train: bad argument");
   hipStream_t st = (hipStream_t)stream;
   NCHK(ensure_acts(C, N, st));
-  NCHK(pair_norms(C, N, e, npairs, st));
+  NCHK(pair_norms(C, N, sys ? r : e, npairs, st));
   const size_t hb = half_bytes(C->g, 1);
   double* losses;
   NCHK(dmalloc((void**)&losses, sizeof(double) * npairs));
@@ -377,8 +395,8 @@ int eofa_net_train(eofa_ctx* C, eofa_net* N, const void* r, const void* e, int32
     for (int b0 = 0; b0 < npairs; b0 += batch) {
       const int b1 = std::min(npairs, b0 + batch);
       for (int k = b0; k < b1; ++k) {
-        const int rc = pair_grad(C, N, (const char*)r + k * hb, (const char*)e + k * hb, N->dev_scalars + k,
-                                 k == b0, losses + k, st);
+        const int rc = pair_grad(C, N, sys, (const char*)r + k * hb, sys ? nullptr : (const char*)e + k * hb,
+                                 N->dev_scalars + k, k == b0, losses + k, st);
         if (rc != EOFA_OK) {
           (void)hipFree(losses);
           return rc;

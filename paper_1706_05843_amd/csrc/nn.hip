@@ -43,102 +43,149 @@ __device__ __forceinline__ void link_mul(const float2* L, cx<float>* z) {
   }
 }
 
+// One thread: one 5D site (i, s) of the output parity and a block of CB
+// output channels c0 .. c0+CB-1. For each stencil term t the input channels
+// are mixed first (z_c = sum_c' W[t][c][c'] X_c'(neighbour)) and the CB mixed
+// spinors are then transported (one link product per term and channel), so
+// every input spinor is loaded once per channel block.
+constexpr int NET_CB = 4;
+
 template <bool ADJ>
 __global__ void __launch_bounds__(256) pt_layer_kernel(NetLayerArgs a) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int c = blockIdx.y;
+  const int c0 = blockIdx.y * NET_CB;
   if (idx >= a.Vh * a.Ls) return;
   const int i = idx / a.Ls, s = idx - i * a.Ls;
   const int p = a.parity;
+  const int nco = min(NET_CB, a.Cout - c0);
   const FD fin = {a.Ls, a.Vh, a.Cin};
-  cx<float> acc[12];
+  cx<float> acc[NET_CB][12];
 #pragma unroll
-  for (int k = 0; k < 12; ++k) acc[k] = {0.f, 0.f};
+  for (int cc = 0; cc < NET_CB; ++cc)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[cc][k] = {0.f, 0.f};
   for (int t = 0; t < 9; ++t) {
     const int j = t == 0 ? i : a.nbr[(size_t)i * 8 + t - 1];
     const float* src = a.xin[t == 0 ? p : 1 - p];
-    cx<float> z[12];
+    cx<float> z[NET_CB][12];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) z[k] = {0.f, 0.f};
+    for (int cc = 0; cc < NET_CB; ++cc)
+#pragma unroll
+      for (int k = 0; k < 12; ++k) z[cc][k] = {0.f, 0.f};
     for (int ci = 0; ci < a.Cin; ++ci) {
-      size_t k;
-      float wr, wi;
-      if (!ADJ) {
-        k = (((size_t)t * a.Cout + c) * a.Cin + ci) * 2;
-        wr = bf16_to_f32(a.w[k]);
-        wi = bf16_to_f32(a.w[k + 1]);
-      } else {  // forward layer had C_out = a.Cin, C_in = a.Cout
-        k = (((size_t)swap_term(t) * a.Cin + ci) * a.Cout + c) * 2;
-        wr = bf16_to_f32(a.w[k]);
-        wi = -bf16_to_f32(a.w[k + 1]);
-      }
       cx<float> v[12];
       ld_spinor<P32>(src, fin, ci, s, j, v);
-      const cx<float> w = {wr, wi};
 #pragma unroll
-      for (int q = 0; q < 12; ++q) z[q] = cfma(w, v[q], z[q]);
+      for (int cc = 0; cc < NET_CB; ++cc) {
+        if (cc >= nco) break;
+        const int c = c0 + cc;
+        size_t k;
+        float wr, wi;
+        if (!ADJ) {
+          k = (((size_t)t * a.Cout + c) * a.Cin + ci) * 2;
+          wr = bf16_to_f32(a.w[k]);
+          wi = bf16_to_f32(a.w[k + 1]);
+        } else {  // forward layer had C_out = a.Cin, C_in = a.Cout
+          k = (((size_t)swap_term(t) * a.Cin + ci) * a.Cout + c) * 2;
+          wr = bf16_to_f32(a.w[k]);
+          wi = -bf16_to_f32(a.w[k + 1]);
+        }
+        const cx<float> w = {wr, wi};
+#pragma unroll
+        for (int q = 0; q < 12; ++q) z[cc][q] = cfma(w, v[q], z[cc][q]);
+      }
     }
-    if (t > 0) link_mul((const float2*)a.links + ((size_t)i * 8 + t - 1) * 9, z);
 #pragma unroll
-    for (int q = 0; q < 12; ++q) acc[q] = acc[q] + z[q];
+    for (int cc = 0; cc < NET_CB; ++cc) {
+      if (cc >= nco) break;
+      if (t > 0) link_mul((const float2*)a.links + ((size_t)i * 8 + t - 1) * 9, z[cc]);
+#pragma unroll
+      for (int q = 0; q < 12; ++q) acc[cc][q] = acc[cc][q] + z[cc][q];
+    }
   }
   const FD fo = {a.Ls, a.Vh, a.Cout};
-  st_spinor<P32>(a.yout, fo, c, s, i, acc);
+#pragma unroll
+  for (int cc = 0; cc < NET_CB; ++cc) {
+    if (cc >= nco) break;
+    st_spinor<P32>(a.yout, fo, c0 + cc, s, i, acc[cc]);
+  }
 }
 
-// dL/dW*[t][c][c'] partial sums: sum over sites of G_c(x) . conj((T_t X_c')(x))
+// dL/dW*[t][c][ci] partial sums: sum over sites of G_c(x) . conj((T_t X_ci)(x)).
+// Work-group (blk, t*ncb + cb, parity): term t, output channels
+// cb*NET_CB .. +NET_CB-1, all input channels; each thread loads its site's
+// G_c once and each transported input once per channel block.
 __global__ void __launch_bounds__(256) pt_wgrad_kernel(NetGradArgs a) {
-  const int y = blockIdx.y;  // t * Cin + ci
-  const int t = y / a.Cin, ci = y - t * a.Cin;
+  const int ncb = (a.Cout + NET_CB - 1) / NET_CB;
+  const int t = blockIdx.y / ncb, cb = blockIdx.y - t * ncb;
+  const int c0 = cb * NET_CB;
+  const int nco = min(NET_CB, a.Cout - c0);
   const int p = blockIdx.z;
   const FD fx = {a.Ls, a.Vh, a.Cin}, fg = {a.Ls, a.Vh, a.Cout};
-  float ar[NET_MAXC], ai[NET_MAXC];
+  float ar[NET_CB][NET_MAXC], ai[NET_CB][NET_MAXC];
 #pragma unroll
-  for (int c = 0; c < NET_MAXC; ++c) ar[c] = ai[c] = 0.f;
+  for (int cc = 0; cc < NET_CB; ++cc)
+#pragma unroll
+    for (int ci = 0; ci < NET_MAXC; ++ci) ar[cc][ci] = ai[cc][ci] = 0.f;
   const int n = a.Vh * a.Ls;
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += gridDim.x * blockDim.x) {
     const int i = idx / a.Ls, s = idx - i * a.Ls;
     const int j = t == 0 ? i : a.nbr[p][(size_t)i * 8 + t - 1];
-    cx<float> v[12];
-    ld_spinor<P32>(a.x[t == 0 ? p : 1 - p], fx, ci, s, j, v);
-    if (t > 0) link_mul((const float2*)a.links[p] + ((size_t)i * 8 + t - 1) * 9, v);
+    cx<float> g[NET_CB][12];
 #pragma unroll
-    for (int c = 0; c < NET_MAXC; ++c) {
-      if (c >= a.Cout) break;
-      cx<float> g[12];
-      ld_spinor<P32>(a.g[p], fg, c, s, i, g);
-      float sr = 0.f, si = 0.f;
+    for (int cc = 0; cc < NET_CB; ++cc) {
+      if (cc >= nco) break;
+      ld_spinor<P32>(a.g[p], fg, c0 + cc, s, i, g[cc]);
+    }
 #pragma unroll
-      for (int q = 0; q < 12; ++q) {  // g * conj(v)
-        sr = fmaf(g[q].r, v[q].r, fmaf(g[q].i, v[q].i, sr));
-        si = fmaf(g[q].i, v[q].r, fmaf(-g[q].r, v[q].i, si));
+    for (int ci = 0; ci < NET_MAXC; ++ci) {
+      if (ci >= a.Cin) break;
+      cx<float> v[12];
+      ld_spinor<P32>(a.x[t == 0 ? p : 1 - p], fx, ci, s, j, v);
+      if (t > 0) link_mul((const float2*)a.links[p] + ((size_t)i * 8 + t - 1) * 9, v);
+#pragma unroll
+      for (int cc = 0; cc < NET_CB; ++cc) {
+        if (cc >= nco) break;
+        float sr = 0.f, si = 0.f;
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {  // g * conj(v)
+          sr = fmaf(g[cc][q].r, v[q].r, fmaf(g[cc][q].i, v[q].i, sr));
+          si = fmaf(g[cc][q].i, v[q].r, fmaf(-g[cc][q].r, v[q].i, si));
+        }
+        ar[cc][ci] += sr;
+        ai[cc][ci] += si;
       }
-      ar[c] += sr;
-      ai[c] += si;
     }
   }
-  __shared__ double red[4][2 * NET_MAXC];
+  // reduce the NET_CB x C_in complex sums over the work-group
+  __shared__ double red[4][2 * NET_CB * NET_MAXC];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int c = 0; c < NET_MAXC; ++c) {
-    if (c >= a.Cout) break;
-    double vr = ar[c], vi = ai[c];
+  for (int cc = 0; cc < NET_CB; ++cc)
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      vr += __shfl_xor(vr, off, 64);
-      vi += __shfl_xor(vi, off, 64);
+    for (int ci = 0; ci < NET_MAXC; ++ci) {
+      if (cc >= nco || ci >= a.Cin) continue;
+      double vr = ar[cc][ci], vi = ai[cc][ci];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        vr += __shfl_xor(vr, off, 64);
+        vi += __shfl_xor(vi, off, 64);
+      }
+      if (lane == 0) {
+        red[wv][2 * (cc * NET_MAXC + ci)] = vr;
+        red[wv][2 * (cc * NET_MAXC + ci) + 1] = vi;
+      }
     }
-    if (lane == 0) {
-      red[wv][2 * c] = vr;
-      red[wv][2 * c + 1] = vi;
-    }
-  }
   __syncthreads();
-  if (threadIdx.x < 2 * a.Cout) {
-    double tsum = 0.0;
-    for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) tsum += red[w][threadIdx.x];
-    const int c = threadIdx.x / 2, comp = threadIdx.x & 1;
-    a.partial[((((size_t)y * 2 + p) * a.Cout + c) * gridDim.x + blockIdx.x) * 2 + comp] = tsum;
+  const int k = threadIdx.x;  // (cc, ci, comp)
+  if (k < 2 * NET_CB * NET_MAXC) {
+    const int comp = k & 1, cc = (k >> 1) / NET_MAXC, ci = (k >> 1) % NET_MAXC;
+    if (cc < nco && ci < a.Cin) {
+      double tsum = 0.0;
+      for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) tsum += red[w][k];
+      const int y = t * a.Cin + ci, c = c0 + cc;
+      a.partial[((((size_t)y * 2 + p) * a.Cout + c) * gridDim.x + blockIdx.x) * 2 + comp] = tsum;
+    }
   }
 }
 
@@ -290,6 +337,18 @@ __global__ void cxpby_dev_kernel(int n, const double2* z, const double* beta, do
   p[k] = make_double2(zz.x + br * a.x - bi * a.y, zz.y + br * a.y + bi * a.x);
 }
 
+// y += alpha x  (alpha complex, on the device)
+__global__ void caxpy_dev_kernel(int n, const double* alpha, const double2* x, double2* y) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double ar = alpha[0], ai = alpha[1];
+  const double2 a = x[k];
+  double2 b = y[k];
+  b.x += ar * a.x - ai * a.y;
+  b.y += ar * a.y + ai * a.x;
+  y[k] = b;
+}
+
 // x += alpha p, r -= alpha q, s -= alpha w; partial |r|^2 and |s|^2 per block
 __global__ void __launch_bounds__(256) fgcg_update_kernel(int n, const double* alpha, double2* x, double2* r,
                                                           double2* s, const double2* p, const double2* q,
@@ -332,7 +391,7 @@ __global__ void __launch_bounds__(256) fgcg_update_kernel(int n, const double* a
 // ---------------------------------------------------------------------------
 
 void launch_pt_layer(const NetLayerArgs& a, bool adj, hipStream_t st) {
-  dim3 grid((a.Vh * a.Ls + 255) / 256, a.Cout);
+  dim3 grid((a.Vh * a.Ls + 255) / 256, (a.Cout + NET_CB - 1) / NET_CB);
   if (adj)
     hipLaunchKernelGGL(pt_layer_kernel<true>, grid, dim3(256), 0, st, a);
   else
@@ -340,7 +399,7 @@ void launch_pt_layer(const NetLayerArgs& a, bool adj, hipStream_t st) {
 }
 
 void launch_pt_wgrad(const NetGradArgs& a, int nblk, int accumulate, double* gw, hipStream_t st) {
-  dim3 grid(nblk, 9 * a.Cin, 2);
+  dim3 grid(nblk, 9 * ((a.Cout + NET_CB - 1) / NET_CB), 2);
   hipLaunchKernelGGL(pt_wgrad_kernel, grid, dim3(256), 0, st, a);
   const int n = 9 * a.Cout * a.Cin * 2;
   hipLaunchKernelGGL(pt_wgrad_final, dim3((n + 255) / 256), dim3(256), 0, st, a.partial, a.Cin, a.Cout, nblk,
@@ -392,6 +451,11 @@ void launch_fgcg_ratio(const double* num, const double* den, double sign, double
 void launch_cxpby_dev(int n, const void* z, const double* beta, void* p, hipStream_t st) {
   hipLaunchKernelGGL(cxpby_dev_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, (const double2*)z, beta,
                      (double2*)p);
+}
+
+void launch_caxpy_dev(int n, const double* alpha, const void* x, void* y, hipStream_t st) {
+  hipLaunchKernelGGL(caxpy_dev_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, alpha, (const double2*)x,
+                     (double2*)y);
 }
 
 int launch_fgcg_update(int n, const double* alpha, void* x, void* r, void* s, const void* p, const void* q,

@@ -40,6 +40,7 @@ void launch_cxpby(int n, const void* z, double br, double bi, void* p, hipStream
 void launch_sub_from(size_t n, const float* xs, float* e, hipStream_t st);
 void launch_fgcg_ratio(const double* num, const double* den, double sign, double* out, int* bad, hipStream_t st);
 void launch_cxpby_dev(int n, const void* z, const double* beta, void* p, hipStream_t st);
+void launch_caxpy_dev(int n, const double* alpha, const void* x, void* y, hipStream_t st);
 // returns the number of blocks; partial holds [2][nblk] (|r|^2 then |s|^2)
 int launch_fgcg_update(int n, const double* alpha, void* x, void* r, void* s, const void* p, const void* q,
                        const void* w, double* partial, hipStream_t st);

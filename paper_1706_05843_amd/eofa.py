@@ -40,7 +40,7 @@ class SolverParams(ctypes.Structure):
                 ("inner_prec", ctypes.c_int32), ("inner_tol", ctypes.c_double),
                 ("fixed_iters", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("rhs_block", ctypes.c_int32),
-                ("waves", ctypes.c_int32), ("precond", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("waves", ctypes.c_int32), ("precond", ctypes.c_int32), ("fcg_window", ctypes.c_int32),
                 ("net", ctypes.c_void_p)]
 
 
@@ -95,9 +95,10 @@ def lib():
         "eofa_net_get_weights": ([_P, ctypes.POINTER(ctypes.c_double)], _I),
         "eofa_net_set_weights": ([_P, ctypes.POINTER(ctypes.c_double)], _I),
         "eofa_net_apply": ([_P, _P, _P, _P, _P], _I),
-        "eofa_net_loss_grad": ([_P, _P, _P, _P, _I, ctypes.POINTER(ctypes.c_double),
+        "eofa_net_loss_grad": ([_P, _P, ctypes.POINTER(System), _P, _P, _I, ctypes.POINTER(ctypes.c_double),
                                 ctypes.POINTER(ctypes.c_double), _P], _I),
-        "eofa_net_train": ([_P, _P, _P, _P, _I, _I, _I, ctypes.c_double, ctypes.POINTER(ctypes.c_double), _P], _I),
+        "eofa_net_train": ([_P, _P, ctypes.POINTER(System), _P, _P, _I, _I, _I, ctypes.c_double,
+                            ctypes.POINTER(ctypes.c_double), _P], _I),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -142,13 +143,13 @@ def make_systems(systems):
 
 def make_params(tol=1e-10, max_iter=100000, max_outer=20, inner_prec=FP64, inner_tol=0.0,
                 fixed_iters=0, check_every=16, profile=0, use_graph=0, rhs_block=0, waves=0,
-                precond=0, net=None):
+                precond=0, net=None, fcg_window=0):
     """Solver parameters; ``net`` (a Net, or None for the identity) is used when precond = 1."""
     p = SolverParams()
     p.tol, p.max_iter, p.max_outer, p.inner_prec = tol, max_iter, max_outer, inner_prec
     p.inner_tol, p.fixed_iters, p.check_every, p.profile = inner_tol, fixed_iters, check_every, profile
     p.use_graph, p.rhs_block, p.waves = use_graph, rhs_block, waves
-    p.precond = precond
+    p.precond, p.fcg_window = precond, fcg_window
     p.net = net._h.value if net is not None else None
     p._net_ref = net  # keeps the network alive as long as the parameters
     return p
@@ -304,13 +305,14 @@ class Net:
     def apply(self, ctx, inp, out, stream=None):
         _check(lib().eofa_net_apply(ctx._h, self._h, _p(inp), _p(out), _stream(stream)))
 
-    def loss_grad(self, ctx, r, e, npairs, stream=None):
-        """(loss, [dL/dW* per layer]) over npairs packed FP32 pairs."""
+    def loss_grad(self, ctx, r, e, npairs, system=None, stream=None):
+        """(loss, [dL/dW* per layer]) over npairs packed FP32 pairs; with ``system``
+        the residual loss |A N(r) - r|^2/|r|^2 (e unused), else the error loss."""
         n = self.num_weights()
         loss = ctypes.c_double()
         g = (ctypes.c_double * (2 * n))()
-        _check(lib().eofa_net_loss_grad(ctx._h, self._h, _p(r), _p(e), npairs, ctypes.byref(loss), g,
-                                        _stream(stream)))
+        _check(lib().eofa_net_loss_grad(ctx._h, self._h, _sys_or_null(system), _p(r), _p_or_null(e), npairs,
+                                        ctypes.byref(loss), g, _stream(stream)))
         flat = np.frombuffer(g, dtype=np.float64).copy()
         flat = flat[0::2] + 1j * flat[1::2]
         out, k = [], 0
@@ -319,13 +321,22 @@ class Net:
             k += 9 * co * ci
         return loss.value, out
 
-    def train(self, ctx, r, e, npairs, epochs, batch, lr, stream=None):
-        """Adam on the pairs; returns the mean loss per pair of every epoch."""
+    def train(self, ctx, r, e, npairs, epochs, batch, lr, system=None, stream=None):
+        """Adam on the pairs (residual loss with ``system``); returns the mean loss
+        per pair of every epoch."""
         hist = (ctypes.c_double * epochs)()
-        _check(lib().eofa_net_train(ctx._h, self._h, _p(r), _p(e), npairs, epochs, batch, lr, hist,
-                                    _stream(stream)))
+        _check(lib().eofa_net_train(ctx._h, self._h, _sys_or_null(system), _p(r), _p_or_null(e), npairs, epochs,
+                                    batch, lr, hist, _stream(stream)))
         return list(hist)
 
 
 def _p(t):
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _p_or_null(t):
+    return None if t is None else _p(t)
+
+
+def _sys_or_null(system):
+    return None if system is None else make_systems([system])

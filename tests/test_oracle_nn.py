@@ -52,6 +52,35 @@ def test_gradients_match_finite_differences():
                 assert abs(fd - an) < 1e-6 * max(1.0, abs(an)), (layer_k, idx, comp, fd, an)
 
 
+def test_residual_loss_gradients_match_finite_differences():
+    """Residual loss sum |A N(r) - r|^2/|r|^2 with A = M^dag M of a Schur system."""
+    act = Action(DIMS, LS, 1.8, 1.5, 0.5, BC)
+    U = synth.gauge_field(DIMS, 0.8, seed=21)
+    S = eo.SchurSystem(act, U, System(0.2))
+    A = lambda x: S.mhat_adj(S.mhat(x))
+    Ws = _weights([1, 2, 1], 22, scale=0.2)
+    rs = [restrict(_field(130 + k), DIMS, 1) for k in range(2)]
+    L, grads = nn.residual_loss_and_grads(U, Ws, rs, A, DIMS, BC)
+    # the loss is what its definition says
+    Lref = sum(norm2(A(nn.forward(U, Ws, r, DIMS, BC)[0]) - r) / norm2(r) for r in rs)
+    assert abs(L - Lref) < 1e-12 * Lref
+    rng = np.random.default_rng(23)
+    h = 1e-6
+    for layer_k in range(2):
+        for _ in range(3):
+            idx = tuple(int(rng.integers(0, n)) for n in Ws[layer_k].shape)
+            for comp, unit in (("re", 1.0), ("im", 1j)):
+                Wp = [w.copy() for w in Ws]
+                Wm = [w.copy() for w in Ws]
+                Wp[layer_k][idx] += unit * h
+                Wm[layer_k][idx] -= unit * h
+                fd = (nn.residual_loss_and_grads(U, Wp, rs, A, DIMS, BC)[0]
+                      - nn.residual_loss_and_grads(U, Wm, rs, A, DIMS, BC)[0]) / (2 * h)
+                g = grads[layer_k][idx]
+                an = 2 * (g.real if comp == "re" else g.imag)
+                assert abs(fd - an) < 1e-6 * max(1.0, abs(an)), (layer_k, idx, comp, fd, an)
+
+
 def test_gauge_covariance():
     """N[U^g](g r) = g N[U](r)."""
     U = synth.gauge_field(DIMS, 0.8, seed=6)
