@@ -295,12 +295,60 @@ def bench_learned(args, eofa, synth, torch, np):
     print(json.dumps(out), flush=True)
 
 
+def bench_force(args, eofa, synth, torch, np):
+    """EOFA pseudofermion force (eqn eofa_force) on 16^3 x 32, Ls = 16: the two
+    solves chi_1, chi_2 as one batched FP16S/FP64 solve to 1e-10, then the link
+    derivative kernels. Reports the whole force time and the link-derivative
+    kernel alone (HIP events on the stream it runs on) against its compulsory
+    bytes: chi read once (V Ls 192 B), links read and force written once
+    (4 V 144 B each)."""
+    dims, Ls, eps, m1, m2 = (16, 16, 16, 32), 16, 0.5, 0.04, 1.0
+    U = torch.from_numpy(synth.gauge_field(dims, eps, 1001)).cuda()
+    ctx = eofa.Context(eofa.make_action(dims, Ls, 1.8, 1.5, 0.5), U)
+    phi = torch.from_numpy(synth.fermion(dims, Ls, 2001, nrhs=1)).cuda()
+    F = torch.zeros(ctx.gauge_shape(), dtype=torch.complex128, device="cuda")
+    prm = eofa.make_params(tol=1e-10, inner_prec=eofa.FP16S)
+    ctx.eofa_force(m1, m2, phi, F, prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rc, st = ctx.eofa_force(m1, m2, phi, F, prm)
+    torch.cuda.synchronize()
+    t_force = (time.perf_counter() - t0) / args.steps
+    y = torch.zeros_like(F)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ctx.eofa_dhop_derivative(phi, phi, y)
+    reps = 20
+    ev[0].record()
+    for _ in range(reps):
+        ctx.eofa_dhop_derivative(phi, phi, y)
+    ev[1].record()
+    torch.cuda.synchronize()
+    t_k = ev[0].elapsed_time(ev[1]) / reps * 1e-3
+    V = int(np.prod(dims))
+    alg = V * Ls * 192 + 2 * 4 * V * 144
+    out = {
+        "metric": METRIC, "value": round(t_force, 5), "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": round(t_force * 1e3, 3), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{dims[0]}x{dims[1]}x{dims[2]}x{dims[3]} Ls={Ls}, EOFA force m1={m1} m2={m2}, "
+                               f"chi_1, chi_2 by one batched FP16S/FP64 solve to 1e-10", "lattice": list(dims),
+                   "Ls": Ls},
+        "solves": [dict(iters=x["iters"], true_resid=x["true_resid"]) for x in st],
+        "link_derivative_kernel": {"seconds": t_k, "algorithmic_bytes": alg,
+                                   "algorithmic_GBs": round(alg / t_k / 1e9, 1),
+                                   "frac_hbm": round(alg / t_k / 1e9 / HBM_PEAK_GBS, 4)},
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["batched", "learned"])
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["batched", "learned", "force"])
     ap.add_argument("--batched-iters", type=int, default=64)
     ap.add_argument("--inner", default="fp16s", choices=sorted(PREC))
     ap.add_argument("--inner-tol", type=float, default=0.0)
@@ -341,6 +389,9 @@ def main():
         return
     if args.workload == "learned":
         bench_learned(args, eofa, synth, torch, np)
+        return
+    if args.workload == "force":
+        bench_force(args, eofa, synth, torch, np)
         return
 
     dims, Ls, eps, m1, gseed, sseed = WORKLOADS[args.workload]

@@ -125,6 +125,9 @@ typedef struct {
   int32_t fcg_window;  /* precond = 1: previous directions each new one is A-orthogonalised
                           against (1..32; 0 = 8 with a network, 1 without)                     */
   const eofa_net* net; /* precond = 1: network (eofa_net_create), evaluated in FP32             */
+  int32_t use_guess;   /* 1: psi holds an initial guess on entry (canonical layout; the
+                          iteration starts from psi' = D~^-1 psi on the odd sublattice)       */
+  int32_t pad1;
 } eofa_solver_params;
 
 typedef struct {
@@ -181,7 +184,8 @@ int eofa_mooee_inv(eofa_ctx* ctx, const eofa_system* sys, const void* in, void* 
                    int32_t dagger, int32_t prec, int32_t nrhs, void* stream);
 
 /* Solve nrhs independent EOFA systems sys[r] for canonical phi[r] -> psi[r]
- * (device, complex128, canonical layout; psi is output only). Inner CG in
+ * (device, complex128, canonical layout; psi is output only unless
+ * params->use_guess = 1, then it is also the initial guess). Inner CG in
  * params->inner_prec with an FP64 defect-correction outer loop (Sec. VI A);
  * all right-hand sides iterate together in batched kernels, each with its
  * own CG scalars. stats: host array [nrhs] (may be NULL).                */
@@ -199,6 +203,28 @@ int eofa_cg_solve(eofa_ctx* ctx, const eofa_system* sys, const void* phi, void* 
 int eofa_heatbath_solve(eofa_ctx* ctx, double m1, double m2, int32_t n_poles, const double* alpha,
                         const double* beta, const void* eta, void* phi,
                         const eofa_solver_params* params, eofa_solver_stats* stats, void* stream);
+
+/* Link derivative of the hopping term (Sec. IV C): for canonical 5D fields
+ * a, b (device complex128, one right-hand side) and every link (x, mu), the
+ * 3 x 3 complex matrix y_mu(x) such that
+ *   a^dag (d/ds Dhop(U_mu(x) -> e^{s T} U_mu(x)))|_{s=0} b = Tr(T y_mu(x))
+ * for every traceless anti-Hermitian T (Dhop with its -1/2 and the boundary
+ * phases, eqn Ddwf). y: device complex128 [4][Lt][Lz][Ly][Lx][3][3], the
+ * gauge layout; it must not alias a or b. Asynchronous on `stream`.       */
+int eofa_dhop_derivative(eofa_ctx* ctx, const void* a, const void* b, void* y, void* stream);
+
+/* EOFA pseudofermion force (Sec. IV C, eqn eofa_force): for every link
+ *   F_mu(x) = sum_a T^a d/ds S(U_mu(x) -> e^{s T^a} U_mu(x))|_{s=0},
+ *   S = phi^dag M_EOFA phi (eqn eofa_action), T^a = i lambda^a / 2,
+ * i.e. F^a = k (g5 R5 chi_1)^dag dDhop chi_1 - k (g5 R5 chi_2)^dag dDhop chi_2
+ * with chi_1 = H(m1)^-1 Omega_- P_- phi and
+ * chi_2 = [H(m2) - Delta_+(m1,m2) P_+]^-1 Omega_+ P_+ phi, both solved in one
+ * batched call with `params` (precond must be 0). phi: device canonical
+ * complex128 field (only its s = 0 slice enters, through Omega). force:
+ * device complex128 gauge layout, traceless anti-Hermitian matrices.
+ * stats: host [2] (chi_1, chi_2) or NULL. Blocks until done.              */
+int eofa_force(eofa_ctx* ctx, double m1, double m2, const void* phi, void* force,
+               const eofa_solver_params* params, eofa_solver_stats* stats, void* stream);
 
 /* Training pairs for the learned preconditioner (not in the paper). Runs
  * FP64 CG on the normal equations A x = M^dag b~ (A = M^dag M, odd Schur
@@ -262,7 +288,7 @@ int eofa_net_train(eofa_ctx* ctx, eofa_net* net, const eofa_system* sys, const v
 /* Host only (no device work): the fifth-dimension matrix `mat` that the
  * library builds for one system, as out[2][Ls][Ls] (row-major; [0] acts on
  * P_+ psi, [1] on P_- psi). mat: 0 M_ee, 1 M_ee^-1, 2 M_ee^T, 3 M_ee^-T,
- * 4 M_ee^-T D~^T, 5 -D~^T, 6 D~^T, 7 D~ (App. A, App. B.2).
+ * 4 M_ee^-T D~^T, 5 -D~^T, 6 D~^T, 7 D~, 8 D~^-1 (App. A, App. B.2).
  * Returns EOFA_ERR_BREAKDOWN if the Sherman-Morrison denominator vanishes. */
 int eofa_fifth_matrix(const eofa_action* act, const eofa_system* sys, int32_t mat, double* out);
 

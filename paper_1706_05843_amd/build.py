@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libeofa.so")
-SOURCES = ["kernels.hip", "nn.hip", "api.cpp", "coeffs.cpp", "net.cpp"]
+SOURCES = ["kernels.hip", "nn.hip", "force.hip", "api.cpp", "coeffs.cpp", "net.cpp"]
 # packed-FP32 instructions are disabled on purpose: plain scalar/float2 code only
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -35,6 +35,7 @@
 
 #include "internal.h"
 #include "nn_internal.h"
+#include "force_internal.h"
 
 using namespace eofa;
 
@@ -611,7 +612,13 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
     a.out = bt;
     CHK(hop(C, P64, ROLE_SRC, a, st));
   }
-  launch_zero(P64, g, x, nrhs, st);
+  if (prm->use_guess) {
+    // x_o = (D~^-1 psi)_o: the right-preconditioned unknown of the guess
+    launch_pack(P64, g, psi, tmp, 1, nrhs, 0, st);
+    launch_smat(P64, g, tmp, x, C->mats, MAT_DT_INV, nrhs, st);
+  } else {
+    launch_zero(P64, g, x, nrhs, st);
+  }
 
   std::vector<double> rro;
   std::vector<int> hbuf(4 * nrhs);
@@ -661,7 +668,7 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
 
   for (int outer = 0; outer < max_outer; ++outer) {
     // r_o = b~ - M^ x  (FP64)
-    if (outer == 0) {
+    if (outer == 0 && !prm->use_guess) {
       launch_convert(P64, P64, g, bt, ro, nrhs, st);
       CHK(norms(C, P64, ro, nrhs, partial, Sst, rro, st));
     } else {
@@ -1129,6 +1136,16 @@ int fgcg_one(eofa_ctx* C, const eofa_system* sys, const void* phi, void* psi, co
   F.st = st;
   CHK(F.init(sys, phi));
   CHK(F.set_window(prm->fcg_window > 0 ? prm->fcg_window : (net ? 8 : 1)));
+  bool guess_done = false;
+  if (prm->use_guess && std::isfinite(F.bb)) {
+    // start from x_o = (D~^-1 psi)_o: s = b~ - M^ x, r = M^dag s
+    launch_pack(P64, C->g, psi, F.tmp, 1, 1, 0, st);
+    launch_smat(P64, C->g, F.tmp, F.x, C->mats, MAT_DT_INV, 1, st);
+    double s2;
+    CHK(F.true_schur(&s2));
+    CHK(F.normal_residual());
+    guess_done = F.bb > 0.0 && std::sqrt(s2 / F.bb) <= prm->tol;
+  }
   const int check = prm->check_every > 0 ? prm->check_every : 16;
   const int max_restart = std::max(1, prm->max_outer);
   const int stall = std::max(256, 16 * check);  // iterations without a 0.7x gain in |s| before falling back
@@ -1137,7 +1154,7 @@ int fgcg_one(eofa_ctx* C, const eofa_system* sys, const void* phi, void* psi, co
   bool converged = false;
   double best = INFINITY;
   int best_it = 0;
-  if (F.bb == 0.0) converged = true;
+  if (F.bb == 0.0 || guess_done) converged = true;
   while (!fallback && !converged) {
     CHK(F.iterate(net));
     ++it;
@@ -1366,10 +1383,92 @@ extern "C" int eofa_heatbath_solve(eofa_ctx* C, double m1, double m2, int32_t n_
   launch_omega_rhs(g, eta, rhs, d_om, d_chir, nsys, st);
   HIPCHK(hipGetLastError());
   std::vector<eofa_solver_stats> st_local(nsys);
-  const int rc = solve_batch(C, sys.data(), nsys, rhs, sol, prm, stats ? stats : st_local.data(), st);
+  eofa_solver_params p2 = *prm;
+  p2.use_guess = 0;  // the pole solutions live in library workspace: no guess
+  const int rc = solve_batch(C, sys.data(), nsys, rhs, sol, &p2, stats ? stats : st_local.data(), st);
   if (rc != EOFA_OK && rc != EOFA_ERR_NOT_CONVERGED) return rc;
   launch_heatbath_combine(g, eta, sol, phi, a_eta, d_coef, d_om, d_chir, nsys, st);
   HIPCHK(hipStreamSynchronize(st));
   HIPCHK(hipGetLastError());
   return rc;
 }
+
+// ---------------------------------------------------------------------------
+// link derivative of the hopping term and the EOFA pseudofermion force
+
+namespace {
+
+DerivArgs deriv_args(eofa_ctx* C, const void* a, const void* b, void* y, double coef, int g5r5_a, int acc) {
+  DerivArgs d;
+  for (int k = 0; k < 4; ++k) d.L[k] = C->g.L[k];
+  d.Ls = C->g.Ls;
+  d.Vh = C->g.Vh;
+  d.links[0] = (const double2*)C->links[P64][0];
+  d.links[1] = (const double2*)C->links[P64][1];
+  d.a = (const double2*)a;
+  d.b = (const double2*)b;
+  d.y = (double2*)y;
+  d.coef = coef;
+  d.g5r5_a = g5r5_a;
+  d.accumulate = acc;
+  return d;
+}
+
+}  // namespace
+
+extern "C" int eofa_dhop_derivative(eofa_ctx* C, const void* a, const void* b, void* y, void* stream) {
+  if (!C || !a || !b || !y) return fail(EOFA_ERR_INVALID, "eofa_dhop_derivative: NULL argument");
+  if (y == a || y == b) return fail(EOFA_ERR_INVALID, "eofa_dhop_derivative: y aliases an input");
+  launch_dhop_deriv(deriv_args(C, a, b, y, 1.0, 0, 0), (hipStream_t)stream);
+  HIPCHK(hipGetLastError());
+  return EOFA_OK;
+}
+
+extern "C" int eofa_force(eofa_ctx* C, double m1, double m2, const void* phi, void* force,
+                          const eofa_solver_params* prm, eofa_solver_stats* stats, void* stream) {
+  if (!C || !phi || !force) return fail(EOFA_ERR_INVALID, "eofa_force: NULL argument");
+  if (phi == force) return fail(EOFA_ERR_INVALID, "eofa_force: phi and force alias");
+  if (!std::isfinite(m1) || !std::isfinite(m2)) return fail(EOFA_ERR_INVALID, "eofa_force: non-finite mass");
+  CHK(check_params(prm));
+  if (prm->precond != 0) return fail(EOFA_ERR_INVALID, "eofa_force: precond must be 0 (batched CGNR)");
+  hipStream_t st = (hipStream_t)stream;
+  const Geometry& g = C->g;
+  // chi_1 = H(m1)^-1 Omega_- P_- phi,  chi_2 = [H(m2) - Delta_+(m1,m2) P_+]^-1 Omega_+ P_+ phi
+  eofa_system sys[2] = {eofa_system{m1, m1, m2, 0.0, -1}, eofa_system{m2, m1, m2, -1.0, +1}};
+  std::vector<double> om(2 * g.Ls);
+  omega_col(g.Ls, C->c, C->d, -1, om.data());
+  omega_col(g.Ls, C->c, C->d, +1, om.data() + g.Ls);
+  const int chir[2] = {-1, +1};
+  const size_t fbytes = (size_t)g.Ls * g.V * 12 * 16;
+  void *rhs, *chi, *cdev;
+  CHK(ws(C, "fo_rhs", 2 * fbytes, &rhs));
+  CHK(ws(C, "fo_chi", 2 * fbytes, &chi));
+  const size_t cbytes = sizeof(double) * 2 * g.Ls + sizeof(int) * 2;
+  CHK(ws(C, "fo_coef", cbytes, &cdev));
+  CHK(stage(C, cbytes));
+  {
+    std::vector<unsigned char> h(cbytes);
+    std::memcpy(h.data(), om.data(), sizeof(double) * 2 * g.Ls);
+    std::memcpy(h.data() + sizeof(double) * 2 * g.Ls, chir, sizeof(int) * 2);
+    CHK(put(C, cdev, h.data(), cbytes, st));
+  }
+  const double* d_om = (const double*)cdev;
+  const int* d_chir = (const int*)(d_om + 2 * g.Ls);
+  launch_omega_rhs(g, phi, rhs, d_om, d_chir, 2, st);
+  HIPCHK(hipGetLastError());
+  std::vector<eofa_solver_stats> local(2);
+  eofa_solver_params p2 = *prm;
+  p2.use_guess = 0;  // chi_1, chi_2 live in library workspace: no guess
+  const int rc = solve_batch(C, sys, 2, rhs, chi, &p2, stats ? stats : local.data(), st);
+  if (rc != EOFA_OK && rc != EOFA_ERR_NOT_CONVERGED) return rc;
+  // F = sum_a T^a k [ (g5 R5 chi_1)^dag dDhop chi_1 - (g5 R5 chi_2)^dag dDhop chi_2 ]
+  const double k = k_eofa(g.Ls, C->c, C->d, m1, m2);
+  const char* chi2 = (const char*)chi + fbytes;
+  launch_dhop_deriv(deriv_args(C, chi, chi, force, k, 1, 0), st);
+  launch_dhop_deriv(deriv_args(C, chi2, chi2, force, -k, 1, 1), st);
+  launch_force_project((size_t)4 * g.V, force, st);
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+  return rc;
+}
+

@@ -186,6 +186,11 @@ int build_fifth(const Geometry& g, double M5, double b5, double c5, const eofa_s
       for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) Minv[i * n + j] -= sigma * x[i] * vA[j] / den;
     }
+    Mat Dinv;
+    if (!invert(Dt, n, Dinv)) {
+      err = "D~(m_op) is singular";
+      return EOFA_ERR_BREAKDOWN;
+    }
     const Mat DtT = transpose(Dt, n);
     const Mat MinvT = transpose(Minv, n);
     Mat mats[NMAT];
@@ -198,6 +203,7 @@ int build_fifth(const Geometry& g, double M5, double b5, double c5, const eofa_s
     for (auto& v : mats[MAT_NEG_DT_T]) v = -v;
     mats[MAT_DT_T] = DtT;
     mats[MAT_DT] = Dt;
+    mats[MAT_DT_INV] = Dinv;
     for (int m = 0; m < NMAT; ++m)
       std::memcpy(out + ((size_t)m * 2 + ci) * n * n, mats[m].data(), sizeof(double) * n * n);
   }

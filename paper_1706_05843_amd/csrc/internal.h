@@ -25,6 +25,7 @@ enum MatId {
   MAT_NEG_DT_T,        // -D~^T
   MAT_DT_T,            // D~^T
   MAT_DT,              // D~ = (c+d) + (c-d) L(m_op)
+  MAT_DT_INV,          // D~^-1 (initial guesses: psi' = D~^-1 psi)
   NMAT
 };
 

@@ -152,8 +152,6 @@ __device__ __forceinline__ void hop_site(const HopArgs& a, const FD& fin, int r,
     __builtin_amdgcn_sched_barrier(0);
     if constexpr (PF) {
       if (dir < 7) load_dir<P>(a.in, fin, r, s, s_nbr[ls * NSTR + dir + 1], (dir & 1) ? b0 : b1);
-    } else {
-      load_dir<P>(a.in, fin, r, s, s_nbr[ls * NSTR + dir], b0);
     }
     const DirIn<P>& b = (PF && (dir & 1)) ? b1 : b0;
     const int mu = dir & 3;
@@ -187,8 +185,12 @@ __device__ __forceinline__ void hop_site(const HopArgs& a, const FD& fin, int r,
         for (int c = 0; c < 12; ++c) raw[c] = w[c];
       }
     } else {
+      if constexpr (PF) {
 #pragma unroll
-      for (int c = 0; c < 12; ++c) sp[c] = b.v[c];
+        for (int c = 0; c < 12; ++c) sp[c] = b.v[c];
+      } else {
+        ld_spinor<P>(a.in, fin, r, s, s_nbr[ls * NSTR + dir], sp);
+      }
       if constexpr (PRE) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
@@ -408,7 +410,9 @@ hop_kernel(HopArgs a) {
   const int k0 = tile * SBk;
   const int kk = k0 + wave * G + g;
   const bool live = in_col && (kk < Vh);
-  const int i = a.order[live ? kk : k0];
+  // the site index itself is staged in LDS (slot 8 of the neighbour row) and
+  // re-read where it is used, so it occupies no register across the kernel
+  const volatile int* s_self = nullptr;
   const FD fd = {Ls, Vh, a.nrhs};
 
   constexpr bool DENSE = RT::AM == A_MAT || RT::AM == A_MATDT;
@@ -435,6 +439,9 @@ hop_kernel(HopArgs a) {
     const int site = j / 8, k = j - site * 8;
     s_nbr[site * NSTR + k] = (k0 + site < Vh) ? a.nbr[(size_t)a.order[k0 + site] * 8 + k] : 0;
   }
+  for (int site = tid; site < SBk; site += nthr) s_nbr[site * NSTR + 8] = a.order[min(k0 + site, Vh - 1)];
+  s_self = s_nbr + ls * NSTR + 8;
+#define EOFA_SITE (*s_self)
 
   const int rb0 = blockIdx.y * a.rhs_block;
   const int rb1 = min(rb0 + a.rhs_block, a.nrhs);
@@ -500,7 +507,7 @@ hop_kernel(HopArgs a) {
       // + M_ee y (B_MEE) or + M_ee^T y (B_MEET):
       //   bee y - cee L y (L^T y) + sk u e_{s*}^T y (sk e_{s*} u^T y) on chirality chi
       cx<R> y[12], t[12];
-      ld_spinor<P>(a.y, fd, r, s, i, y);
+      ld_spinor<P>(a.y, fd, r, s, EOFA_SITE, y);
       lmul<R, RT::BM == B_MEET>(y, t, nb);
       const R bee = (R)a.bee, cee = (R)a.cee;
 #pragma unroll
@@ -524,18 +531,18 @@ hop_kernel(HopArgs a) {
     double nrm = 0.0;
     if (live) {
       if constexpr (RT::OM == O_STORE) {
-        st_spinor<P>(a.out, fd, r, s, i, v);
+        st_spinor<P>(a.out, fd, r, s, EOFA_SITE, v);
       } else if constexpr (RT::OM == O_ADDZ) {
         cx<R> z[12];
-        ld_spinor<P>(a.z, fd, r, s, i, z);
+        ld_spinor<P>(a.z, fd, r, s, EOFA_SITE, z);
 #pragma unroll
         for (int c = 0; c < 12; ++c) v[c] = z[c] - v[c];
-        st_spinor<P>(a.out, fd, r, s, i, v);
+        st_spinor<P>(a.out, fd, r, s, EOFA_SITE, v);
       } else {
         using RR = typename ST<PR>::R;
         cx<RR> w[12];
         if constexpr (RT::OM == O_RUPD) {
-          ld_spinor<PR>(a.r, fd, r, s, i, w);
+          ld_spinor<PR>(a.r, fd, r, s, EOFA_SITE, w);
           const RR al = (RR)a.alpha[r];
 #pragma unroll
           for (int c = 0; c < 12; ++c) {
@@ -546,7 +553,7 @@ hop_kernel(HopArgs a) {
 #pragma unroll
           for (int c = 0; c < 12; ++c) w[c] = {(RR)v[c].r, (RR)v[c].i};
         }
-        st_spinor<PR>(a.r, fd, r, s, i, w);
+        st_spinor<PR>(a.r, fd, r, s, EOFA_SITE, w);
 #pragma unroll
         for (int c = 0; c < 12; ++c) v[c] = {(R)w[c].r, (R)w[c].i};
       }
@@ -568,6 +575,8 @@ hop_kernel(HopArgs a) {
     }
   }
 }
+
+#undef EOFA_SITE
 
 template <int P>
 constexpr int acc_prec() {

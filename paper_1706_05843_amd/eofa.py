@@ -22,7 +22,7 @@ EOFA_ERR_OOM = -5
 
 FP64, FP32, FP16S = 0, 1, 2
 
-MAT_NAMES = ["mee", "mee_inv", "mee_t", "mee_inv_t", "mee_inv_t_dt_t", "neg_dt_t", "dt_t", "dt"]
+MAT_NAMES = ["mee", "mee_inv", "mee_t", "mee_inv_t", "mee_inv_t_dt_t", "neg_dt_t", "dt_t", "dt", "dt_inv"]
 
 
 class Action(ctypes.Structure):
@@ -41,7 +41,7 @@ class SolverParams(ctypes.Structure):
                 ("fixed_iters", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("rhs_block", ctypes.c_int32),
                 ("waves", ctypes.c_int32), ("precond", ctypes.c_int32), ("fcg_window", ctypes.c_int32),
-                ("net", ctypes.c_void_p)]
+                ("net", ctypes.c_void_p), ("use_guess", ctypes.c_int32), ("pad1", ctypes.c_int32)]
 
 
 class SolverStats(ctypes.Structure):
@@ -87,6 +87,9 @@ def lib():
                                  ctypes.POINTER(SolverStats), _P], _I),
         "eofa_fifth_matrix": ([ctypes.POINTER(Action), ctypes.POINTER(System), _I,
                                ctypes.POINTER(ctypes.c_double)], _I),
+        "eofa_dhop_derivative": ([_P, _P, _P, _P, _P], _I),
+        "eofa_force": ([_P, ctypes.c_double, ctypes.c_double, _P, _P, ctypes.POINTER(SolverParams),
+                        ctypes.POINTER(SolverStats), _P], _I),
         "eofa_cg_pairs": ([_P, ctypes.POINTER(System), _P, _I, _I, _I, ctypes.c_double, _I, _P, _P,
                            ctypes.POINTER(_I), ctypes.POINTER(_I), _P], _I),
         "eofa_net_create": ([_P, _I, ctypes.POINTER(_I), ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(_P)], _I),
@@ -143,13 +146,13 @@ def make_systems(systems):
 
 def make_params(tol=1e-10, max_iter=100000, max_outer=20, inner_prec=FP64, inner_tol=0.0,
                 fixed_iters=0, check_every=16, profile=0, use_graph=0, rhs_block=0, waves=0,
-                precond=0, net=None, fcg_window=0):
+                precond=0, net=None, fcg_window=0, use_guess=0):
     """Solver parameters; ``net`` (a Net, or None for the identity) is used when precond = 1."""
     p = SolverParams()
     p.tol, p.max_iter, p.max_outer, p.inner_prec = tol, max_iter, max_outer, inner_prec
     p.inner_tol, p.fixed_iters, p.check_every, p.profile = inner_tol, fixed_iters, check_every, profile
     p.use_graph, p.rhs_block, p.waves = use_graph, rhs_block, waves
-    p.precond, p.fcg_window = precond, fcg_window
+    p.precond, p.fcg_window, p.use_guess = precond, fcg_window, use_guess
     p.net = net._h.value if net is not None else None
     p._net_ref = net  # keeps the network alive as long as the parameters
     return p
@@ -247,6 +250,20 @@ class Context:
         if rc in (EOFA_ERR_INVALID, EOFA_ERR_HIP, EOFA_ERR_OOM):
             _check(rc)
         return rc, [s.as_dict() for s in stats]
+
+    def eofa_dhop_derivative(self, a, b, y, stream=None):
+        _check(lib().eofa_dhop_derivative(self._h, _p(a), _p(b), _p(y), _stream(stream)))
+
+    def eofa_force(self, m1, m2, phi, force, params, stream=None):
+        stats = (SolverStats * 2)()
+        rc = lib().eofa_force(self._h, m1, m2, _p(phi), _p(force), ctypes.byref(params), stats, _stream(stream))
+        if rc in (EOFA_ERR_INVALID, EOFA_ERR_HIP, EOFA_ERR_OOM):
+            _check(rc)
+        return rc, [s.as_dict() for s in stats]
+
+    def gauge_shape(self):
+        lx, ly, lz, lt = self.dims
+        return (4, lt, lz, ly, lx, 3, 3)
 
     def eofa_cg_pairs(self, system, phi, npairs, first, stride, tol, max_iter, r_out, e_out, stream=None):
         """Training pairs (r_k, e_k) into r_out, e_out (uint8 tensors of npairs packed FP32 odd

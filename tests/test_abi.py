@@ -46,6 +46,7 @@ int main(void) {
   printf("%zu %zu %zu %zu\n", sizeof(eofa_action), sizeof(eofa_system), sizeof(eofa_solver_params), sizeof(eofa_solver_stats));
   printf("%zu %zu %zu %zu %zu\n", offsetof(eofa_action, M5), offsetof(eofa_action, bc), offsetof(eofa_solver_params, inner_tol), offsetof(eofa_solver_stats, hop_ms), offsetof(eofa_solver_params, waves));
   printf("%zu %zu %zu\n", offsetof(eofa_solver_params, precond), offsetof(eofa_solver_params, net), offsetof(eofa_solver_stats, fell_back));
+  printf("%zu\n", offsetof(eofa_solver_params, use_guess));
   return 0;
 }
 '''
@@ -61,7 +62,8 @@ int main(void) {
     assert sizes[4:] == [eofa.Action.M5.offset, eofa.Action.bc.offset,
                          eofa.SolverParams.inner_tol.offset, eofa.SolverStats.hop_ms.offset,
                          eofa.SolverParams.waves.offset, eofa.SolverParams.precond.offset,
-                         eofa.SolverParams.net.offset, eofa.SolverStats.fell_back.offset]
+                         eofa.SolverParams.net.offset, eofa.SolverStats.fell_back.offset,
+                         eofa.SolverParams.use_guess.offset]
 
 
 @pytest.mark.parametrize("bad", [
@@ -89,6 +91,7 @@ def _oracle_mats(Ls, M5, b5, c5, sysd):
         "mee": (Ap, Am), "mee_inv": (Ip, Im), "mee_t": (Ap.T, Am.T), "mee_inv_t": (Ip.T, Im.T),
         "mee_inv_t_dt_t": (Ip.T @ Dp.T, Im.T @ Dm.T), "neg_dt_t": (-Dp.T, -Dm.T),
         "dt_t": (Dp.T, Dm.T), "dt": (Dp, Dm),
+        "dt_inv": (fifth.Dtilde_inv_closed(Ls, c, d, m_op, +1), fifth.Dtilde_inv_closed(Ls, c, d, m_op, -1)),
     }
 
 
