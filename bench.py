@@ -343,12 +343,68 @@ def bench_force(args, eofa, synth, torch, np):
     print(json.dumps(out), flush=True)
 
 
+def bench_heatbath(args, eofa, synth, torch, np):
+    """EOFA heatbath (eqn eofa_heatbath) on 16^3 x 32, Ls = 16 with a 6-pole
+    partial-fraction approximation of x^-1/2 (6-node Gauss-Legendre rule for
+    x^-1/2 = (2/pi) int_0^1 du / (u^2 + x (1 - u)^2), written as
+    sum_l alpha_l / (beta_l + x); 1e-4 relative on [0.5, 4]).
+    Modes (Sec. VI B): all 12 systems in one batched solve; poles one after
+    another from chronological forecasts; forecasts plus per-pole tolerances
+    relaxed by each pole's weight k alpha_l gamma_l^2 in phi. Inner FP16S,
+    outer FP64."""
+    dims, Ls, eps, m1, m2 = (16, 16, 16, 32), 16, 0.5, 0.04, 1.0
+    U = torch.from_numpy(synth.gauge_field(dims, eps, 1001)).cuda()
+    ctx = eofa.Context(eofa.make_action(dims, Ls, 1.8, 1.5, 0.5), U)
+    eta = torch.from_numpy(synth.fermion(dims, Ls, 2002, nrhs=1)).cuda()
+    # (2/pi) int_0^1 du / ((1 - u)^2 (x + u^2 / (1 - u)^2)) on a 6-node Gauss-Legendre rule
+    uu, ww = np.polynomial.legendre.leggauss(6)
+    uu, ww = 0.5 * (uu + 1.0), 0.5 * ww
+    beta = [float(x * x / (1.0 - x) ** 2) for x in uu]
+    alpha = [0.0] + [float(2.0 / np.pi * wk / (1.0 - x) ** 2) for x, wk in zip(uu, ww)]
+    c, d = 1.0, 0.5  # (b5 + c5)/2, (b5 - c5)/2
+    Nf = lambda m: (c + d) ** Ls + m * (c - d) ** Ls
+    k = 2.0 * c * (m2 - m1) * (c + d) ** (2 * Ls) / (Nf(m1) * Nf(m2))
+    wts = [abs(a) * k / (1.0 + b) ** 2 for a, b in zip(alpha[1:], beta)]
+    tol = 1e-10
+    ptol = [float(min(1e-5, tol * max(wts) / wl)) for wl in wts] * 2
+    res = {}
+    ref = None
+    for name, prm, pt in [("batched", eofa.make_params(tol=tol, inner_prec=eofa.FP16S), None),
+                          ("forecast", eofa.make_params(tol=tol, inner_prec=eofa.FP16S, use_guess=1), None),
+                          ("forecast_pole_tol", eofa.make_params(tol=tol, inner_prec=eofa.FP16S, use_guess=1), ptol)]:
+        phi = torch.zeros_like(eta)
+        ctx.eofa_heatbath_solve(m1, m2, alpha, beta, eta, phi, prm, pole_tol=pt)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, st = ctx.eofa_heatbath_solve(m1, m2, alpha, beta, eta, phi, prm, pole_tol=pt)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if ref is None:
+            ref = phi.clone()
+        diff = float(torch.linalg.vector_norm(phi - ref) / torch.linalg.vector_norm(ref))
+        res[name] = dict(seconds=round(dt, 4), iters=[s["iters"] for s in st], total_iters=sum(s["iters"] for s in st),
+                         rel_diff_vs_batched=diff, rc=rc)
+        print(f"bench: heatbath {name}: {dt:.3f} s, iterations {res[name]['iters']}", file=sys.stderr, flush=True)
+    out = {
+        "metric": METRIC, "value": res["forecast_pole_tol"]["seconds"], "unit": "s", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": round(res["forecast_pole_tol"]["seconds"] * 1e3, 3), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{dims[0]}x{dims[1]}x{dims[2]}x{dims[3]} Ls={Ls}, EOFA heatbath m1={m1} m2={m2}, "
+                               f"6 poles (12 systems), FP16S inner / FP64 outer, tol {tol}", "lattice": list(dims),
+                   "Ls": Ls},
+        "poles": {"alpha": alpha, "beta": beta, "pole_tol": ptol},
+        "modes": res,
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["batched", "learned", "force"])
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["batched", "learned", "force", "heatbath"])
     ap.add_argument("--batched-iters", type=int, default=64)
     ap.add_argument("--inner", default="fp16s", choices=sorted(PREC))
     ap.add_argument("--inner-tol", type=float, default=0.0)
@@ -392,6 +448,9 @@ def main():
         return
     if args.workload == "force":
         bench_force(args, eofa, synth, torch, np)
+        return
+    if args.workload == "heatbath":
+        bench_heatbath(args, eofa, synth, torch, np)
         return
 
     dims, Ls, eps, m1, gseed, sseed = WORKLOADS[args.workload]

@@ -196,12 +196,16 @@ int eofa_cg_solve(eofa_ctx* ctx, const eofa_system* sys, const void* phi, void* 
  * the rational f(x) = alpha[0] + sum_l alpha[l] / (beta[l-1] + x),
  * l = 1..n_poles, via the 2*n_poles systems
  *   LH: (H(m1) - gamma_l Delta_-(m1,m2) P_-),  RH: (H(m2) - beta_l gamma_l Delta_+(m1,m2) P_+),
- * gamma_l = 1/(1+beta_l), solved as one batch. eta, phi: device canonical
- * complex128 fields (one right-hand side). alpha: host [n_poles+1],
- * beta: host [n_poles]. stats: host [2*n_poles] (LH poles then RH), may
- * be NULL.                                                               */
+ * gamma_l = 1/(1+beta_l). eta, phi: device canonical complex128 fields (one
+ * right-hand side). alpha: host [n_poles+1], beta: host [n_poles].
+ * pole_tol: host [2*n_poles] FP64 true-residual target per system (LH poles
+ * then RH; Sec. VI B per-pole tuning), or NULL for params->tol everywhere.
+ * params->use_guess = 0: all systems in one batched solve; 1: the poles of
+ * each side one after another, each started from the chronological forecast
+ * (Sec. VI B, after Brower et al.) over up to 8 previous solutions of that
+ * side. stats: host [2*n_poles] (LH poles then RH), may be NULL.         */
 int eofa_heatbath_solve(eofa_ctx* ctx, double m1, double m2, int32_t n_poles, const double* alpha,
-                        const double* beta, const void* eta, void* phi,
+                        const double* beta, const double* pole_tol, const void* eta, void* phi,
                         const eofa_solver_params* params, eofa_solver_stats* stats, void* stream);
 
 /* Link derivative of the hopping term (Sec. IV C): for canonical 5D fields

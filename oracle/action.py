@@ -75,3 +75,16 @@ def heatbath(act, m1, m2, alpha, beta_poles, eta, solve):
 def heatbath_error(act, m1, m2, eta, phi, solve):
     nn = vdot(eta, eta).real
     return abs(nn - vdot(phi, apply_meofa(act, m1, m2, phi, solve)).real) / nn
+
+
+def chronological_guess(A, phi, psis):
+    """Sec. VI B (after Brower et al.): the guess sum_k c_k psi_k minimising
+    psi^dag A psi - phi^dag psi - psi^dag phi over the span of psis, from
+    sum_k c_k psi_l^dag A psi_k = psi_l^dag phi (A an operator callable)."""
+    N = len(psis)
+    Apsi = [A(p) for p in psis]
+    G = np.array([[vdot(psis[l], Apsi[k]) for k in range(N)] for l in range(N)])
+    f = np.array([vdot(psis[l], phi) for l in range(N)])
+    c = np.linalg.solve(G, f)
+    return sum(ck * p for ck, p in zip(c, psis))
+

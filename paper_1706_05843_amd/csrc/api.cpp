@@ -27,6 +27,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -550,8 +551,10 @@ int reconstruct(eofa_ctx* C, int nrhs, void* x, void* be, void* bo, void* te, vo
   return EOFA_OK;
 }
 
+// tolr: per right-hand side FP64 true-residual targets (nullptr: prm->tol for all)
 int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, void* psi,
-                const eofa_solver_params* prm, eofa_solver_stats* stats, hipStream_t st) {
+                const eofa_solver_params* prm, eofa_solver_stats* stats, hipStream_t st,
+                const double* tolr = nullptr) {
   const double t0 = now_s();
   const Geometry& g = C->g;
   const int S = prm->inner_prec;
@@ -699,7 +702,7 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
         done[r] = 1;
         continue;
       }
-      if (!fixed && res <= prm->tol) done[r] = 1;
+      if (!fixed && res <= (tolr ? tolr[r] : prm->tol)) done[r] = 1;
       if (!fixed && iters[r] >= prm->max_iter) done[r] = 1;
       if (!done[r]) all = false;
     }
@@ -713,7 +716,7 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
       mi[r] = done[r] ? 0 : (fixed ? prm->fixed_iters : std::max(0, prm->max_iter - iters[r]));
       double it_r = 0.0;
       if (!fixed && !done[r]) {
-        const double need = 0.3 * prm->tol * std::sqrt(bb[r] / std::max(rro[r], 1e-300));
+        const double need = 0.3 * (tolr ? tolr[r] : prm->tol) * std::sqrt(bb[r] / std::max(rro[r], 1e-300));
         it_r = std::min(0.5, std::max(inner_floor, need));
       }
       t2[r] = it_r * it_r;
@@ -839,7 +842,7 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
   int worst = EOFA_OK;
   for (int r = 0; r < nrhs; ++r) {
     const double tr = bb[r] > 0 ? std::sqrt((re[r] + rodd[r]) / bb[r]) : ((re[r] + rodd[r]) == 0.0 ? 0.0 : NAN);
-    const bool conv = std::isfinite(tr) && tr <= prm->tol;
+    const bool conv = std::isfinite(tr) && tr <= (tolr ? tolr[r] : prm->tol);
     if (status[r] == EOFA_OK && !conv && !fixed) status[r] = std::isfinite(tr) ? EOFA_ERR_NOT_CONVERGED : EOFA_ERR_BREAKDOWN;
     if (stats) {
       eofa_solver_stats& o = stats[r];
@@ -1328,13 +1331,121 @@ extern "C" int eofa_fifth_matrix(const eofa_action* act, const eofa_system* sys,
   return EOFA_OK;
 }
 
+namespace {
+
+// Small dense complex solve G c = f (Gaussian elimination, partial pivoting);
+// false if G is numerically singular.
+bool solve_small(int n, std::vector<std::complex<double>> G, std::vector<std::complex<double>>& f) {
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::abs(G[r * n + c]) > std::abs(G[piv * n + c])) piv = r;
+    if (!(std::abs(G[piv * n + c]) > 1e-300) || !std::isfinite(std::abs(G[piv * n + c]))) return false;
+    if (piv != c) {
+      for (int k = 0; k < n; ++k) std::swap(G[c * n + k], G[piv * n + k]);
+      std::swap(f[c], f[piv]);
+    }
+    for (int r = c + 1; r < n; ++r) {
+      const std::complex<double> m = G[r * n + c] / G[c * n + c];
+      for (int k = c; k < n; ++k) G[r * n + k] -= m * G[c * n + k];
+      f[r] -= m * f[c];
+    }
+  }
+  for (int c = n - 1; c >= 0; --c) {
+    for (int k = c + 1; k < n; ++k) f[c] -= G[c * n + k] * f[k];
+    f[c] /= G[c * n + c];
+  }
+  for (auto& v : f)
+    if (!std::isfinite(v.real()) || !std::isfinite(v.imag())) return false;
+  return true;
+}
+
+// Chronological forecast of the next pole's solution (Sec. VI B, after
+// Brower et al.): guess = sum_k c_k psi_k over the previous solutions psi_k of
+// the same side, with sum_k c_k psi_l^dag A psi_k = psi_l^dag rhs for every l,
+// A = H(m_op) + beta Delta_chi P_chi of the next pole (the minimiser of
+// psi^dag A psi - rhs^dag psi - psi^dag rhs on their span). A psi_k is formed
+// in the Cayley form, A psi = g5 R5 M_C D~^-1 psi (App. B.2), M_C on both
+// parities by the FULLRES role with a zero source. Fields: canonical FP64.
+int forecast(eofa_ctx* C, const eofa_system* sys, const void* rhs, const std::vector<const void*>& prev,
+             void* guess, hipStream_t st) {
+  const Geometry& g = C->g;
+  const int N = (int)prev.size();
+  CHK(upload_systems(C, sys, 1, st));
+  const size_t b64 = packed_bytes(P64, g, 1);
+  const size_t fbytes = (size_t)g.Ls * g.V * 12 * 16;
+  void *t, *xe, *xo, *me, *mo, *zero, *g5, *pv, *dv;
+  CHK(ws(C, "fc_t", b64, &t));
+  CHK(ws(C, "fc_xe", b64, &xe));
+  CHK(ws(C, "fc_xo", b64, &xo));
+  CHK(ws(C, "fc_me", b64, &me));
+  CHK(ws(C, "fc_mo", b64, &mo));
+  CHK(ws(C, "fc_zero", b64, &zero));
+  CHK(ws(C, "fc_g5", 2 * b64 * (size_t)N, &g5));
+  const int maxblk = std::max({hop_blocks(P64, g.Vh, g.Ls, 1), (g.Ls * g.Vh + 255) / 256, 2048});
+  CHK(ws(C, "fc_partial", sizeof(double) * 2 * (size_t)maxblk, &pv));
+  CHK(ws(C, "fc_dot", sizeof(double) * (4 * (size_t)N * N + 2 * (size_t)N), &dv));
+  CHK(stage(C, sizeof(double) * (4 * (size_t)N * N + 2 * (size_t)N)));
+  double* partial = (double*)pv;
+  double* dots = (double*)dv;  // [l][k][parity][re, im], then f[l][re, im]
+  launch_zero(P64, g, zero, 1, st);
+  const int nh = (int)(b64 / 16);
+  for (int l = 0; l < N; ++l) {
+    launch_pack(P64, g, prev[l], (char*)g5 + (2 * l) * b64, 0, 1, 1, st);
+    launch_pack(P64, g, prev[l], (char*)g5 + (2 * l + 1) * b64, 1, 1, 1, st);
+  }
+  for (int k = 0; k < N; ++k) {
+    launch_pack(P64, g, prev[k], t, 0, 1, 0, st);
+    launch_smat(P64, g, t, xe, C->mats, MAT_DT_INV, 1, st);
+    launch_pack(P64, g, prev[k], t, 1, 1, 0, st);
+    launch_smat(P64, g, t, xo, C->mats, MAT_DT_INV, 1, st);
+    for (int p = 0; p < 2; ++p) {  // out_p = 0 - (M_ee x_p + Dhop D~ x_{1-p}) = -(M_C D~^-1 psi_k)_p
+      HopArgs a = base_args(C, P64, p, 1);
+      a.in = p ? xe : xo;
+      a.y = p ? xo : xe;
+      a.z = zero;
+      a.out = p ? mo : me;
+      a.matB = MAT_MEE;
+      a.partial = partial;
+      CHK(hop(C, P64, ROLE_FULLRES, a, st));
+    }
+    for (int l = 0; l < N; ++l) {
+      launch_cdot(nh, (char*)g5 + (2 * l) * b64, me, partial, dots + 4 * (l * N + k), st);
+      launch_cdot(nh, (char*)g5 + (2 * l + 1) * b64, mo, partial, dots + 4 * (l * N + k) + 2, st);
+    }
+  }
+  const int nfull = (int)(fbytes / 16);
+  for (int l = 0; l < N; ++l) launch_cdot(nfull, prev[l], rhs, partial, dots + 4 * N * N + 2 * l, st);
+  HIPCHK(hipGetLastError());
+  std::vector<double> h(4 * (size_t)N * N + 2 * (size_t)N);
+  CHK(fetch(C, dots, sizeof(double) * h.size(), h.data(), st));
+  std::vector<std::complex<double>> G((size_t)N * N), f(N);
+  for (int l = 0; l < N; ++l) {
+    for (int k = 0; k < N; ++k) {
+      const double* d = h.data() + 4 * (l * N + k);
+      G[l * N + k] = -std::complex<double>(d[0] + d[2], d[1] + d[3]);
+    }
+    f[l] = {h[4 * N * N + 2 * l], h[4 * N * N + 2 * l + 1]};
+  }
+  HIPCHK(hipMemsetAsync(guess, 0, fbytes, st));
+  if (!solve_small(N, G, f)) return EOFA_OK;  // no usable forecast: start from zero
+  for (int k = 0; k < N; ++k) launch_caxpy(nfull, f[k].real(), f[k].imag(), prev[k], guess, st);
+  HIPCHK(hipGetLastError());
+  return EOFA_OK;
+}
+
+}  // namespace
+
 extern "C" int eofa_heatbath_solve(eofa_ctx* C, double m1, double m2, int32_t n_poles, const double* alpha,
-                                   const double* beta, const void* eta, void* phi,
+                                   const double* beta, const double* pole_tol, const void* eta, void* phi,
                                    const eofa_solver_params* prm, eofa_solver_stats* stats, void* stream) {
   if (!C || !alpha || !beta || !eta || !phi) return fail(EOFA_ERR_INVALID, "eofa_heatbath_solve: NULL argument");
   if (eta == phi) return fail(EOFA_ERR_INVALID, "eofa_heatbath_solve: eta and phi alias");
   if (n_poles < 1) return fail(EOFA_ERR_INVALID, "n_poles must be >= 1");
   CHK(check_params(prm));
+  if (pole_tol)
+    for (int r = 0; r < 2 * n_poles; ++r)
+      if (!(pole_tol[r] > 0.0)) return fail(EOFA_ERR_INVALID, "pole_tol entries must be > 0");
   hipStream_t st = (hipStream_t)stream;
   const Geometry& g = C->g;
   const int nsys = 2 * n_poles;
@@ -1383,10 +1494,34 @@ extern "C" int eofa_heatbath_solve(eofa_ctx* C, double m1, double m2, int32_t n_
   launch_omega_rhs(g, eta, rhs, d_om, d_chir, nsys, st);
   HIPCHK(hipGetLastError());
   std::vector<eofa_solver_stats> st_local(nsys);
-  eofa_solver_params p2 = *prm;
-  p2.use_guess = 0;  // the pole solutions live in library workspace: no guess
-  const int rc = solve_batch(C, sys.data(), nsys, rhs, sol, &p2, stats ? stats : st_local.data(), st);
-  if (rc != EOFA_OK && rc != EOFA_ERR_NOT_CONVERGED) return rc;
+  eofa_solver_stats* sts = stats ? stats : st_local.data();
+  int rc = EOFA_OK;
+  if (!prm->use_guess) {
+    // all 2 N_p systems in one batched solve
+    eofa_solver_params p2 = *prm;
+    rc = solve_batch(C, sys.data(), nsys, rhs, sol, &p2, sts, st, pole_tol);
+    if (rc != EOFA_OK && rc != EOFA_ERR_NOT_CONVERGED) return rc;
+  } else {
+    // poles one after another, each starting from the chronological forecast
+    // over up to 8 previous solutions of the same side (LH or RH)
+    constexpr int max_prev = 8;
+    for (int side = 0; side < 2; ++side) {
+      std::vector<const void*> prev;
+      for (int l = 0; l < n_poles; ++l) {
+        const int r = side * n_poles + l;
+        const void* rhs_r = (const char*)rhs + fbytes * r;
+        void* sol_r = (char*)sol + fbytes * r;
+        eofa_solver_params p2 = *prm;
+        p2.use_guess = prev.empty() ? 0 : 1;
+        if (!prev.empty()) CHK(forecast(C, &sys[r], rhs_r, prev, sol_r, st));
+        const int rr = solve_batch(C, &sys[r], 1, rhs_r, sol_r, &p2, sts + r, st, pole_tol ? pole_tol + r : nullptr);
+        if (rr != EOFA_OK && rr != EOFA_ERR_NOT_CONVERGED) return rr;
+        if (rr != EOFA_OK) rc = rr;
+        prev.push_back(sol_r);
+        if ((int)prev.size() > max_prev) prev.erase(prev.begin());
+      }
+    }
+  }
   launch_heatbath_combine(g, eta, sol, phi, a_eta, d_coef, d_om, d_chir, nsys, st);
   HIPCHK(hipStreamSynchronize(st));
   HIPCHK(hipGetLastError());

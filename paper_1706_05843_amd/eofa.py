@@ -83,8 +83,8 @@ def lib():
         "eofa_cg_solve": ([_P, ctypes.POINTER(System), _P, _P, _I, ctypes.POINTER(SolverParams),
                            ctypes.POINTER(SolverStats), _P], _I),
         "eofa_heatbath_solve": ([_P, ctypes.c_double, ctypes.c_double, _I, ctypes.POINTER(ctypes.c_double),
-                                 ctypes.POINTER(ctypes.c_double), _P, _P, ctypes.POINTER(SolverParams),
-                                 ctypes.POINTER(SolverStats), _P], _I),
+                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _P, _P,
+                                 ctypes.POINTER(SolverParams), ctypes.POINTER(SolverStats), _P], _I),
         "eofa_fifth_matrix": ([ctypes.POINTER(Action), ctypes.POINTER(System), _I,
                                ctypes.POINTER(ctypes.c_double)], _I),
         "eofa_dhop_derivative": ([_P, _P, _P, _P, _P], _I),
@@ -239,13 +239,17 @@ class Context:
             _check(rc)
         return rc, [s.as_dict() for s in stats]
 
-    def eofa_heatbath_solve(self, m1, m2, alpha, beta, eta, phi, params, stream=None):
+    def eofa_heatbath_solve(self, m1, m2, alpha, beta, eta, phi, params, pole_tol=None, stream=None):
         npol = len(beta)
         assert len(alpha) == npol + 1
         a = (ctypes.c_double * (npol + 1))(*alpha)
         b = (ctypes.c_double * npol)(*beta)
+        pt = None
+        if pole_tol is not None:
+            assert len(pole_tol) == 2 * npol
+            pt = (ctypes.c_double * (2 * npol))(*pole_tol)
         stats = (SolverStats * (2 * npol))()
-        rc = lib().eofa_heatbath_solve(self._h, m1, m2, npol, a, b, _p(eta), _p(phi), ctypes.byref(params),
+        rc = lib().eofa_heatbath_solve(self._h, m1, m2, npol, a, b, pt, _p(eta), _p(phi), ctypes.byref(params),
                                        stats, _stream(stream))
         if rc in (EOFA_ERR_INVALID, EOFA_ERR_HIP, EOFA_ERR_OOM):
             _check(rc)

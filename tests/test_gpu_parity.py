@@ -277,6 +277,35 @@ def test_heatbath_matches_oracle(c1ctx):
     assert rel2(host(phi)[0], ref) < 1e-9
 
 
+def test_heatbath_forecast_and_pole_tol(c1ctx):
+    """Poles solved one after another from chronological forecasts (Sec. VI B)
+    give the batched phi with fewer iterations; per-pole tolerances are met."""
+    act, U, _, _ = oracle_c1("chi1")
+    eta = dev(synth.fermion(act.dims, act.Ls, seed=2101)[None])
+    alpha = [0.35, 0.2, 0.3, 0.5, 0.9]
+    beta = [0.01, 0.1, 0.5, 2.0]
+    ph_b = torch.zeros(c1ctx.full_shape(1), dtype=torch.complex128, device="cuda")
+    rc, st_b = c1ctx.eofa_heatbath_solve(M1, M2, alpha, beta, eta, ph_b, eofa.make_params(tol=1e-11))
+    assert rc == eofa.EOFA_OK
+    ph_f = torch.zeros_like(ph_b)
+    rc, st_f = c1ctx.eofa_heatbath_solve(M1, M2, alpha, beta, eta, ph_f,
+                                          eofa.make_params(tol=1e-11, use_guess=1))
+    assert rc == eofa.EOFA_OK and all(s["converged"] for s in st_f)
+    assert rel2(host(ph_f)[0], host(ph_b)[0]) < 1e-9
+    it_b, it_f = [s["iters"] for s in st_b], [s["iters"] for s in st_f]
+    print("heatbath iterations per pole: batched", it_b, "forecast", it_f)
+    n = len(beta)
+    assert it_f[0] == it_b[0] and it_f[n] == it_b[n]  # first pole of each side: no forecast
+    assert sum(it_f) < sum(it_b)
+    ptol = [1e-6, 1e-8, 1e-10, 1e-11, 1e-7, 1e-9, 1e-10, 1e-11]
+    ph_t = torch.zeros_like(ph_b)
+    rc, st_t = c1ctx.eofa_heatbath_solve(M1, M2, alpha, beta, eta, ph_t, eofa.make_params(tol=1e-11),
+                                          pole_tol=ptol)
+    assert rc == eofa.EOFA_OK
+    for s, t in zip(st_t, ptol):
+        assert s["converged"] == 1 and s["true_resid"] <= t
+
+
 # --- errors ----------------------------------------------------------------------
 
 def test_error_paths(c1ctx):

@@ -158,3 +158,21 @@ def test_heatbath_woodbury(tiny):
     for a, b in zip(alpha[1:], beta):
         ref = ref + a * np.linalg.solve(Me + b * np.eye(n), eta.ravel())
     assert np.abs(phi.ravel() - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_chronological_guess(tiny):
+    """Sec. VI B forecast: exact when the solution is in the span; otherwise
+    the Galerkin residual is orthogonal to the span."""
+    act, U = tiny
+    sysm = System(M1, M1, M2, -0.5, -1)
+    A = lambda x: H_system(act, U, sysm, x)
+    phi = synth.fermion(act.dims, act.Ls, seed=77)
+    x = reference.solve_dense(act, U, sysm, phi)
+    others = [synth.fermion(act.dims, act.Ls, seed=78 + k) for k in range(3)]
+    g = action.chronological_guess(A, phi, others[:2] + [x] + others[2:])
+    assert np.sqrt(norm2(g - x) / norm2(x)) < 1e-10
+    g2 = action.chronological_guess(A, phi, others)
+    r = phi - A(g2)
+    for p in others:
+        assert abs(np.vdot(p, r)) < 1e-10 * np.sqrt(norm2(p) * norm2(phi))
+
