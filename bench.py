@@ -399,12 +399,75 @@ def bench_heatbath(args, eofa, synth, torch, np):
     print(json.dumps(out), flush=True)
 
 
+def bench_gparity(args, eofa, synth, torch, np):
+    """G-parity in x on 32^3 x 64, Ls = 12 (two flavours: the library holds the
+    x-doubled 64 x 32 x 32 x 64 lattice): a 4-RHS FP32 Dslash launch (fields far
+    larger than the 256 MB MALL, so this is HBM-bound territory) against its
+    compulsory bytes, and one FP16S/FP64 solve of H(m2) - Delta_+(m1,m2) P_+ to
+    1e-10 (m1 = 0.0025, m2 = 1.0)."""
+    dims, Ls, eps, m1, m2 = (32, 32, 32, 64), 12, 0.5, 0.0025, 1.0
+    log = lambda m: print(f"bench: {m}", file=sys.stderr, flush=True)
+    log("G-parity workload: generating the 32^3x64 gauge field")
+    U = torch.from_numpy(synth.gauge_field(dims, eps, 1005)).cuda()
+    act = eofa.make_action(dims, Ls, 1.8, 1.5, 0.5, bc=(2, 1, 1, -1))
+    ctx = eofa.Context(act, U)
+    del U
+    torch.cuda.empty_cache()
+    Vd = 2 * int(np.prod(dims))  # doubled lattice
+    Nh = Vd // 2 * Ls
+    nrhs = 4
+    prec = eofa.FP32
+    sysl = [(m1, 0.0, 0.0, 0.0, 1)] * nrhs
+    src = synth.fermion_torch((2 * dims[0],) + dims[1:], Ls, seed=2005, nrhs=nrhs)
+    pin, pout = ctx.new_packed(prec, nrhs), ctx.new_packed(prec, nrhs)
+    ctx.eofa_pack(src, pin, 1, prec, nrhs)
+    del src
+    torch.cuda.empty_cache()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ctx.eofa_dslash(sysl, pin, pout, 0, 0, prec, nrhs)
+    reps = 10
+    ev[0].record()
+    for _ in range(reps):
+        ctx.eofa_dslash(sysl, pin, pout, 0, 0, prec, nrhs)
+    ev[1].record()
+    torch.cuda.synchronize()
+    t_d = ev[0].elapsed_time(ev[1]) / reps * 1e-3
+    alg = 2 * site_bytes(prec) * Nh * nrhs + link_bytes_per_site(prec) * (Vd // 2)
+    log(f"4-RHS Dslash {t_d * 1e3:.2f} ms, {alg / t_d / 1e9:.1f} GB/s")
+    del pin, pout
+    torch.cuda.empty_cache()
+    phi = synth.fermion_torch((2 * dims[0],) + dims[1:], Ls, seed=2006, nrhs=1)
+    psi = torch.zeros_like(phi)
+    prm = eofa.make_params(tol=1e-10, inner_prec=eofa.FP16S)
+    system = [(m2, m1, m2, -1.0, +1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, st = ctx.eofa_cg_solve(system, phi, psi, prm)
+    torch.cuda.synchronize()
+    t_s = time.perf_counter() - t0
+    log(f"solve {t_s:.2f} s, {st[0]['iters']} iterations, residual {st[0]['true_resid']:.2e}")
+    out = {
+        "metric": METRIC, "value": round(alg / t_d / 1e9, 1), "unit": "GB/s", "n_gpus": 1, "steps": reps,
+        "warmup": 1, "ms_per_step": round(t_d * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{dims[0]}x{dims[1]}x{dims[2]}x{dims[3]} Ls={Ls}, G-parity in x (2 flavours), "
+                               f"4-RHS FP32 Dslash; FP16S/FP64 solve of H(m2)-Delta_+ P_+ m1={m1} m2={m2}",
+                   "lattice": list(dims), "Ls": Ls},
+        "dslash_4rhs": {"seconds": t_d, "algorithmic_bytes": alg, "algorithmic_GBs": round(alg / t_d / 1e9, 1),
+                        "frac_hbm": round(alg / t_d / 1e9 / HBM_PEAK_GBS, 4)},
+        "solve": {"seconds": round(t_s, 3), "iters": st[0]["iters"], "outer_iters": st[0]["outer_iters"],
+                  "true_resid": st[0]["true_resid"], "rc": rc},
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["batched", "learned", "force", "heatbath"])
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["batched", "learned", "force", "heatbath", "gparity"])
     ap.add_argument("--batched-iters", type=int, default=64)
     ap.add_argument("--inner", default="fp16s", choices=sorted(PREC))
     ap.add_argument("--inner-tol", type=float, default=0.0)
@@ -451,6 +514,9 @@ def main():
         return
     if args.workload == "heatbath":
         bench_heatbath(args, eofa, synth, torch, np)
+        return
+    if args.workload == "gparity":
+        bench_gparity(args, eofa, synth, torch, np)
         return
 
     dims, Ls, eps, m1, gseed, sseed = WORKLOADS[args.workload]

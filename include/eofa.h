@@ -29,6 +29,14 @@
  * Canonical (user) layouts, complex128 = two doubles (re, im):
  *   gauge   [4][Lt][Lz][Ly][Lx][3][3]           row-major SU(3) links U_mu(x)
  *   fermion [nrhs][Ls][Lt][Lz][Ly][Lx][4][3]     spin then colour
+ * G-parity in x (bc[0] = 2; the paper's G-parity ensembles, operator form
+ * read as: two flavours, flavour 1 hopping with conj(U), fields across the x
+ * edge psi(x + Lx) = [[0, 1], [-1, 0]] psi(x), links U(x + Lx) = conj(U(x))):
+ *   fermion [nrhs][Ls][Lt][Lz][Ly][2][Lx][4][3]  (flavour between y and x;
+ *   internally the x-doubled lattice 2Lx with links [U, conj(U)] and an
+ *   antiperiodic x edge). The gauge input and the force stay physical
+ *   [4][Lt][Lz][Ly][Lx][3][3]; eofa_dhop_derivative returns the doubled
+ *   [4][Lt][Lz][Ly][2][Lx][3][3]. Only x may carry G-parity.
  *
  * Packed (internal) half-field of one parity: site index
  *   i = (((t*Lz + z)*Ly + y)*Lx + x) / 2,  Vh = Lx*Ly*Lz*Lt / 2,
@@ -91,7 +99,8 @@ typedef struct {
   int32_t dims[4]; /* Lx, Ly, Lz, Lt                                  */
   int32_t Ls;
   double M5, b5, c5;
-  int32_t bc[4];   /* +1 periodic, -1 antiperiodic, per direction     */
+  int32_t bc[4];   /* +1 periodic, -1 antiperiodic, per direction;
+                      bc[0] = 2: G-parity in x (see the layouts above)    */
 } eofa_action;
 
 /* One EOFA system (eqn generic_eofa_system):

@@ -32,8 +32,10 @@ class Action:
 
     @property
     def field_shape(self):
+        """G-parity in x (bc[0] == 2): flavour-doubled, flavour axis first."""
         lx, ly, lz, lt = self.dims
-        return (self.Ls, lt, lz, ly, lx, 4, 3)
+        shape = (self.Ls, lt, lz, ly, lx, 4, 3)
+        return (2,) + shape if self.bc[0] == 2 else shape
 
 
 def apply_s(Ap, Am, psi):

@@ -91,7 +91,10 @@ def hop(U, psi, bc, adjoint=False):
                                 + (1 + g_mu) U_mu(x - mu)^dag psi(x - mu) ].
     The adjoint follows from conjugate-transposing each matrix element:
     it is the same sum with gamma_mu -> -gamma_mu.
+    bc[0] == 2 selects G-parity in x (``hop_gparity``).
     """
+    if bc[0] == 2:
+        return hop_gparity(U, psi, bc, adjoint)
     sg = -1.0 if adjoint else 1.0
     out = np.zeros_like(psi)
     for mu in range(4):
@@ -100,6 +103,50 @@ def hop(U, psi, bc, adjoint=False):
         bwd = _colour(ub, shift(psi, mu, -1, bc[mu]))
         out += _spin(ID4 - sg * GAMMA[mu], fwd) + _spin(ID4 + sg * GAMMA[mu], bwd)
     return -0.5 * out
+
+
+def hop_gparity(U, psi, bc, adjoint=False):
+    """Dhop with G-parity boundary conditions in x (Sec. II mentions G-parity
+    ensembles; the operator form is this build's reading): flavour-doubled
+    fields psi[f] (axis 0, f = 0, 1); flavour 0 hops with U, flavour 1 with
+    conj(U); across the x edge the fields obey psi(x + L) = Tw psi(x) with
+    Tw = [[0, 1], [-1, 0]] on (psi_0, psi_1) and the links U(x + L) = conj(U(x)).
+    bc[1..3] are the ordinary phases of y, z, t. Fields are 5D,
+    [..., 2, Ls, T, Z, Y, X, 4, 3]: the flavour axis is the eighth from the end."""
+    sg = -1.0 if adjoint else 1.0
+    Uf = [U, np.conj(U)]
+    psi = np.moveaxis(psi, -8, 0)
+    out = np.zeros_like(psi)
+    L = psi.shape[-3]
+    for f in range(2):
+        for mu in range(4):
+            if mu != 0:
+                fwd = _colour(Uf[f][mu], shift(psi[f], mu, +1, bc[mu]))
+                ub = dagger(shift(Uf[f][mu], mu, -1))
+                bwd = _colour(ub, shift(psi[f], mu, -1, bc[mu]))
+            else:
+                ax = psi[f].ndim - 3
+                # psi_f(x + 1); at x = L - 1: (Tw psi(0))_f = psi_1(0) (f = 0), -psi_0(0) (f = 1)
+                nxt = np.roll(psi[f], -1, axis=ax)
+                other = psi[1] if f == 0 else -psi[0]
+                idx = [slice(None)] * nxt.ndim
+                idx[ax] = L - 1
+                src = [slice(None)] * nxt.ndim
+                src[ax] = 0
+                nxt[tuple(idx)] = other[tuple(src)]
+                fwd = _colour(Uf[f][0], nxt)
+                # psi_f(x - 1); at x = 0: (Tw^-1 psi(L - 1))_f = -psi_1(L - 1) (f = 0), psi_0(L - 1) (f = 1)
+                prv = np.roll(psi[f], +1, axis=ax)
+                other = -psi[1] if f == 0 else psi[0]
+                idx[ax] = 0
+                src[ax] = L - 1
+                prv[tuple(idx)] = other[tuple(src)]
+                # U_x(x - 1); at x = 0 the link U_x(-1) = conj_(1-f)(U_x(L - 1))
+                ul = np.roll(Uf[f][0], +1, axis=Uf[f][0].ndim - 3)
+                ul[..., 0, :, :] = Uf[1 - f][0][..., L - 1, :, :]
+                bwd = _colour(dagger(ul), prv)
+            out[f] += _spin(ID4 - sg * GAMMA[mu], fwd) + _spin(ID4 + sg * GAMMA[mu], bwd)
+    return np.moveaxis(-0.5 * out, 0, -8)
 
 
 def wilson(U, psi, M5, bc, adjoint=False):

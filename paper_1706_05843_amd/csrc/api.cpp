@@ -203,14 +203,17 @@ int eofa_create(const eofa_action* act, const void* gauge, void* stream, eofa_ct
   for (int k = 0; k < 4; ++k) {
     if (act->dims[k] < 2 || act->dims[k] % 2 != 0)
       return fail(EOFA_ERR_INVALID, "every lattice extent must be even and >= 2");
-    if (act->bc[k] != 1 && act->bc[k] != -1) return fail(EOFA_ERR_INVALID, "bc entries must be +1 or -1");
+    const bool gp_ok = k == 0 && act->bc[k] == 2;
+    if (act->bc[k] != 1 && act->bc[k] != -1 && !gp_ok)
+      return fail(EOFA_ERR_INVALID, "bc entries must be +1 or -1 (bc[0] may be 2: G-parity in x)");
   }
+  const bool gparity = act->bc[0] == 2;
   if (act->Ls < 2 || act->Ls > 32 || act->Ls % 2 != 0) return fail(EOFA_ERR_INVALID, "Ls must be even, 2..32");
   if (std::fabs(act->b5 - act->c5 - 1.0) > 1e-12)
     return fail(EOFA_ERR_INVALID, "b5 - c5 must be 1 (d = 1/2)");
   if (!std::isfinite(act->M5) || !std::isfinite(act->b5) || !std::isfinite(act->c5))
     return fail(EOFA_ERR_INVALID, "non-finite action parameter");
-  const double V = (double)act->dims[0] * act->dims[1] * act->dims[2] * act->dims[3];
+  const double V = (double)act->dims[0] * act->dims[1] * act->dims[2] * act->dims[3] * (gparity ? 2 : 1);
   if (V / 2 * act->Ls * 6 > 2.0e9) return fail(EOFA_ERR_INVALID, "lattice too large for 32-bit site indexing");
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
@@ -224,6 +227,12 @@ int eofa_create(const eofa_action* act, const void* gauge, void* stream, eofa_ct
   for (int k = 0; k < 4; ++k) {
     C->g.L[k] = act->dims[k];
     C->bc[k] = act->bc[k];
+  }
+  if (gparity) {  // x-doubled lattice, flavour-1 copy at x + Lx, antiperiodic x edge
+    C->gparity = true;
+    C->Lx_phys = act->dims[0];
+    C->g.L[0] = 2 * act->dims[0];
+    C->bc[0] = -1;
   }
   C->g.Ls = act->Ls;
   C->g.V = (int)V;
@@ -263,9 +272,20 @@ int eofa_create(const eofa_action* act, const void* gauge, void* stream, eofa_ct
   void* l64[2] = {C->links[P64][0], C->links[P64][1]};
   void* l32[2] = {C->links[P32][0], C->links[P32][1]};
   void* l16[2] = {C->links[P16][0], C->links[P16][1]};
-  launch_gauge_pack(C->g, gauge, C->bc, l64, l32, l16, C->nbr, st);
+  void* gauge2 = nullptr;
+  if (gparity) {
+    const size_t rows = (size_t)C->g.L[1] * C->g.L[2] * C->g.L[3];
+    if (hipMalloc(&gauge2, (size_t)4 * rows * C->g.L[0] * 9 * 16) != hipSuccess) {
+      (void)hipGetLastError();
+      eofa_destroy(C);
+      return fail(EOFA_ERR_OOM, "hipMalloc failed for the x-doubled gauge field");
+    }
+    launch_double_gauge(C->Lx_phys, rows, gauge, gauge2, st);
+  }
+  launch_gauge_pack(C->g, gparity ? gauge2 : gauge, C->bc, l64, l32, l16, C->nbr, st);
   hipError_t e = hipStreamSynchronize(st);
   if (e == hipSuccess) e = hipGetLastError();
+  if (gauge2) (void)hipFree(gauge2);
   if (e != hipSuccess) {
     eofa_destroy(C);
     return fail(EOFA_ERR_HIP, std::string("gauge packing: ") + hipGetErrorString(e));
@@ -1599,9 +1619,12 @@ extern "C" int eofa_force(eofa_ctx* C, double m1, double m2, const void* phi, vo
   // F = sum_a T^a k [ (g5 R5 chi_1)^dag dDhop chi_1 - (g5 R5 chi_2)^dag dDhop chi_2 ]
   const double k = k_eofa(g.Ls, C->c, C->d, m1, m2);
   const char* chi2 = (const char*)chi + fbytes;
-  launch_dhop_deriv(deriv_args(C, chi, chi, force, k, 1, 0), st);
-  launch_dhop_deriv(deriv_args(C, chi2, chi2, force, -k, 1, 1), st);
-  launch_force_project((size_t)4 * g.V, force, st);
+  void* f2 = force;
+  if (C->gparity) CHK(ws(C, "fo_f2", (size_t)4 * g.V * 9 * 16, &f2));  // doubled lattice, folded below
+  launch_dhop_deriv(deriv_args(C, chi, chi, f2, k, 1, 0), st);
+  launch_dhop_deriv(deriv_args(C, chi2, chi2, f2, -k, 1, 1), st);
+  launch_force_project((size_t)4 * g.V, f2, st);
+  if (C->gparity) launch_fold_force(C->Lx_phys, (size_t)g.L[1] * g.L[2] * g.L[3], f2, force, st);
   HIPCHK(hipStreamSynchronize(st));
   HIPCHK(hipGetLastError());
   return rc;

@@ -171,7 +171,49 @@ __global__ void force_project_kernel(size_t nlinks, double2* y) {
     }
 }
 
+// G-parity in x on the x-doubled lattice: U2(x') = U(x') for x' < Lx,
+// conj(U(x' - Lx)) for Lx <= x' < 2 Lx (the flavour-1 copy)
+__global__ void double_gauge_kernel(int Lx, size_t rows, const double2* U, double2* U2) {
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;  // over 4 * rows * 2Lx sites
+  const size_t nsite = (size_t)4 * rows * 2 * Lx;
+  if (k >= nsite) return;
+  const int xd = (int)(k % (2 * Lx));
+  const size_t row = k / (2 * Lx);  // (mu, t, z, y)
+  const bool flv = xd >= Lx;
+  const double2* src = U + (row * Lx + (flv ? xd - Lx : xd)) * 9;
+  double2* dst = U2 + k * 9;
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    const double2 v = src[c];
+    dst[c] = make_double2(v.x, flv ? -v.y : v.y);
+  }
+}
+
+// physical force F(x) = F2(x) + conj(F2(x + Lx)) from the doubled-lattice one
+__global__ void fold_force_kernel(int Lx, size_t rows, const double2* F2, double2* F) {
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;  // over 4 * rows * Lx links
+  if (k >= (size_t)4 * rows * Lx) return;
+  const int x = (int)(k % Lx);
+  const size_t row = k / Lx;
+  const double2* a = F2 + (row * 2 * Lx + x) * 9;
+  const double2* b = F2 + (row * 2 * Lx + x + Lx) * 9;
+#pragma unroll
+  for (int c = 0; c < 9; ++c) F[k * 9 + c] = make_double2(a[c].x + b[c].x, a[c].y - b[c].y);
+}
+
 }  // namespace
+
+void launch_double_gauge(int Lx, size_t rows, const void* U, void* U2, hipStream_t st) {
+  const size_t n = (size_t)4 * rows * 2 * Lx;
+  hipLaunchKernelGGL(double_gauge_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Lx, rows,
+                     (const double2*)U, (double2*)U2);
+}
+
+void launch_fold_force(int Lx, size_t rows, const void* F2, void* F, hipStream_t st) {
+  const size_t n = (size_t)4 * rows * Lx;
+  hipLaunchKernelGGL(fold_force_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Lx, rows,
+                     (const double2*)F2, (double2*)F);
+}
 
 void launch_dhop_deriv(const DerivArgs& d, hipStream_t st) {
   dim3 grid((d.Vh + 127) / 128, 4, 2);

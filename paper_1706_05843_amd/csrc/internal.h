@@ -167,6 +167,10 @@ struct eofa_ctx {
   void* links[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
   int* nbr[2] = {nullptr, nullptr};
   int* order = nullptr;  // hop-kernel traversal order (site_order), [Vh]
+  // G-parity in x: the lattice is held x-doubled (flavour f at x + f Lx) with
+  // links [U, conj(U)] and an antiperiodic x edge; Lx_phys is the physical Lx
+  bool gparity = false;
+  int Lx_phys = 0;
   std::map<std::string, Buf> pool;
   // fifth-dimension matrices of the last systems uploaded
   std::vector<double> sys_key;

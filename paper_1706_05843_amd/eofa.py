@@ -184,6 +184,7 @@ class Context:
         self.action = action
         self.dims = tuple(action.dims)
         self.Ls = action.Ls
+        self.gparity = action.bc[0] == 2
         self._h = ctypes.c_void_p()
         _check(lib().eofa_create(ctypes.byref(action), ctypes.c_void_p(gauge.data_ptr()), _stream(stream),
                                  ctypes.byref(self._h)))
@@ -208,7 +209,10 @@ class Context:
         return torch.empty(self.packed_bytes(prec, nrhs), dtype=torch.uint8, device="cuda")
 
     def full_shape(self, nrhs=1):
+        """Canonical fermion shape; with G-parity in x the flavour axis sits between y and x."""
         lx, ly, lz, lt = self.dims
+        if self.gparity:
+            return (nrhs, self.Ls, lt, lz, ly, 2, lx, 4, 3)
         return (nrhs, self.Ls, lt, lz, ly, lx, 4, 3)
 
     # --- entry points ------------------------------------------------------
