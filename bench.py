@@ -462,12 +462,69 @@ def bench_gparity(args, eofa, synth, torch, np):
     print(json.dumps(out), flush=True)
 
 
+def bench_dense(args, eofa, synth, torch, np):
+    """The paper's Cayley form (App. B.2: D~^-1 right preconditioning, sparse
+    fifth-dimension blocks) against the dense form of the same EOFA system
+    (off-parity Dhop, same-parity D_ee = M_ee D~^-1 dense in s) on the default
+    16^3 x 32, Ls = 16 workload, both to an FP64 true residual of 1e-10, with
+    FP64 and FP16S inner CG. Per form: time, iterations, per-kernel average
+    launch time and algorithmic GB/s (both forms move the same bytes: the
+    Ls x Ls matrices are staged in LDS once per work-group)."""
+    dims, Ls, eps, m1, gseed, sseed = WORKLOADS["c2"]
+    m2 = 1.0
+    log = lambda m: print(f"bench: {m}", file=sys.stderr, flush=True)
+    U = torch.from_numpy(synth.gauge_field(dims, eps, gseed)).cuda()
+    phi = torch.from_numpy(synth.fermion(dims, Ls, sseed, nrhs=1)).cuda()
+    psi = torch.zeros_like(phi)
+    ctx = eofa.Context(eofa.make_action(dims, Ls, 1.8, 1.5, 0.5), U)
+    system = [(m2, m1, m2, -1.0, +1)]
+    Nh = int(np.prod(dims)) // 2 * Ls
+    res = {}
+    for pname in ("fp64", "fp16s"):
+        prec = PREC[pname]
+        for form, fname in ((0, "cayley"), (1, "dense")):
+            prm = eofa.make_params(tol=1e-10, inner_prec=prec, profile=1, form=form)
+            ctx.eofa_cg_solve(system, phi, psi, prm)  # warm-up (autotune)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, st = ctx.eofa_cg_solve(system, phi, psi, prm)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            if rc != eofa.EOFA_OK:
+                raise RuntimeError(f"{fname} {pname} solve failed rc={rc}")
+            s0 = st[0]
+            timed = max(s0["hop_timed"], 1)
+            us = [h / timed * 1e3 for h in s0["hop_ms"]]
+            gbs = [role_bytes(k, prec, Ls, Nh) / (us[k] * 1e-6) / 1e9 for k in range(4)]
+            per_iter = sum(role_bytes(k, prec, Ls, Nh) for k in range(4))
+            res[f"{fname}_{pname}"] = dict(seconds=round(t, 4), iters=s0["iters"], outer_iters=s0["outer_iters"],
+                                           true_resid=s0["true_resid"],
+                                           kernel_avg_us=[round(v, 2) for v in us],
+                                           kernel_gbs=[round(v, 1) for v in gbs],
+                                           whole_job_gbs=round(s0["iters"] * per_iter / t / 1e9, 1))
+            log(f"{fname} {pname}: {t:.3f} s, {s0['iters']} iterations, kernels {[round(v, 1) for v in us]} us")
+    d = res["dense_fp16s"]
+    out = {
+        "metric": METRIC, "value": d["whole_job_gbs"], "unit": "GB/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(d["seconds"] * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{dims[0]}x{dims[1]}x{dims[2]}x{dims[3]} Ls={Ls}: Cayley form vs dense form, "
+                               f"H(m2)-Delta_+(m1,m2)P_+ m1={m1} m2={m2}, true residual 1e-10",
+                   "lattice": list(dims), "Ls": Ls},
+        "forms": res,
+        "cayley_speedup_fp64": round(res["dense_fp64"]["seconds"] / res["cayley_fp64"]["seconds"], 3),
+        "cayley_speedup_fp16s": round(res["dense_fp16s"]["seconds"] / res["cayley_fp16s"]["seconds"], 3),
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["batched", "learned", "force", "heatbath", "gparity"])
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["batched", "learned", "force", "heatbath", "gparity", "dense"])
     ap.add_argument("--batched-iters", type=int, default=64)
     ap.add_argument("--inner", default="fp16s", choices=sorted(PREC))
     ap.add_argument("--inner-tol", type=float, default=0.0)
@@ -486,7 +543,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on a single GPU; --gpus must be 1 (no multi-GPU path here)",
+        print("bench.py: the solver runs on a single GPU; --gpus must be 1 (no multi-GPU path)",
               file=sys.stderr)
         sys.exit(2)
 
@@ -517,6 +574,9 @@ def main():
         return
     if args.workload == "gparity":
         bench_gparity(args, eofa, synth, torch, np)
+        return
+    if args.workload == "dense":
+        bench_dense(args, eofa, synth, torch, np)
         return
 
     dims, Ls, eps, m1, gseed, sseed = WORKLOADS[args.workload]

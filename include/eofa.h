@@ -136,7 +136,11 @@ typedef struct {
   const eofa_net* net; /* precond = 1: network (eofa_net_create), evaluated in FP32             */
   int32_t use_guess;   /* 1: psi holds an initial guess on entry (canonical layout; the
                           iteration starts from psi' = D~^-1 psi on the odd sublattice)       */
-  int32_t pad1;
+  int32_t form;        /* 0: Cayley form with D~^-1 right preconditioning (App. B.2, the
+                          paper's route); 1: the dense form for comparison: the EOFA matrix
+                          itself, off-parity blocks Dhop and same-parity blocks the dense
+                          Ls x Ls D_ee = M_ee D~^-1 per chirality (eofa_cg_solve with
+                          precond = 0 only; heatbath and force reject it)                     */
 } eofa_solver_params;
 
 typedef struct {
@@ -301,7 +305,8 @@ int eofa_net_train(eofa_ctx* ctx, eofa_net* net, const eofa_system* sys, const v
 /* Host only (no device work): the fifth-dimension matrix `mat` that the
  * library builds for one system, as out[2][Ls][Ls] (row-major; [0] acts on
  * P_+ psi, [1] on P_- psi). mat: 0 M_ee, 1 M_ee^-1, 2 M_ee^T, 3 M_ee^-T,
- * 4 M_ee^-T D~^T, 5 -D~^T, 6 D~^T, 7 D~, 8 D~^-1 (App. A, App. B.2).
+ * 4 M_ee^-T D~^T, 5 -D~^T, 6 D~^T, 7 D~, 8 D~^-1, and the dense form's
+ * 9 D_ee = M_ee D~^-1, 10 D_ee^-1, 11 D_ee^T, 12 D_ee^-T (App. A, App. B.2).
  * Returns EOFA_ERR_BREAKDOWN if the Sherman-Morrison denominator vanishes. */
 int eofa_fifth_matrix(const eofa_action* act, const eofa_system* sys, int32_t mat, double* out);
 

@@ -11,6 +11,9 @@ Field shape: [..., Ls, T, Z, Y, X, 4, 3]; the s axis is axis -7.
 * H = gamma_5 R5 D_EOFA (Sec. II).
 * the EOFA system (eqn generic_eofa_system):
     (H(m_op) + beta Delta_chi(m_a, m_b) P_chi) psi = phi.
+* its non-Hermitian form gamma_5 R5 (H + beta Delta P) = D_EOFA +
+  gamma_5 R5 beta Delta P (dense_op), the matrix the Cayley form
+  right-preconditions with D~^-1 (App. B.2).
 """
 import numpy as np
 
@@ -103,6 +106,14 @@ def H_system(act, U, sys, psi):
     out = g5R5(D_eofa(act, U, sys.m_op, psi))
     if sys.beta != 0.0:
         out = out + sys.beta * shift_op(act, sys.m_a, sys.m_b, sys.chi, psi)
+    return out
+
+
+def dense_op(act, U, sys, psi):
+    """(D_EOFA(m_op) + gamma_5 R5 beta Delta_chi P_chi) psi = gamma_5 R5 (H + beta Delta P) psi."""
+    out = D_eofa(act, U, sys.m_op, psi)
+    if sys.beta != 0.0:
+        out = out + sys.beta * gamma5(R5_op(shift_op(act, sys.m_a, sys.m_b, sys.chi, psi)))
     return out
 
 

@@ -22,8 +22,8 @@ on input and the other on output; nothing is fused or reordered.
 import numpy as np
 
 from . import fifth
-from .dwf import apply_s, D_dwf, D_dwf_adj, Dtilde_op, g5R5, cayley_op
-from .lattice import restrict, norm2
+from .dwf import apply_s, D_dwf, D_dwf_adj, Dtilde_op, g5R5, cayley_op, dense_op
+from .lattice import restrict, norm2, hop
 
 EVEN, ODD = 0, 1
 
@@ -138,3 +138,38 @@ def solve_mirror(act, U, sys, phi, iters=None, tol=1e-10):
     schur = np.sqrt(norm2(bt - S.mhat(xo)) / norm2(phi))
     return dict(psi=psi, psi_prime=xp, iters=n, hist=hist, true_resid=res,
                 schur_resid=schur, schur_source=bt, x_odd=xo)
+
+
+class DenseSchurSystem(SchurSystem):
+    """Even-odd Schur complement of the non-Cayley form gamma_5 R5 (H + beta
+    Delta P) (dense_op): off-parity blocks the Wilson hop alone, same-parity
+    blocks D_ee = (4 - M5) + M_chi(m_op) (+ chi beta R5 Delta_chi), dense in s
+    (App. A closed forms; the comparison route to App. B.2's preconditioned
+    form). Inverses by LU."""
+
+    def __init__(self, act, U, sys):
+        self.act, self.U, self.sys = act, U, sys
+        self.Ap, self.Am = fifth.dense_blocks(act.Ls, act.M5, act.c, act.d, sys.m_op, sys.beta,
+                                              sys.chi, sys.m_a, sys.m_b)
+        self.Ip, self.Im = np.linalg.inv(self.Ap), np.linalg.inv(self.Am)
+
+    def hop_block(self, x, out_par):
+        d = self.act.dims
+        return restrict(hop(self.U, restrict(x, d, 1 - out_par), self.act.bc), d, out_par)
+
+    def hop_block_adj(self, x, out_par):
+        d = self.act.dims
+        return restrict(hop(self.U, restrict(x, d, 1 - out_par), self.act.bc, adjoint=True), d, out_par)
+
+
+def solve_dense_form(act, U, sys, phi, iters=None, tol=1e-10):
+    """The EOFA system without Cayley preconditioning: b = gamma_5 R5 phi,
+    odd Schur complement of dense_op, CGNR, psi_e = D_ee^-1 (b_e - Dhop psi_o).
+    Returns psi, iters, history and |b - dense_op psi| / |b|."""
+    S = DenseSchurSystem(act, U, sys)
+    b = g5R5(phi)
+    bt = S.schur_source(b)
+    xo, n, hist = cgnr(S.mhat, S.mhat_adj, bt, iters=iters, tol=tol)
+    psi = S.reconstruct(xo, b)
+    res = np.sqrt(norm2(b - dense_op(act, U, sys, psi)) / norm2(b))
+    return dict(psi=psi, iters=n, hist=hist, true_resid=res, schur_source=bt, x_odd=xo)

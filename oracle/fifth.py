@@ -16,6 +16,9 @@ Sources:
 * Shamir forms                    App. A (Shamir kernel)
 * u_+-, v_+-                      App. B.2, eqn delta_rank_one
 * R5                              Sec. II, (R5)_{ss'} = delta_{s, Ls-1-s'}
+* dense same-site block           eqn eofa_dop_def with D_W -> (4 - M5), plus
+                                  gamma_5 R5 times the shift of eqn
+                                  generic_eofa_system
 """
 import numpy as np
 
@@ -207,3 +210,20 @@ def sherman_morrison_inverse(A0, sigma, u, v):
     if den == 0.0:
         raise ZeroDivisionError("Sherman-Morrison denominator vanishes")
     return A0i - sigma * np.outer(x, v @ A0i) / den
+
+
+def dense_blocks(Ls, M5, c, d, m_op, beta=0.0, chi=0, m_a=0.0, m_b=0.0):
+    """Same-site block of gamma_5 R5 (H(m_op) + beta Delta_chi P_chi), per chirality.
+
+    gamma_5 R5 H = D_EOFA (Sec. II); its site-local part is (4 - M5) 1 + M_+-
+    (eqn eofa_dop_def, App. A closed forms). gamma_5 R5 beta Delta_chi P_chi
+    acts on chirality chi as chi beta R5 Delta_chi (gamma_5 = chi there).
+    Dense in s: the system without the Cayley-form preconditioning.
+    """
+    out = []
+    for chir in (+1, -1):
+        A = (4.0 - M5) * np.eye(Ls) + M_closed(Ls, c, d, m_op, chir)
+        if beta != 0.0 and chi == chir:
+            A = A + chir * beta * R5(Ls) @ Delta(Ls, c, d, m_a, m_b, chir)
+        out.append(A)
+    return out[0], out[1]

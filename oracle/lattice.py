@@ -107,7 +107,7 @@ def hop(U, psi, bc, adjoint=False):
 
 def hop_gparity(U, psi, bc, adjoint=False):
     """Dhop with G-parity boundary conditions in x (Sec. II mentions G-parity
-    ensembles; the operator form is this build's reading): flavour-doubled
+    ensembles but gives no operator form; this one is a reading): flavour-doubled
     fields psi[f] (axis 0, f = 0, 1); flavour 0 hops with U, flavour 1 with
     conj(U); across the x edge the fields obey psi(x + L) = Tw psi(x) with
     Tw = [[0, 1], [-1, 0]] on (psi_0, psi_1) and the links U(x + L) = conj(U(x)).

@@ -446,23 +446,40 @@ int put(eofa_ctx* C, void* dev, const void* host, size_t bytes, hipStream_t st) 
   return EOFA_OK;
 }
 
+// The kernels and fifth-dimension matrices of one form of the odd Schur
+// system. Cayley (App. B.2): off-parity blocks Dhop D~, same-parity M_ee.
+// Dense (the EOFA matrix itself, for comparison): off-parity blocks Dhop,
+// same-parity D_ee = M_ee D~^-1, both forms with the same residual b - D psi.
+struct Form {
+  int k1, k2, k3, k4, k4s, src, res, fullres;  // roles
+  int m1, m2, m3, m4a, m4b;                     // matA of K1, matB of K2, matA of K3, matA/matB of K4
+  int inv, diag;                                // same-parity block inverse / block (source, residual)
+  bool cayley;                                  // psi = D~ psi' on reconstruction, guess through D~^-1
+};
+const Form kCayley = {ROLE_K1, ROLE_K2, ROLE_K3, ROLE_K4, ROLE_K4S, ROLE_SRC, ROLE_RES, ROLE_FULLRES,
+                      MAT_MEE_INV, MAT_MEE, MAT_MEE_INV_T, MAT_NEG_DT_T, MAT_MEE_T,
+                      MAT_MEE_INV, MAT_MEE, true};
+const Form kDense = {ROLE_D1, ROLE_D2, ROLE_D3, ROLE_D4, ROLE_D4S, ROLE_DSRC, ROLE_DRES, ROLE_DFULLRES,
+                     MAT_DEE_INV, MAT_DEE, MAT_DEE_INV_T, 0, MAT_DEE_T,
+                     MAT_DEE_INV, MAT_DEE, false};
+
 // One inner CGNR iteration: K1, K2, alpha, K3, K4, beta, x/p update.
-int inner_iteration(eofa_ctx* C, int S, int PR, const HopArgs& k1, const HopArgs& k2, const HopArgs& k3,
-                    const HopArgs& k4, int nbh, int nrhs, CgState Sst, double* partial, void* xin, void* rin,
-                    void* pS, hipStream_t st, hipEvent_t* ev) {
+int inner_iteration(eofa_ctx* C, const Form& F, int S, int PR, const HopArgs& k1, const HopArgs& k2,
+                    const HopArgs& k3, const HopArgs& k4, int nbh, int nrhs, CgState Sst, double* partial,
+                    void* xin, void* rin, void* pS, hipStream_t st, hipEvent_t* ev) {
   const Geometry& g = C->g;
   if (ev) HIPCHK(hipEventRecord(ev[0], st));
-  CHK(hop(C, S, ROLE_K1, k1, st));
+  CHK(hop(C, S, F.k1, k1, st));
   if (ev) HIPCHK(hipEventRecord(ev[1], st));
   if (ev) HIPCHK(hipEventRecord(ev[2], st));
-  CHK(hop(C, S, ROLE_K2, k2, st));
+  CHK(hop(C, S, F.k2, k2, st));
   if (ev) HIPCHK(hipEventRecord(ev[3], st));
   launch_finalize(FIN_ALPHA, partial, nbh, nrhs, Sst, nullptr, st);
   if (ev) HIPCHK(hipEventRecord(ev[4], st));
-  CHK(hop(C, S, ROLE_K3, k3, st));
+  CHK(hop(C, S, F.k3, k3, st));
   if (ev) HIPCHK(hipEventRecord(ev[5], st));
   if (ev) HIPCHK(hipEventRecord(ev[6], st));
-  CHK(hop(C, S, ROLE_K4, k4, st));
+  CHK(hop(C, S, F.k4, k4, st));
   if (ev) HIPCHK(hipEventRecord(ev[7], st));
   launch_finalize(FIN_BETA, partial, nbh, nrhs, Sst, nullptr, st);
   launch_cg_update(S, PR, g, xin, rin, pS, Sst.alpha, Sst.beta, Sst.u2run, nrhs, st);
@@ -472,14 +489,17 @@ int inner_iteration(eofa_ctx* C, int S, int PR, const HopArgs& k1, const HopArgs
 // Autotuner: time the four inner hop kernels for each (waves per
 // work-group, right-hand sides per work-group) candidate on the solve's own
 // buffers (halt flags off, before the CG state exists) and keep the fastest.
-int autotune(eofa_ctx* C, int S, int nrhs, HopArgs k1, HopArgs k2, HopArgs k3, HopArgs k4, hipStream_t st) {
-  const int key = S * 4096 + nrhs;
+int tune_key(const Form& F, int S, int nrhs) { return ((F.cayley ? 0 : 8) + S) * 4096 + nrhs; }
+
+int autotune(eofa_ctx* C, const Form& F, int S, int nrhs, HopArgs k1, HopArgs k2, HopArgs k3, HopArgs k4,
+             hipStream_t st) {
+  const int key = tune_key(F, S, nrhs);
   if (C->tuned.count(key)) return EOFA_OK;
   const int Ls = C->g.Ls;
   std::vector<int> waves, blocks;
   for (int w : {1, 2, 4}) {
     bool fits = true;
-    for (int role : {ROLE_K1, ROLE_K2, ROLE_K3, ROLE_K4})
+    for (int role : {F.k1, F.k2, F.k3, F.k4})
       fits = fits && hop_lds_bytes(S, role, Ls, w) <= 65536;
     if (fits) waves.push_back(w);
   }
@@ -499,7 +519,7 @@ int autotune(eofa_ctx* C, int S, int nrhs, HopArgs k1, HopArgs k2, HopArgs k3, H
         x.rhs_block = rb;
         x.halt = nullptr;
       }
-      const int roles[4] = {ROLE_K1, ROLE_K2, ROLE_K3, ROLE_K4};
+      const int roles[4] = {F.k1, F.k2, F.k3, F.k4};
       for (int k = 0; k < 4; ++k) CHK(hop(C, S, roles[k], a[k], st));  // warm-up
       HIPCHK(hipEventRecord(e0, st));
       for (int rep = 0; rep < 2; ++rep)
@@ -521,8 +541,9 @@ int autotune(eofa_ctx* C, int S, int nrhs, HopArgs k1, HopArgs k2, HopArgs k3, H
 
 // psi'_e = M_ee^-1 (b_e - Dhop D~ x_o), the FP64 true residual of the
 // Cayley system per parity (re, rodd: |.|^2 per rhs), psi = D~ psi' unpacked
-// to the canonical layout. Overwrites te, tmp, ro; synchronises.
-int reconstruct(eofa_ctx* C, int nrhs, void* x, void* be, void* bo, void* te, void* tmp, void* ro,
+// to the canonical layout (dense form: psi_e = D_ee^-1 (b_e - Dhop x_o), psi
+// itself unpacked). Overwrites te, tmp, ro; synchronises.
+int reconstruct(eofa_ctx* C, const Form& F, int nrhs, void* x, void* be, void* bo, void* te, void* tmp, void* ro,
                 double* partial, CgState Sst, void* psi, std::vector<double>& re, std::vector<double>& rodd,
                 hipStream_t st) {
   const Geometry& g = C->g;
@@ -534,20 +555,20 @@ int reconstruct(eofa_ctx* C, int nrhs, void* x, void* be, void* bo, void* te, vo
     a.in = x;
     a.z = be;
     a.out = tmp;
-    CHK(hop(C, P64, ROLE_SRC, a, st));
+    CHK(hop(C, P64, F.src, a, st));
   }
-  launch_smat(P64, g, tmp, te, C->mats, MAT_MEE_INV, nrhs, st);
-  // FP64 true residual of the Cayley system on both parities
+  launch_smat(P64, g, tmp, te, C->mats, F.inv, nrhs, st);
+  // FP64 true residual of the system on both parities
   {
     HopArgs a = base_args(C, P64, 0, nrhs);
     a.in = x;
     a.y = te;
     a.z = be;
     a.out = tmp;
-    a.matB = MAT_MEE;
+    a.matB = F.diag;
     a.partial = partial;
     int nb = 0;
-    CHK(hop(C, P64, ROLE_FULLRES, a, st, &nb));
+    CHK(hop(C, P64, F.fullres, a, st, &nb));
     launch_finalize(FIN_NORM, partial, nb, nrhs, Sst, Sst.norm, st);
     CHK(fetch(C, Sst.norm, nrhs * sizeof(double), re.data(), st));
     HopArgs b = base_args(C, P64, 1, nrhs);
@@ -555,17 +576,21 @@ int reconstruct(eofa_ctx* C, int nrhs, void* x, void* be, void* bo, void* te, vo
     b.y = x;
     b.z = bo;
     b.out = ro;
-    b.matB = MAT_MEE;
+    b.matB = F.diag;
     b.partial = partial;
-    CHK(hop(C, P64, ROLE_FULLRES, b, st, &nb));
+    CHK(hop(C, P64, F.fullres, b, st, &nb));
     launch_finalize(FIN_NORM, partial, nb, nrhs, Sst, Sst.norm, st);
     CHK(fetch(C, Sst.norm, nrhs * sizeof(double), rodd.data(), st));
   }
-  // psi = D~ psi'
-  launch_smat(P64, g, te, tmp, C->mats, MAT_DT, nrhs, st);
-  launch_unpack(P64, g, tmp, psi, 0, nrhs, st);
-  launch_smat(P64, g, x, ro, C->mats, MAT_DT, nrhs, st);
-  launch_unpack(P64, g, ro, psi, 1, nrhs, st);
+  if (F.cayley) {  // psi = D~ psi'
+    launch_smat(P64, g, te, tmp, C->mats, MAT_DT, nrhs, st);
+    launch_unpack(P64, g, tmp, psi, 0, nrhs, st);
+    launch_smat(P64, g, x, ro, C->mats, MAT_DT, nrhs, st);
+    launch_unpack(P64, g, ro, psi, 1, nrhs, st);
+  } else {
+    launch_unpack(P64, g, te, psi, 0, nrhs, st);
+    launch_unpack(P64, g, x, psi, 1, nrhs, st);
+  }
   HIPCHK(hipStreamSynchronize(st));
   HIPCHK(hipGetLastError());
   return EOFA_OK;
@@ -577,6 +602,7 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
                 const double* tolr = nullptr) {
   const double t0 = now_s();
   const Geometry& g = C->g;
+  const Form& F = prm->form == 1 ? kDense : kCayley;
   const int S = prm->inner_prec;
   const int PR = S == P64 ? P64 : P32;
   const bool fixed = prm->fixed_iters > 0;
@@ -626,19 +652,21 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
     }
   }
 
-  // Schur source b~_o = b_o - Dhop D~ M_ee^-1 b_e
-  launch_smat(P64, g, be, te, C->mats, MAT_MEE_INV, nrhs, st);
+  // Schur source b~_o = b_o - Dhop D~ M_ee^-1 b_e (dense: b_o - Dhop D_ee^-1 b_e)
+  launch_smat(P64, g, be, te, C->mats, F.inv, nrhs, st);
   {
     HopArgs a = base_args(C, P64, 1, nrhs);
     a.in = te;
     a.z = bo;
     a.out = bt;
-    CHK(hop(C, P64, ROLE_SRC, a, st));
+    CHK(hop(C, P64, F.src, a, st));
   }
-  if (prm->use_guess) {
+  if (prm->use_guess && F.cayley) {
     // x_o = (D~^-1 psi)_o: the right-preconditioned unknown of the guess
     launch_pack(P64, g, psi, tmp, 1, nrhs, 0, st);
     launch_smat(P64, g, tmp, x, C->mats, MAT_DT_INV, nrhs, st);
+  } else if (prm->use_guess) {
+    launch_pack(P64, g, psi, x, 1, nrhs, 0, st);
   } else {
     launch_zero(P64, g, x, nrhs, st);
   }
@@ -657,32 +685,32 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
   HopArgs k1 = base_args(C, S, 0, nrhs);
   k1.in = pS;
   k1.out = tS;
-  k1.matA = MAT_MEE_INV;
+  k1.matA = F.m1;
   k1.halt = Sst.halt;
   HopArgs k2 = base_args(C, S, 1, nrhs);
   k2.in = tS;
   k2.y = pS;
   k2.out = wS;
-  k2.matB = MAT_MEE;
+  k2.matB = F.m2;
   k2.partial = partial;
   k2.halt = Sst.halt;
   HopArgs k3 = base_args(C, S, 0, nrhs);
   k3.in = wS;
   k3.out = tS;
-  k3.matA = MAT_MEE_INV_T;
+  k3.matA = F.m3;
   k3.halt = Sst.halt;
   HopArgs k4 = base_args(C, S, 1, nrhs);
   k4.in = tS;
   k4.y = wS;
   k4.r = rin;
-  k4.matA = MAT_NEG_DT_T;
-  k4.matB = MAT_MEE_T;
+  k4.matA = F.m4a;
+  k4.matB = F.m4b;
   k4.alpha = Sst.alpha;
   k4.partial = partial;
   k4.halt = Sst.halt;
   if (prm->rhs_block <= 0 && prm->waves <= 0) {
-    CHK(autotune(C, S, nrhs, k1, k2, k3, k4, st));
-    const auto pick = C->tuned[S * 4096 + nrhs];
+    CHK(autotune(C, F, S, nrhs, k1, k2, k3, k4, st));
+    const auto pick = C->tuned[tune_key(F, S, nrhs)];
     for (HopArgs* x : {&k1, &k2, &k3, &k4}) {
       x->W = pick.first;
       x->rhs_block = pick.second;
@@ -698,17 +726,17 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
       HopArgs a1 = base_args(C, P64, 0, nrhs);
       a1.in = x;
       a1.out = te;
-      a1.matA = MAT_MEE_INV;
-      CHK(hop(C, P64, ROLE_K1, a1, st));
+      a1.matA = F.m1;
+      CHK(hop(C, P64, F.k1, a1, st));
       HopArgs a2 = base_args(C, P64, 1, nrhs);
       a2.in = te;
       a2.y = x;
       a2.z = bt;
       a2.out = ro;
-      a2.matB = MAT_MEE;
+      a2.matB = F.m2;
       a2.partial = partial;
       int nb = 0;
-      CHK(hop(C, P64, ROLE_RES, a2, st, &nb));
+      CHK(hop(C, P64, F.res, a2, st, &nb));
       launch_finalize(FIN_NORM, partial, nb, nrhs, Sst, Sst.norm, st);
       rro.resize(nrhs);
       CHK(fetch(C, Sst.norm, nrhs * sizeof(double), rro.data(), st));
@@ -749,17 +777,17 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
       HopArgs a3 = base_args(C, S, 0, nrhs);
       a3.in = rS;
       a3.out = tS;
-      a3.matA = MAT_MEE_INV_T;
-      CHK(hop(C, S, ROLE_K3, a3, st));
+      a3.matA = F.m3;
+      CHK(hop(C, S, F.k3, a3, st));
       HopArgs a4 = base_args(C, S, 1, nrhs);
       a4.in = tS;
       a4.y = rS;
       a4.r = rin;
-      a4.matA = MAT_NEG_DT_T;
-      a4.matB = MAT_MEE_T;
+      a4.matA = F.m4a;
+      a4.matB = F.m4b;
       a4.partial = partial;
       int nb = 0;
-      CHK(hop(C, S, ROLE_K4S, a4, st, &nb));
+      CHK(hop(C, S, F.k4s, a4, st, &nb));
       launch_finalize(FIN_INIT, partial, nb, nrhs, Sst, nullptr, st);
     }
     launch_convert(PR, S, g, rin, pS, nrhs, st);
@@ -791,7 +819,8 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
       hipGraphExec_t exec;
       HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
       for (int k = 0; k < check; ++k) {
-        const int rc = inner_iteration(C, S, PR, k1, k2, k3, k4, nbh, nrhs, Sst, partial, xin, rin, pS, cs, nullptr);
+        const int rc =
+            inner_iteration(C, F, S, PR, k1, k2, k3, k4, nbh, nrhs, Sst, partial, xin, rin, pS, cs, nullptr);
         if (rc != EOFA_OK) {
           hipGraph_t dead;
           (void)hipStreamEndCapture(cs, &dead);
@@ -822,7 +851,7 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
         // events bracket the kernels and not host launch latency
         const bool prof = prm->profile && timed < max_timed && (it % 8 == 4);
         hipEvent_t* ev = prof ? &C->events[timed * 8] : nullptr;
-        CHK(inner_iteration(C, S, PR, k1, k2, k3, k4, nbh, nrhs, Sst, partial, xin, rin, pS, st, ev));
+        CHK(inner_iteration(C, F, S, PR, k1, k2, k3, k4, nbh, nrhs, Sst, partial, xin, rin, pS, st, ev));
         if (prof) ++timed;
         ++it;
         if (it % check == 0 || it >= cap) {
@@ -849,7 +878,7 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
   }
 
   std::vector<double> re, rodd;
-  CHK(reconstruct(C, nrhs, x, be, bo, te, tmp, ro, partial, Sst, psi, re, rodd, st));
+  CHK(reconstruct(C, F, nrhs, x, be, bo, te, tmp, ro, partial, Sst, psi, re, rodd, st));
   const double t1 = now_s();
   for (int j = 0; j < timed; ++j) {  // events are read only after the solve: no mid-solve host stalls
     float ms;
@@ -893,6 +922,9 @@ int check_params(const eofa_solver_params* prm) {
   if (prm->precond != 0 && prm->precond != 1) return fail(EOFA_ERR_INVALID, "precond must be 0 or 1");
   if (prm->precond == 1 && prm->fixed_iters > 0)
     return fail(EOFA_ERR_INVALID, "fixed_iters applies to CGNR only (precond = 0)");
+  if (prm->form != 0 && prm->form != 1) return fail(EOFA_ERR_INVALID, "form must be 0 or 1");
+  if (prm->form == 1 && prm->precond != 0)
+    return fail(EOFA_ERR_INVALID, "the dense form (form = 1) is solved by CGNR only (precond = 0)");
   return EOFA_OK;
 }
 
@@ -1231,7 +1263,7 @@ int fgcg_one(eofa_ctx* C, const eofa_system* sys, const void* phi, void* psi, co
     return rc;
   }
   std::vector<double> re, rodd;
-  CHK(reconstruct(C, 1, F.x, F.be, F.bo, F.te, F.tmp, F.s, F.partial, F.Sst, psi, re, rodd, st));
+  CHK(reconstruct(C, kCayley, 1, F.x, F.be, F.bo, F.te, F.tmp, F.s, F.partial, F.Sst, psi, re, rodd, st));
   const double tr = F.bb > 0 ? std::sqrt((re[0] + rodd[0]) / F.bb) : ((re[0] + rodd[0]) == 0.0 ? 0.0 : NAN);
   const bool conv = std::isfinite(tr) && tr <= prm->tol;
   if (status == EOFA_OK && !conv) status = std::isfinite(tr) ? EOFA_ERR_NOT_CONVERGED : EOFA_ERR_BREAKDOWN;
@@ -1463,6 +1495,7 @@ extern "C" int eofa_heatbath_solve(eofa_ctx* C, double m1, double m2, int32_t n_
   if (eta == phi) return fail(EOFA_ERR_INVALID, "eofa_heatbath_solve: eta and phi alias");
   if (n_poles < 1) return fail(EOFA_ERR_INVALID, "n_poles must be >= 1");
   CHK(check_params(prm));
+  if (prm->form != 0) return fail(EOFA_ERR_INVALID, "eofa_heatbath_solve: form must be 0 (Cayley)");
   if (pole_tol)
     for (int r = 0; r < 2 * n_poles; ++r)
       if (!(pole_tol[r] > 0.0)) return fail(EOFA_ERR_INVALID, "pole_tol entries must be > 0");
@@ -1586,6 +1619,7 @@ extern "C" int eofa_force(eofa_ctx* C, double m1, double m2, const void* phi, vo
   if (!std::isfinite(m1) || !std::isfinite(m2)) return fail(EOFA_ERR_INVALID, "eofa_force: non-finite mass");
   CHK(check_params(prm));
   if (prm->precond != 0) return fail(EOFA_ERR_INVALID, "eofa_force: precond must be 0 (batched CGNR)");
+  if (prm->form != 0) return fail(EOFA_ERR_INVALID, "eofa_force: form must be 0 (Cayley)");
   hipStream_t st = (hipStream_t)stream;
   const Geometry& g = C->g;
   // chi_1 = H(m1)^-1 Omega_- P_- phi,  chi_2 = [H(m2) - Delta_+(m1,m2) P_+]^-1 Omega_+ P_+ phi

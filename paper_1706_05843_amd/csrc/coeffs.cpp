@@ -204,6 +204,10 @@ int build_fifth(const Geometry& g, double M5, double b5, double c5, const eofa_s
     mats[MAT_DT_T] = DtT;
     mats[MAT_DT] = Dt;
     mats[MAT_DT_INV] = Dinv;
+    mats[MAT_DEE] = matmul(Mee, Dinv, n);
+    mats[MAT_DEE_INV] = matmul(Dt, Minv, n);
+    mats[MAT_DEE_T] = transpose(mats[MAT_DEE], n);
+    mats[MAT_DEE_INV_T] = transpose(mats[MAT_DEE_INV], n);
     for (int m = 0; m < NMAT; ++m)
       std::memcpy(out + ((size_t)m * 2 + ci) * n * n, mats[m].data(), sizeof(double) * n * n);
   }

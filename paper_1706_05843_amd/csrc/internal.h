@@ -26,6 +26,10 @@ enum MatId {
   MAT_DT_T,            // D~^T
   MAT_DT,              // D~ = (c+d) + (c-d) L(m_op)
   MAT_DT_INV,          // D~^-1 (initial guesses: psi' = D~^-1 psi)
+  MAT_DEE,             // dense form: D_ee = M_ee D~^-1 (App. B.2, same-parity block of D_EOFA + shift)
+  MAT_DEE_INV,         // D_ee^-1 = D~ M_ee^-1
+  MAT_DEE_T,           // D_ee^T
+  MAT_DEE_INV_T,       // D_ee^-T
   NMAT
 };
 
@@ -79,6 +83,15 @@ enum HopRole {
   ROLE_SRC,          // out = z - Dhop D~ in
   ROLE_RES,          // out = z - (B y - Dhop D~ in), |out|^2
   ROLE_FULLRES,      // out = z - (B y + Dhop D~ in), |out|^2
+  // dense (non-Cayley) form, App. B.2: off-parity blocks Dhop, same-parity D_ee dense
+  ROLE_D1,           // out = A (Dhop in)
+  ROLE_D2,           // out = B y - Dhop in, |out|^2
+  ROLE_D3,           // out = A (g5 Dhop g5 in)
+  ROLE_D4,           // r -= alpha (B y - g5Dhopg5 in), |r|^2
+  ROLE_D4S,          // r  = B y - g5Dhopg5 in, |r|^2
+  ROLE_DSRC,         // out = z - Dhop in
+  ROLE_DRES,         // out = z - (B y - Dhop in), |out|^2
+  ROLE_DFULLRES,     // out = z - (B y + Dhop in), |out|^2
   NROLE
 };
 

@@ -36,7 +36,7 @@ namespace eofa {
 // plus the same-site term B y:
 //   B_MEE   + M_ee y           B_MEET + M_ee^T y    (structured: lane exchange)
 enum { A_ID = 0, A_NEG = 1, A_MAT = 2, A_DTT = 3, A_NDTT = 4, A_MATDT = 5 };
-enum { B_NONE = 0, B_MEE = 1, B_MEET = 2 };
+enum { B_NONE = 0, B_MEE = 1, B_MEET = 2, B_DENSE = 3 };
 enum { O_STORE = 0, O_ADDZ = 1, O_RUPD = 2, O_STORE_R = 3 };
 
 template <int ROLE>
@@ -60,6 +60,15 @@ EOFA_ROLE(ROLE_K4S, true, false, A_NDTT, B_MEET, O_STORE_R, true)
 EOFA_ROLE(ROLE_SRC, false, true, A_ID, B_NONE, O_ADDZ, false)
 EOFA_ROLE(ROLE_RES, false, true, A_NEG, B_MEE, O_ADDZ, true)
 EOFA_ROLE(ROLE_FULLRES, false, true, A_ID, B_MEE, O_ADDZ, true)
+// dense (non-Cayley) form: off-parity blocks Dhop alone, same-parity blocks dense
+EOFA_ROLE(ROLE_D1, false, false, A_MAT, B_NONE, O_STORE, false)
+EOFA_ROLE(ROLE_D2, false, false, A_NEG, B_DENSE, O_STORE, true)
+EOFA_ROLE(ROLE_D3, true, false, A_MAT, B_NONE, O_STORE, false)
+EOFA_ROLE(ROLE_D4, true, false, A_NEG, B_DENSE, O_RUPD, true)
+EOFA_ROLE(ROLE_D4S, true, false, A_NEG, B_DENSE, O_STORE_R, true)
+EOFA_ROLE(ROLE_DSRC, false, false, A_ID, B_NONE, O_ADDZ, false)
+EOFA_ROLE(ROLE_DRES, false, false, A_NEG, B_DENSE, O_ADDZ, true)
+EOFA_ROLE(ROLE_DFULLRES, false, false, A_ID, B_DENSE, O_ADDZ, true)
 #undef EOFA_ROLE
 
 constexpr int LSTR = 73;  // padded link stride per site in LDS (complex units)
@@ -416,14 +425,14 @@ hop_kernel(HopArgs a) {
   const FD fd = {Ls, Vh, a.nrhs};
 
   constexpr bool DENSE = RT::AM == A_MAT || RT::AM == A_MATDT;
-  constexpr bool COL = DENSE || RT::BM == B_MEET;  // needs the LDS column buffer
+  constexpr bool BDENSE = RT::BM == B_DENSE;  // never together with DENSE: one matrix in LDS
   unsigned char* p = smem;
   cx<R>* s_link = (cx<R>*)p;
   p += L::links(SBk);
   int* s_nbr = (int*)p;
   p += L::nbr(SBk);
   R* s_mA = (R*)p;
-  if (DENSE) p += L::mat(Ls);
+  if (DENSE || BDENSE) p += L::mat(Ls);
   cx<R>* s_col = (cx<R>*)p;  // SBk x (Ls*6+1) complex: one chirality half of each column
   const int cstr = Ls * 6 + 1;
   (void)s_col;
@@ -448,9 +457,9 @@ hop_kernel(HopArgs a) {
   for (int r = rb0; r < rb1; ++r) {
     if (a.halt != nullptr && a.halt[r] != 0) continue;  // uniform over the block
     __syncthreads();
-    if constexpr (DENSE) {
+    if constexpr (DENSE || BDENSE) {
       const double* mats_r = a.mats + (size_t)r * NMAT * 2 * Ls * Ls;
-      load_mat<R>(s_mA, mats_r + (size_t)a.matA * 2 * Ls * Ls, Ls, tid, nthr);
+      load_mat<R>(s_mA, mats_r + (size_t)(DENSE ? a.matA : a.matB) * 2 * Ls * Ls, Ls, tid, nthr);
     }
     __syncthreads();
 
@@ -503,7 +512,19 @@ hop_kernel(HopArgs a) {
         col_matvec<R>(s_mA, mycol, Ls, s, half, v, false);
       }
     }
-    if constexpr (RT::BM != B_NONE) {
+    if constexpr (BDENSE) {  // v += M y, M dense per chirality, through the column in LDS
+      cx<R> y[12];
+      ld_spinor<P>(a.y, fd, r, s, EOFA_SITE, y);
+      cx<R>* mycol = s_col + ls * cstr;
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        if (half == 1) __syncthreads();
+        if (in_col)
+          for (int c = 0; c < 6; ++c) mycol[s * 6 + c] = y[half * 6 + c];
+        __syncthreads();
+        col_matvec<R>(s_mA, mycol, Ls, s, half, v, true);
+      }
+    } else if constexpr (RT::BM != B_NONE) {
       // + M_ee y (B_MEE) or + M_ee^T y (B_MEET):
       //   bee y - cee L y (L^T y) + sk u e_{s*}^T y (sk e_{s*} u^T y) on chirality chi
       cx<R> y[12], t[12];
@@ -595,7 +616,7 @@ size_t hop_lds_t(int Ls, int W) {
   using RT = RoleT<ROLE>;
   using L = HopLds<R>;
   const int SBk = W * sites_per_wave(Ls);
-  constexpr bool DENSE = RT::AM == A_MAT || RT::AM == A_MATDT;
+  constexpr bool DENSE = RT::AM == A_MAT || RT::AM == A_MATDT || RT::BM == B_DENSE;
   size_t lds = L::links(SBk) + L::nbr(SBk);
   if (DENSE) lds += L::mat(Ls);
   if (DENSE || RT::BM == B_MEET) lds += L::col(SBk, Ls);
@@ -615,6 +636,14 @@ size_t hop_lds_p(int role, int Ls, int W) {
     case ROLE_SRC: return hop_lds_t<P, ROLE_SRC>(Ls, W);
     case ROLE_RES: return hop_lds_t<P, ROLE_RES>(Ls, W);
     case ROLE_FULLRES: return hop_lds_t<P, ROLE_FULLRES>(Ls, W);
+    case ROLE_D1: return hop_lds_t<P, ROLE_D1>(Ls, W);
+    case ROLE_D2: return hop_lds_t<P, ROLE_D2>(Ls, W);
+    case ROLE_D3: return hop_lds_t<P, ROLE_D3>(Ls, W);
+    case ROLE_D4: return hop_lds_t<P, ROLE_D4>(Ls, W);
+    case ROLE_D4S: return hop_lds_t<P, ROLE_D4S>(Ls, W);
+    case ROLE_DSRC: return hop_lds_t<P, ROLE_DSRC>(Ls, W);
+    case ROLE_DRES: return hop_lds_t<P, ROLE_DRES>(Ls, W);
+    case ROLE_DFULLRES: return hop_lds_t<P, ROLE_DFULLRES>(Ls, W);
   }
   return 0;
 }
@@ -658,6 +687,14 @@ int launch_hop_p(int role, const HopArgs& a, hipStream_t st, int* nb) {
     case ROLE_SRC: return launch_hop_t<P, ROLE_SRC>(a, st, nb);
     case ROLE_RES: return launch_hop_t<P, ROLE_RES>(a, st, nb);
     case ROLE_FULLRES: return launch_hop_t<P, ROLE_FULLRES>(a, st, nb);
+    case ROLE_D1: return launch_hop_t<P, ROLE_D1>(a, st, nb);
+    case ROLE_D2: return launch_hop_t<P, ROLE_D2>(a, st, nb);
+    case ROLE_D3: return launch_hop_t<P, ROLE_D3>(a, st, nb);
+    case ROLE_D4: return launch_hop_t<P, ROLE_D4>(a, st, nb);
+    case ROLE_D4S: return launch_hop_t<P, ROLE_D4S>(a, st, nb);
+    case ROLE_DSRC: return launch_hop_t<P, ROLE_DSRC>(a, st, nb);
+    case ROLE_DRES: return launch_hop_t<P, ROLE_DRES>(a, st, nb);
+    case ROLE_DFULLRES: return launch_hop_t<P, ROLE_DFULLRES>(a, st, nb);
   }
   return EOFA_ERR_INVALID;
 }

@@ -46,7 +46,7 @@ int main(void) {
   printf("%zu %zu %zu %zu\n", sizeof(eofa_action), sizeof(eofa_system), sizeof(eofa_solver_params), sizeof(eofa_solver_stats));
   printf("%zu %zu %zu %zu %zu\n", offsetof(eofa_action, M5), offsetof(eofa_action, bc), offsetof(eofa_solver_params, inner_tol), offsetof(eofa_solver_stats, hop_ms), offsetof(eofa_solver_params, waves));
   printf("%zu %zu %zu\n", offsetof(eofa_solver_params, precond), offsetof(eofa_solver_params, net), offsetof(eofa_solver_stats, fell_back));
-  printf("%zu\n", offsetof(eofa_solver_params, use_guess));
+  printf("%zu %zu\n", offsetof(eofa_solver_params, use_guess), offsetof(eofa_solver_params, form));
   return 0;
 }
 '''
@@ -63,7 +63,7 @@ int main(void) {
                          eofa.SolverParams.inner_tol.offset, eofa.SolverStats.hop_ms.offset,
                          eofa.SolverParams.waves.offset, eofa.SolverParams.precond.offset,
                          eofa.SolverParams.net.offset, eofa.SolverStats.fell_back.offset,
-                         eofa.SolverParams.use_guess.offset]
+                         eofa.SolverParams.use_guess.offset, eofa.SolverParams.form.offset]
 
 
 @pytest.mark.parametrize("bad", [
@@ -87,11 +87,15 @@ def _oracle_mats(Ls, M5, b5, c5, sysd):
     Ap, Am = fifth.mee_blocks(Ls, M5, c, d, m_op, beta, chi, m_a, m_b)
     Dp, Dm = fifth.Dtilde(Ls, c, d, m_op, +1), fifth.Dtilde(Ls, c, d, m_op, -1)
     Ip, Im = np.linalg.inv(Ap), np.linalg.inv(Am)
+    Ep, Em = fifth.dense_blocks(Ls, M5, c, d, m_op, beta, chi, m_a, m_b)
     return {
         "mee": (Ap, Am), "mee_inv": (Ip, Im), "mee_t": (Ap.T, Am.T), "mee_inv_t": (Ip.T, Im.T),
         "mee_inv_t_dt_t": (Ip.T @ Dp.T, Im.T @ Dm.T), "neg_dt_t": (-Dp.T, -Dm.T),
         "dt_t": (Dp.T, Dm.T), "dt": (Dp, Dm),
         "dt_inv": (fifth.Dtilde_inv_closed(Ls, c, d, m_op, +1), fifth.Dtilde_inv_closed(Ls, c, d, m_op, -1)),
+        # dense form from the App. A closed forms, not from M_ee D~^-1 as the library builds it
+        "dee": (Ep, Em), "dee_inv": (np.linalg.inv(Ep), np.linalg.inv(Em)), "dee_t": (Ep.T, Em.T),
+        "dee_inv_t": (np.linalg.inv(Ep).T, np.linalg.inv(Em).T),
     }
 
 
@@ -147,3 +151,16 @@ def test_pairs_and_solver_params_validation():
     rc = eofa.lib().eofa_cg_solve(dummy, sysl, dummy, ctypes.c_void_p(32), 1, ctypes.byref(prm), None, None)
     assert rc == eofa.EOFA_ERR_INVALID
 
+    for kw in (dict(form=2), dict(form=1, precond=1)):
+        prm = eofa.make_params(**kw)
+        rc = eofa.lib().eofa_cg_solve(dummy, sysl, dummy, ctypes.c_void_p(32), 1, ctypes.byref(prm), None, None)
+        assert rc == eofa.EOFA_ERR_INVALID, kw
+    # heatbath and force take the Cayley form only
+    prm = eofa.make_params(form=1)
+    a = (ctypes.c_double * 1)(1.0)
+    rc = eofa.lib().eofa_heatbath_solve(dummy, ctypes.c_double(0.1), ctypes.c_double(1.0), 1, a, a, None, dummy,
+                                        ctypes.c_void_p(32), ctypes.byref(prm), None, None)
+    assert rc == eofa.EOFA_ERR_INVALID
+    rc = eofa.lib().eofa_force(dummy, ctypes.c_double(0.1), ctypes.c_double(1.0), dummy, ctypes.c_void_p(32),
+                               ctypes.byref(prm), None, None)
+    assert rc == eofa.EOFA_ERR_INVALID

@@ -21,7 +21,7 @@ M1, M2 = 0.04, 1.0
 
 
 def systems():
-    """The systems the action, force and heatbath solve (BASELINE action)."""
+    """The systems the action, force and heatbath solve (m1 = 0.04, m2 = 1.0)."""
     return {
         "chi1": System(M1, M1, M2, 0.0, -1),
         "chi2": System(M2, M1, M2, -1.0, +1),
