@@ -46,10 +46,11 @@
  * with element = two complex numbers:
  *   EOFA_FP64  : 2 x (double re, double im)      32 bytes
  *   EOFA_FP32  : 2 x (float re, float im)        16 bytes
- *   EOFA_FP16S : 2 x (half re, half im)           8 bytes, plus one float
- *                scale per 5D site at (rhs*Vh + i)*Ls + s stored after
- *                the values; the site's 24 reals are value * scale with
- *                scale = max |re|, |im| of the site.
+ * EOFA_FP16S groups the components in quads j = c/4 (j = 0..2) instead:
+ * element (rhs, j, s, i) at ((rhs*3 + j)*Vh + i)*Ls + s holds
+ *   4 x (half re, half im)                        16 bytes, plus one float
+ *   scale per 5D site at (rhs*Vh + i)*Ls + s stored after the values; the
+ *   site's 24 reals are value * scale with scale = max |re|, |im| of the site.
  * eofa_packed_bytes() gives the size of one packed half-field block.
  *
  * Memory and streams

@@ -58,8 +58,14 @@ struct FD {
   int Ls, Vh, nrhs;
 };
 
-// element (r, q, s, i) = r * 6 * Vh * Ls + q * Vh * Ls + (i * Ls + s)
+// element (r, q, s, i) = r * 6 * Vh * Ls + q * Vh * Ls + (i * Ls + s); FP16S
+// groups the components in quads instead (uint4 element (r, j, s, i) at
+// r * 3 * Vh * Ls + j * Vh * Ls + (i * Ls + s)): one 16-byte load per lane
+// and quad, three per spinor, as many bytes per instruction as FP32 pairs
 __device__ __forceinline__ size_t qstride(const FD& f) { return (size_t)f.Vh * f.Ls; }
+__device__ __forceinline__ size_t qidx16(const FD& f, int r, int j, int s, int i) {
+  return (size_t)(r * 3 + j) * qstride(f) + (unsigned)(i * f.Ls + s);
+}
 __device__ __forceinline__ size_t eidx(const FD& f, int r, int q, int s, int i) {
   return (size_t)(r * 6 + q) * qstride(f) + (unsigned)(i * f.Ls + s);
 }
@@ -78,16 +84,11 @@ __device__ __forceinline__ void ld_pair(const void* base, size_t e, cx<typename 
     const double2 v0 = p[0], v1 = p[1];
     a = {v0.x, v0.y};
     b = {v1.x, v1.y};
-  } else if constexpr (P == P32) {
+  } else {
+    static_assert(P == P32, "FP16S fields are read by quads");
     const float4 v = ((const float4*)base)[e];
     a = {v.x, v.y};
     b = {v.z, v.w};
-  } else {
-    const uint2 v = ((const uint2*)base)[e];
-    const h2_t h0 = __builtin_bit_cast(h2_t, v.x);
-    const h2_t h1 = __builtin_bit_cast(h2_t, v.y);
-    a = {(float)h0.x, (float)h0.y};
-    b = {(float)h1.x, (float)h1.y};
   }
 }
 
@@ -98,39 +99,46 @@ __device__ __forceinline__ void st_pair(void* base, size_t e, cx<typename ST<P>:
     double2* p = (double2*)base + 2 * e;
     p[0] = make_double2(a.r, a.i);
     p[1] = make_double2(b.r, b.i);
-  } else if constexpr (P == P32) {
-    ((float4*)base)[e] = make_float4(a.r, a.i, b.r, b.i);
   } else {
-    h2_t h0, h1;
-    h0.x = (_Float16)a.r;
-    h0.y = (_Float16)a.i;
-    h1.x = (_Float16)b.r;
-    h1.y = (_Float16)b.i;
-    uint2 v;
-    v.x = __builtin_bit_cast(unsigned int, h0);
-    v.y = __builtin_bit_cast(unsigned int, h1);
-    ((uint2*)base)[e] = v;
+    static_assert(P == P32, "FP16S fields are written by quads");
+    ((float4*)base)[e] = make_float4(a.r, a.i, b.r, b.i);
   }
 }
 
-// load pairs [q0, q1) of the spinor at (r, s, i) into v[2*q0 .. 2*q1)
-template <int P, class R>
-__device__ __forceinline__ void ld_spinor(const void* base, const FD& f, int r, int s, int i, cx<R>* v,
-                                          int q0 = 0, int q1 = 6) {
-  R sc = R(1);
-  if constexpr (P == P16) sc = scale_ptr(base, f)[sidx(f, r, s, i)];
-  const size_t e0 = eidx(f, r, 0, s, i), qs = qstride(f);
+// the 12 raw half2 words (component c = word c) of an FP16S spinor
+__device__ __forceinline__ void ld_words16(const void* base, const FD& f, int r, int s, int i, unsigned* w) {
+  const size_t e0 = qidx16(f, r, 0, s, i), qs = qstride(f);
 #pragma unroll
-  for (int q = 0; q < 6; ++q) {
-    if (q < q0 || q >= q1) continue;
-    cx<R> a, b;
-    ld_pair<P>(base, e0 + q * qs, a, b);
-    if constexpr (P == P16) {
-      a = sc * a;
-      b = sc * b;
+  for (int j = 0; j < 3; ++j) {
+    const uint4 v = ((const uint4*)base)[e0 + j * qs];
+    w[4 * j] = v.x;
+    w[4 * j + 1] = v.y;
+    w[4 * j + 2] = v.z;
+    w[4 * j + 3] = v.w;
+  }
+}
+
+// the spinor at (r, s, i) into v[0..12)
+template <int P, class R>
+__device__ __forceinline__ void ld_spinor(const void* base, const FD& f, int r, int s, int i, cx<R>* v) {
+  if constexpr (P == P16) {
+    const R sc = scale_ptr(base, f)[sidx(f, r, s, i)];
+    unsigned w[12];
+    ld_words16(base, f, r, s, i, w);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const h2_t h = __builtin_bit_cast(h2_t, w[c]);
+      v[c] = {sc * (R)(float)h.x, sc * (R)(float)h.y};
     }
-    v[2 * q] = a;
-    v[2 * q + 1] = b;
+  } else {
+    const size_t e0 = eidx(f, r, 0, s, i), qs = qstride(f);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      cx<R> a, b;
+      ld_pair<P>(base, e0 + q * qs, a, b);
+      v[2 * q] = a;
+      v[2 * q + 1] = b;
+    }
   }
 }
 
@@ -141,13 +149,18 @@ __device__ __forceinline__ void st_spinor(void* base, const FD& f, int r, int s,
 #pragma unroll
     for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf((float)v[c].r), fabsf((float)v[c].i)));
     const float inv = m > 0.f ? 1.0f / m : 0.f;
-    const size_t e0 = eidx(f, r, 0, s, i), qs = qstride(f);
+    unsigned w[12];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      cx<float> a = {(float)v[2 * q].r * inv, (float)v[2 * q].i * inv};
-      cx<float> b = {(float)v[2 * q + 1].r * inv, (float)v[2 * q + 1].i * inv};
-      st_pair<P16>(base, e0 + q * qs, a, b);
+    for (int c = 0; c < 12; ++c) {
+      h2_t h;
+      h.x = (_Float16)((float)v[c].r * inv);
+      h.y = (_Float16)((float)v[c].i * inv);
+      w[c] = __builtin_bit_cast(unsigned int, h);
     }
+    const size_t e0 = qidx16(f, r, 0, s, i), qs = qstride(f);
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      ((uint4*)base)[e0 + j * qs] = make_uint4(w[4 * j], w[4 * j + 1], w[4 * j + 2], w[4 * j + 3]);
     float* sp = (float*)scale_ptr(base, f);
     sp[sidx(f, r, s, i)] = m;
   } else {

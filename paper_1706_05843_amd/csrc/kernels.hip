@@ -114,23 +114,153 @@ struct DirIn<P16> {
 template <int P>
 __device__ __forceinline__ void load_dir(const void* in, const FD& fin, int r, int s, int n, DirIn<P>& b) {
   if constexpr (P == P16) {
-    const size_t e0 = eidx(fin, r, 0, s, n), qs = qstride(fin);
     b.sc = scale_ptr(in, fin)[sidx(fin, r, s, n)];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      const uint2 v = ((const uint2*)in)[e0 + q * qs];
-      b.w[2 * q] = v.x;
-      b.w[2 * q + 1] = v.y;
-    }
+    ld_words16(in, fin, r, s, n, b.w);
   } else {
     ld_spinor<P>(in, fin, r, s, n, b.v);
   }
+}
+
+// FP16S: neighbour spinors and links stay in half precision through the
+// SU(3) products. Each link element sits in LDS as the two half2 words
+// (Re u, -Im u) and (Im u, Re u), so that one complex multiply-accumulate
+// of u and a projected half-spinor component h = (Re h, Im h) is two
+// v_dot2_f32_f16 (FP16 products, exact in FP32, summed in FP32):
+//   Re += (Re u, -Im u) . h,   Im += (Im u, Re u) . h.
+// The projection (1 +- g_mu) and the D~ premix run on packed halves; the
+// premix is taken in units of the largest of the three site scales involved
+// (own, s-1, s+1), so every factor is at most 1 and no half overflows. The
+// unit multiplies the FP32 products as they are accumulated.
+template <bool DAG, bool PRE>
+__device__ __forceinline__ void hop_site_h(const HopArgs& a, const FD& fin, int r, int s, int g, int ls,
+                                           const cx<float>* s_link, const int* s_nbr, cx<float>* acc) {
+  const int Ls = a.Ls;
+  float aup = 0.f, alo = 0.f, post = -0.5f;
+  int src_up = 0, src_lo = 0;
+  if constexpr (PRE) {
+    const float q = (float)(a.cmd / a.cpd);
+    const float m = (float)a.mop[r];
+    post = (float)(-0.5 * a.cpd);
+    aup = s > 0 ? q : -m * q;
+    alo = s < Ls - 1 ? q : -m * q;
+    src_up = g * Ls + (s > 0 ? s - 1 : Ls - 1);
+    src_lo = g * Ls + (s < Ls - 1 ? s + 1 : 0);
+  }
+#pragma unroll
+  for (int c = 0; c < 12; ++c) acc[c] = {0.f, 0.f};
+  DirIn<P16> b0, b1;
+  load_dir<P16>(a.in, fin, r, s, s_nbr[ls * NSTR], b0);
+#pragma unroll
+  for (int dir = 0; dir < 8; ++dir) {
+    __builtin_amdgcn_sched_barrier(0);
+    if (dir < 7) load_dir<P16>(a.in, fin, r, s, s_nbr[ls * NSTR + dir + 1], (dir & 1) ? b0 : b1);
+    // the next direction's loads leave before this direction's data is
+    // touched: without this fence the scheduler hoists the lane exchanges of
+    // this direction (which wait for its loads) above them, and nothing overlaps
+    __builtin_amdgcn_sched_barrier(0);
+    const DirIn<P16>& b = (dir & 1) ? b1 : b0;
+    const int mu = dir & 3;
+    const bool fwd = dir < 4;
+    const float sc = b.sc;
+    h2_t x[12];
+    float unit;
+    if constexpr (PRE) {
+      // (D~ psi)_s / (c+d) = sc h_s + aup su h_{s-1} (upper) / + alo sl h_{s+1} (lower)
+      const float su = __shfl(sc, src_up, 64) * aup, sl = __shfl(sc, src_lo, 64) * alo;
+      unit = fmaxf(sc, fmaxf(fabsf(su), fabsf(sl)));
+      unit = unit > 0.f ? unit : 1.f;
+      const float inv = __builtin_amdgcn_rcpf(unit);
+      const _Float16 f0 = (_Float16)(sc * inv), fu = (_Float16)(su * inv), fl = (_Float16)(sl * inv);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        const unsigned t = __shfl((int)b.w[c], c < 6 ? src_up : src_lo, 64);
+        const h2_t hs = __builtin_bit_cast(h2_t, b.w[c]), ht = __builtin_bit_cast(h2_t, t);
+        x[c] = (c < 6 ? fu : fl) * ht + f0 * hs;
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) x[c] = __builtin_bit_cast(h2_t, b.w[c]);
+      unit = sc != 0.f ? sc : 1.f;  // sc = 0: the halves are all zero
+    }
+    // (1 + sg g_mu) projection on packed halves (sg = -1 for (1 - g_mu));
+    // i v = (-Im v, Re v)
+    const bool neg = fwd != DAG;
+    h2_t h[6];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const h2_t u0 = x[c], u1 = x[3 + c], l0 = x[6 + c], l1 = x[9 + c];
+      const h2_t il0 = {-l0.y, l0.x}, il1 = {-l1.y, l1.x};
+      if (mu == 0) {  // u0 - sg i l1, u1 - sg i l0
+        h[c] = neg ? u0 + il1 : u0 - il1;
+        h[3 + c] = neg ? u1 + il0 : u1 - il0;
+      } else if (mu == 1) {  // u0 - sg l1, u1 + sg l0
+        h[c] = neg ? u0 + l1 : u0 - l1;
+        h[3 + c] = neg ? u1 - l0 : u1 + l0;
+      } else if (mu == 2) {  // u0 - sg i l0, u1 + sg i l1
+        h[c] = neg ? u0 + il0 : u0 - il0;
+        h[3 + c] = neg ? u1 - il1 : u1 + il1;
+      } else {  // u0 + sg l0, u1 + sg l1
+        h[c] = neg ? u0 - l0 : u0 + l0;
+        h[3 + c] = neg ? u1 - l1 : u1 + l1;
+      }
+    }
+    const uint2* U = (const uint2*)(s_link + ls * LSTR + dir * 9);
+    cx<float> gv[6];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int a3 = 0; a3 < 3; ++a3) {
+        // first product in the three-operand form with an inline zero
+        // accumulator (the two-operand form would need a register cleared first)
+        const uint2 u0 = U[a3 * 3];
+        const unsigned h0 = __builtin_bit_cast(unsigned, h[k * 3]);
+        float re, im;
+        asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(re) : "v"(u0.x), "v"(h0));
+        asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(im) : "v"(u0.y), "v"(h0));
+#pragma unroll
+        for (int b3 = 1; b3 < 3; ++b3) {
+          const uint2 u = U[a3 * 3 + b3];
+          re = __builtin_amdgcn_fdot2(__builtin_bit_cast(h2_t, u.x), h[k * 3 + b3], re, false);
+          im = __builtin_amdgcn_fdot2(__builtin_bit_cast(h2_t, u.y), h[k * 3 + b3], im, false);
+        }
+        gv[k * 3 + a3] = {re, im};
+      }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) asm volatile("" : "+v"(gv[c].r), "+v"(gv[c].i));
+    // acc += unit * [g ; sg A^dag g]
+    const float ps = unit, ms = neg ? -unit : unit;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const cx<float> g0 = gv[c], g1 = gv[3 + c];
+      acc[c] = cfma_r(ps, g0, acc[c]);
+      acc[3 + c] = cfma_r(ps, g1, acc[3 + c]);
+      if (mu == 0) {  // A^dag g = (i g1, i g0)
+        acc[6 + c] = cfma_r(ms, mul_i(g1), acc[6 + c]);
+        acc[9 + c] = cfma_r(ms, mul_i(g0), acc[9 + c]);
+      } else if (mu == 1) {  // A^dag g = (g1, -g0)
+        acc[6 + c] = cfma_r(ms, g1, acc[6 + c]);
+        acc[9 + c] = cfma_r(-ms, g0, acc[9 + c]);
+      } else if (mu == 2) {  // A^dag g = (i g0, -i g1)
+        acc[6 + c] = cfma_r(ms, mul_i(g0), acc[6 + c]);
+        acc[9 + c] = cfma_r(-ms, mul_i(g1), acc[9 + c]);
+      } else {
+        acc[6 + c] = cfma_r(ms, g0, acc[6 + c]);
+        acc[9 + c] = cfma_r(ms, g1, acc[9 + c]);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 12; ++c) acc[c] = post * acc[c];
 }
 
 template <int P, bool DAG, bool PRE>
 __device__ __forceinline__ void hop_site(const HopArgs& a, const FD& fin, int r, int s, int g, int ls,
                                          const cx<typename ST<P>::R>* s_link, const int* s_nbr,
                                          cx<typename ST<P>::R>* acc) {
+  if constexpr (P == P16) {
+    hop_site_h<DAG, PRE>(a, fin, r, s, g, ls, s_link, s_nbr, acc);
+    return;
+  } else {
   using R = typename ST<P>::R;
   const int Ls = a.Ls;
   // D~ psi = (c+d) [psi_s + (c-d)/(c+d) (P_+ (L_+ psi)_s + P_- (L_- psi)_s)]: the
@@ -161,84 +291,30 @@ __device__ __forceinline__ void hop_site(const HopArgs& a, const FD& fin, int r,
     __builtin_amdgcn_sched_barrier(0);
     if constexpr (PF) {
       if (dir < 7) load_dir<P>(a.in, fin, r, s, s_nbr[ls * NSTR + dir + 1], (dir & 1) ? b0 : b1);
+      __builtin_amdgcn_sched_barrier(0);  // the loads leave first (as in the FP16S path)
     }
     const DirIn<P>& b = (PF && (dir & 1)) ? b1 : b0;
     const int mu = dir & 3;
     const bool fwd = dir < 4;
     cx<R> sp[12];
-    unsigned raw[12];  // FP16S without premix: the raw half2 words, projected directly
-    (void)raw;
-    // the spinor of this direction is scl * sp (scl = 1 unless FP16S); scl
-    // is applied in the accumulation below, as FMAs
-    R scl = R(1);
-    if constexpr (P == P16) {
-      // raw half2 words; the neighbours' halves travel as raw words too and
-      // every conversion is folded into a mixed-precision FMA:
-      //   (D~ psi)_s = sc h_s + f_up su h_{s-1} (+ f_lo sl h_{s+1})
-      //              = scl (h_s + (f su / scl) h_{s-1}),  scl = sc (1 if sc = 0, where h_s = 0)
-      const float sc = b.sc;
-      const unsigned* w = b.w;
-      scl = sc != 0.f ? sc : 1.f;
-      if constexpr (PRE) {
-        const float inv = __builtin_amdgcn_rcpf(scl);
-        const float su = __shfl(sc, src_up, 64) * aup * inv, sl = __shfl(sc, src_lo, 64) * alo * inv;
+    if constexpr (PF) {
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-          const unsigned t = __shfl((int)w[c], c < 6 ? src_up : src_lo, 64);
-          const h2_t hs = __builtin_bit_cast(h2_t, w[c]), ht = __builtin_bit_cast(h2_t, t);
-          const float f = c < 6 ? su : sl;
-          sp[c] = {fmaf(f, (float)ht.x, (float)hs.x), fmaf(f, (float)ht.y, (float)hs.y)};
-        }
-      } else {
-#pragma unroll
-        for (int c = 0; c < 12; ++c) raw[c] = w[c];
-      }
+      for (int c = 0; c < 12; ++c) sp[c] = b.v[c];
     } else {
-      if constexpr (PF) {
+      ld_spinor<P>(a.in, fin, r, s, s_nbr[ls * NSTR + dir], sp);
+    }
+    if constexpr (PRE) {
 #pragma unroll
-        for (int c = 0; c < 12; ++c) sp[c] = b.v[c];
-      } else {
-        ld_spinor<P>(a.in, fin, r, s, s_nbr[ls * NSTR + dir], sp);
-      }
-      if constexpr (PRE) {
-#pragma unroll
-        for (int c = 0; c < 12; ++c) {
-          const int src = c < 6 ? src_up : src_lo;
-          const R f = c < 6 ? aup : alo;
-          const cx<R> t = {__shfl(sp[c].r, src, 64), __shfl(sp[c].i, src, 64)};
-          sp[c] = {fma(f, t.r, sp[c].r), fma(f, t.i, sp[c].i)};
-        }
+      for (int c = 0; c < 12; ++c) {
+        const int src = c < 6 ? src_up : src_lo;
+        const R f = c < 6 ? aup : alo;
+        const cx<R> t = {__shfl(sp[c].r, src, 64), __shfl(sp[c].i, src, 64)};
+        sp[c] = {fma(f, t.r, sp[c].r), fma(f, t.i, sp[c].i)};
       }
     }
     // sg = -1 for (1 - g_mu), +1 for (1 + g_mu)
     const R sg = (fwd != DAG) ? R(-1) : R(1);
     cx<R> h[6];
-    if constexpr (P == P16 && !PRE) {
-      // (1 + sg g_mu) projection straight from the halves: each component is
-      // one mixed-precision FMA with both conversions folded in
-      // +-1 kept opaque so that the conversions fold into v_fma_mix instead
-      // of becoming separate conversions and adds
-      float k = sg;
-      asm volatile("" : "+s"(k));
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const h2_t u0 = __builtin_bit_cast(h2_t, raw[c]), u1 = __builtin_bit_cast(h2_t, raw[3 + c]);
-        const h2_t l0 = __builtin_bit_cast(h2_t, raw[6 + c]), l1 = __builtin_bit_cast(h2_t, raw[9 + c]);
-        if (mu == 0) {  // u0 - sg i l1, u1 - sg i l0
-          h[c] = {fmaf(k, (float)l1.y, (float)u0.x), fmaf(-k, (float)l1.x, (float)u0.y)};
-          h[3 + c] = {fmaf(k, (float)l0.y, (float)u1.x), fmaf(-k, (float)l0.x, (float)u1.y)};
-        } else if (mu == 1) {  // u0 - sg l1, u1 + sg l0
-          h[c] = {fmaf(-k, (float)l1.x, (float)u0.x), fmaf(-k, (float)l1.y, (float)u0.y)};
-          h[3 + c] = {fmaf(k, (float)l0.x, (float)u1.x), fmaf(k, (float)l0.y, (float)u1.y)};
-        } else if (mu == 2) {  // u0 - sg i l0, u1 + sg i l1
-          h[c] = {fmaf(k, (float)l0.y, (float)u0.x), fmaf(-k, (float)l0.x, (float)u0.y)};
-          h[3 + c] = {fmaf(-k, (float)l1.y, (float)u1.x), fmaf(k, (float)l1.x, (float)u1.y)};
-        } else {  // u0 + sg l0, u1 + sg l1
-          h[c] = {fmaf(k, (float)l0.x, (float)u0.x), fmaf(k, (float)l0.y, (float)u0.y)};
-          h[3 + c] = {fmaf(k, (float)l1.x, (float)u1.x), fmaf(k, (float)l1.y, (float)u1.y)};
-        }
-      }
-    } else
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const cx<R> u0 = sp[c], u1 = sp[3 + c], l0 = sp[6 + c], l1 = sp[9 + c];
@@ -269,30 +345,30 @@ __device__ __forceinline__ void hop_site(const HopArgs& a, const FD& fin, int r,
       }
 #pragma unroll
     for (int c = 0; c < 6; ++c) asm volatile("" : "+v"(gv[c].r), "+v"(gv[c].i));
-    // acc += scl * [g ; sg A^dag g]
-    const R ps = scl, ms = sg * scl;
+    // acc += [g ; sg A^dag g]
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const cx<R> g0 = gv[c], g1 = gv[3 + c];
-      acc[c] = cfma_r(ps, g0, acc[c]);
-      acc[3 + c] = cfma_r(ps, g1, acc[3 + c]);
+      acc[c] = acc[c] + g0;
+      acc[3 + c] = acc[3 + c] + g1;
       if (mu == 0) {  // A^dag g = (i g1, i g0)
-        acc[6 + c] = cfma_r(ms, mul_i(g1), acc[6 + c]);
-        acc[9 + c] = cfma_r(ms, mul_i(g0), acc[9 + c]);
+        acc[6 + c] = acc[6 + c] + sg * mul_i(g1);
+        acc[9 + c] = acc[9 + c] + sg * mul_i(g0);
       } else if (mu == 1) {  // A^dag g = (g1, -g0)
-        acc[6 + c] = cfma_r(ms, g1, acc[6 + c]);
-        acc[9 + c] = cfma_r(-ms, g0, acc[9 + c]);
+        acc[6 + c] = acc[6 + c] + sg * g1;
+        acc[9 + c] = acc[9 + c] - sg * g0;
       } else if (mu == 2) {  // A^dag g = (i g0, -i g1)
-        acc[6 + c] = cfma_r(ms, mul_i(g0), acc[6 + c]);
-        acc[9 + c] = cfma_r(-ms, mul_i(g1), acc[9 + c]);
+        acc[6 + c] = acc[6 + c] + sg * mul_i(g0);
+        acc[9 + c] = acc[9 + c] - sg * mul_i(g1);
       } else {
-        acc[6 + c] = cfma_r(ms, g0, acc[6 + c]);
-        acc[9 + c] = cfma_r(ms, g1, acc[9 + c]);
+        acc[6 + c] = acc[6 + c] + sg * g0;
+        acc[9 + c] = acc[9 + c] + sg * g1;
       }
     }
   }
 #pragma unroll
   for (int c = 0; c < 12; ++c) acc[c] = post * acc[c];
+  }
 }
 
 template <class R>
@@ -440,9 +516,15 @@ hop_kernel(HopArgs a) {
   // stage the links and neighbour indices of this block's sites
   for (int j = tid; j < SBk * 72; j += nthr) {
     const int site = j / 72, k = j - site * 72;
-    cx<R> v = {R(0), R(0)};
-    if (k0 + site < Vh) v = ld_link<P>(a.links, (size_t)a.order[k0 + site] * 72 + k);
-    s_link[site * LSTR + k] = v;
+    if constexpr (P == P16) {  // (Re u, -Im u) and (Im u, Re u) as half2 words
+      unsigned w = 0u;
+      if (k0 + site < Vh) w = ((const unsigned*)a.links)[(size_t)a.order[k0 + site] * 72 + k];
+      s_link[site * LSTR + k] = {__uint_as_float(w ^ 0x80000000u), __uint_as_float((w >> 16) | (w << 16))};
+    } else {
+      cx<R> v = {R(0), R(0)};
+      if (k0 + site < Vh) v = ld_link<P>(a.links, (size_t)a.order[k0 + site] * 72 + k);
+      s_link[site * LSTR + k] = v;
+    }
   }
   for (int j = tid; j < SBk * 8; j += nthr) {
     const int site = j / 8, k = j - site * 8;
