@@ -457,11 +457,12 @@ __device__ __forceinline__ void rank_one(const cx<R>* y, cx<R>* v, R sk, R us, i
   }
 }
 
-// Occupancy target: 4 waves per SIMD for FP32 arithmetic (128 VGPRs),
-// 3 for FP64 (about 168 VGPRs); the stencil hides latency by occupancy.
+// Occupancy target (waves per SIMD the register allocation must allow): 5
+// for FP16S (96 VGPRs, no spills), 4 for FP32 (128; it would spill at 5), 3
+// for FP64 (about 168); the stencil hides latency by occupancy.
 template <int P>
 struct HopOcc {
-  static constexpr int waves = P == P64 ? 3 : 4;
+  static constexpr int waves = P == P64 ? 3 : (P == P16 ? 5 : 4);
 };
 
 template <int P, int PR, int ROLE>
