@@ -111,6 +111,41 @@ struct DirIn<P16> {
   float sc;
 };
 
+// Rotation across the 16 lanes of a DPP row: lane l of each row receives the
+// value of lane (l - K) mod 16 of the same row. With Ls = 16 a row is exactly
+// one site's s-column (lane = g * 16 + s), so the fifth-dimension neighbour
+// s - K (cyclic) costs one VALU move instead of an LDS permute.
+template <int K>
+__device__ __forceinline__ int row_ror(int v) {
+  if constexpr ((K & 15) == 0) {
+    return v;
+  } else {
+    return __builtin_amdgcn_mov_dpp(v, 0x120 + (K & 15), 0xF, 0xF, false);
+  }
+}
+template <int K>
+__device__ __forceinline__ unsigned row_ror(unsigned v) { return (unsigned)row_ror<K>((int)v); }
+template <int K>
+__device__ __forceinline__ float row_ror(float v) { return __int_as_float(row_ror<K>(__float_as_int(v))); }
+template <int K>
+__device__ __forceinline__ double row_ror(double v) {
+  const int2 w = __builtin_bit_cast(int2, v);
+  return __builtin_bit_cast(double, make_int2(row_ror<K>(w.x), row_ror<K>(w.y)));
+}
+template <int K, class R>
+__device__ __forceinline__ cx<R> row_ror(cx<R> v) { return {row_ror<K>(v.r), row_ror<K>(v.i)}; }
+
+// value of lane s - 1 (UP) or s + 1 (!UP) of this site's column: a DPP
+// rotation when the column is a 16-lane row (RL = 16), else a lane permute
+template <int RL, bool UP, class T>
+__device__ __forceinline__ T col_nbr(T v, int src) {
+  if constexpr (RL == 16) {
+    return row_ror<UP ? 1 : 15>(v);
+  } else {
+    return __shfl(v, src, 64);
+  }
+}
+
 template <int P>
 __device__ __forceinline__ void load_dir(const void* in, const FD& fin, int r, int s, int n, DirIn<P>& b) {
   if constexpr (P == P16) {
@@ -131,7 +166,7 @@ __device__ __forceinline__ void load_dir(const void* in, const FD& fin, int r, i
 // premix is taken in units of the largest of the three site scales involved
 // (own, s-1, s+1), so every factor is at most 1 and no half overflows. The
 // unit multiplies the FP32 products as they are accumulated.
-template <bool DAG, bool PRE>
+template <bool DAG, bool PRE, int RL>
 __device__ __forceinline__ void hop_site_h(const HopArgs& a, const FD& fin, int r, int s, int g, int ls,
                                            const cx<float>* s_link, const int* s_nbr, cx<float>* acc) {
   const int Ls = a.Ls;
@@ -166,14 +201,14 @@ __device__ __forceinline__ void hop_site_h(const HopArgs& a, const FD& fin, int 
     float unit;
     if constexpr (PRE) {
       // (D~ psi)_s / (c+d) = sc h_s + aup su h_{s-1} (upper) / + alo sl h_{s+1} (lower)
-      const float su = __shfl(sc, src_up, 64) * aup, sl = __shfl(sc, src_lo, 64) * alo;
+      const float su = col_nbr<RL, true>(sc, src_up) * aup, sl = col_nbr<RL, false>(sc, src_lo) * alo;
       unit = fmaxf(sc, fmaxf(fabsf(su), fabsf(sl)));
       unit = unit > 0.f ? unit : 1.f;
       const float inv = __builtin_amdgcn_rcpf(unit);
       const _Float16 f0 = (_Float16)(sc * inv), fu = (_Float16)(su * inv), fl = (_Float16)(sl * inv);
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
-        const unsigned t = __shfl((int)b.w[c], c < 6 ? src_up : src_lo, 64);
+        const unsigned t = c < 6 ? col_nbr<RL, true>(b.w[c], src_up) : col_nbr<RL, false>(b.w[c], src_lo);
         const h2_t hs = __builtin_bit_cast(h2_t, b.w[c]), ht = __builtin_bit_cast(h2_t, t);
         x[c] = (c < 6 ? fu : fl) * ht + f0 * hs;
       }
@@ -253,12 +288,12 @@ __device__ __forceinline__ void hop_site_h(const HopArgs& a, const FD& fin, int 
   for (int c = 0; c < 12; ++c) acc[c] = post * acc[c];
 }
 
-template <int P, bool DAG, bool PRE>
+template <int P, bool DAG, bool PRE, int RL>
 __device__ __forceinline__ void hop_site(const HopArgs& a, const FD& fin, int r, int s, int g, int ls,
                                          const cx<typename ST<P>::R>* s_link, const int* s_nbr,
                                          cx<typename ST<P>::R>* acc) {
   if constexpr (P == P16) {
-    hop_site_h<DAG, PRE>(a, fin, r, s, g, ls, s_link, s_nbr, acc);
+    hop_site_h<DAG, PRE, RL>(a, fin, r, s, g, ls, s_link, s_nbr, acc);
     return;
   } else {
   using R = typename ST<P>::R;
@@ -306,9 +341,9 @@ __device__ __forceinline__ void hop_site(const HopArgs& a, const FD& fin, int r,
     if constexpr (PRE) {
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
-        const int src = c < 6 ? src_up : src_lo;
         const R f = c < 6 ? aup : alo;
-        const cx<R> t = {__shfl(sp[c].r, src, 64), __shfl(sp[c].i, src, 64)};
+        const cx<R> t = c < 6 ? cx<R>{col_nbr<RL, true>(sp[c].r, src_up), col_nbr<RL, true>(sp[c].i, src_up)}
+                              : cx<R>{col_nbr<RL, false>(sp[c].r, src_lo), col_nbr<RL, false>(sp[c].i, src_lo)};
         sp[c] = {fma(f, t.r, sp[c].r), fma(f, t.i, sp[c].i)};
       }
     }
@@ -416,22 +451,90 @@ struct SNbr {
   R fp, fn;    // 1, or -m across the wrap
 };
 
-template <class R, bool TRANS>
+template <class R, bool TRANS, int RL>
 __device__ __forceinline__ void lmul(const cx<R>* v, cx<R>* out, const SNbr<R>& nb) {
 #pragma unroll
-  for (int c = 0; c < 6; ++c) out[c] = (TRANS ? nb.fn : nb.fp) * shfl_cx(v[c], TRANS ? nb.sn : nb.sp);
+  for (int c = 0; c < 6; ++c) {
+    const cx<R> t = TRANS ? cx<R>{col_nbr<RL, false>(v[c].r, nb.sn), col_nbr<RL, false>(v[c].i, nb.sn)}
+                          : cx<R>{col_nbr<RL, true>(v[c].r, nb.sp), col_nbr<RL, true>(v[c].i, nb.sp)};
+    out[c] = (TRANS ? nb.fn : nb.fp) * t;
+  }
 #pragma unroll
-  for (int c = 6; c < 12; ++c) out[c] = (TRANS ? nb.fp : nb.fn) * shfl_cx(v[c], TRANS ? nb.sp : nb.sn);
+  for (int c = 6; c < 12; ++c) {
+    const cx<R> t = TRANS ? cx<R>{col_nbr<RL, true>(v[c].r, nb.sp), col_nbr<RL, true>(v[c].i, nb.sp)}
+                          : cx<R>{col_nbr<RL, false>(v[c].r, nb.sn), col_nbr<RL, false>(v[c].i, nb.sn)};
+    out[c] = (TRANS ? nb.fp : nb.fn) * t;
+  }
+}
+
+// v[half] (+)= M v'[half] for the Ls x Ls matrix of chirality `half` (rows
+// padded to Ls + 1 in LDS), Ls = 16: the sum over s' runs along the cyclic
+// diagonals, M[s][s-k] times the value of lane s-k brought by a row rotation,
+// so the column never goes through LDS
+template <class R, int K>
+__device__ __forceinline__ void diag_step(const R* M, const cx<R>* src, int s, int half, cx<R>* t) {
+  // one diagonal at a time: unfenced, the scheduler hoists all 16 rotations
+  // and their LDS reads together and the live values spill
+  __builtin_amdgcn_sched_barrier(0);
+  const R d = M[(half * 16 + s) * 17 + ((s - K) & 15)];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const cx<R> v = row_ror<K>(src[half * 6 + c]);
+    t[c].r = fma(d, v.r, t[c].r);
+    t[c].i = fma(d, v.i, t[c].i);
+  }
+}
+template <class R, int K = 0>
+__device__ __forceinline__ void diag_steps(const R* M, const cx<R>* src, int s, int half, cx<R>* t) {
+  if constexpr (K < 16) {
+    diag_step<R, K>(M, src, s, half, t);
+    diag_steps<R, K + 1>(M, src, s, half, t);
+  }
+}
+template <class R>
+__device__ __forceinline__ void row_matvec(const R* M, const cx<R>* src, int s, cx<R>* v, bool accumulate) {
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    cx<R> t[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) t[c] = accumulate ? v[half * 6 + c] : cx<R>{R(0), R(0)};
+    diag_steps<R>(M, src, s, half, t);
+    // the sums are complete here: the rotations are convergent and cannot
+    // follow the arithmetic into the (live-lane) store branch, so without
+    // this fence every rotated value stays live across it and spills
+#pragma unroll
+    for (int c = 0; c < 6; ++c) asm volatile("" : "+v"(t[c].r), "+v"(t[c].i));
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[half * 6 + c] = t[c];
+  }
+}
+
+// sum over the 16 lanes of each row, left in every lane
+template <class R>
+__device__ __forceinline__ cx<R> row_sum(cx<R> v) {
+  v = v + row_ror<8>(v);
+  v = v + row_ror<4>(v);
+  v = v + row_ror<2>(v);
+  return v + row_ror<1>(v);
 }
 
 // Rank-one part of the shifted same-parity block on the chirality half H0
 // (0: P_+, 6: P_-), with s* the special fifth-dimension index:
 //   TRANS = false:  v_s += sk u_s y_{s*}              (sk u e_{s*}^T y)
 //   TRANS = true :  v_s += delta_{s,s*} sk sum_s' u_s' y_s'   (sk e_{s*} u^T y)
-template <class R, bool TRANS, int H0>
+template <class R, bool TRANS, int H0, int RL>
 __device__ __forceinline__ void rank_one(const cx<R>* y, cx<R>* v, R sk, R us, int star_lane, bool is_star,
                                          cx<R>* mycol, int s, int Ls, bool in_col) {
-  if constexpr (!TRANS) {
+  if constexpr (TRANS && RL == 16) {  // the sum over s' along the row, no LDS
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const cx<R> sum = row_sum(us * y[H0 + c]);
+      if (is_star) {
+        v[H0 + c].r = fma(sk, sum.r, v[H0 + c].r);
+        v[H0 + c].i = fma(sk, sum.i, v[H0 + c].i);
+      }
+    }
+  } else if constexpr (!TRANS) {
     const R f = sk * us;
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
@@ -465,7 +568,10 @@ struct HopOcc {
   static constexpr int waves = P == P64 ? 3 : (P == P16 ? 5 : 4);
 };
 
-template <int P, int PR, int ROLE>
+// RL = 16: Ls = 16, each site's s-column is one DPP row and every exchange
+// along s (D~ premix, L, the dense Ls x Ls epilogues, the rank-one sums) is
+// a row rotation; RL = 0: any Ls, exchanges through lane permutes and LDS.
+template <int P, int PR, int ROLE, int RL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HopOcc<P>::waves, 8)))
 hop_kernel(HopArgs a) {
   using RT = RoleT<ROLE>;
@@ -547,7 +653,7 @@ hop_kernel(HopArgs a) {
     __syncthreads();
 
     cx<R> acc[12];
-    hop_site<P, RT::DAG, RT::PRE>(a, fd, r, s, g, ls, s_link, s_nbr, acc);
+    hop_site<P, RT::DAG, RT::PRE, RL>(a, fd, r, s, g, ls, s_link, s_nbr, acc);
     // an unconditional use: stops the hop arithmetic from being sunk into the
     // (live-only) store block, away from the per-direction loads and shuffles
 #pragma unroll
@@ -573,7 +679,7 @@ hop_kernel(HopArgs a) {
       for (int c = 0; c < 12; ++c) v[c] = R(-1) * acc[c];
     } else {  // D~^T h = (c+d) h + (c-d) L^T h
       cx<R> t[12];
-      lmul<R, true>(acc, t, nb);
+      lmul<R, true, RL>(acc, t, nb);
       const R sgn = RT::AM == A_NDTT ? R(-1) : R(1);
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
@@ -581,7 +687,12 @@ hop_kernel(HopArgs a) {
         v[c] = sgn * d;
       }
     }
-    if constexpr (DENSE) {  // v <- M v through the column in LDS
+    if constexpr (DENSE && RL == 16) {  // v <- M v along the row's diagonals
+      cx<R> src[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) src[c] = v[c];
+      row_matvec<R>(s_mA, src, s, v, false);
+    } else if constexpr (DENSE) {  // v <- M v through the column in LDS
       cx<R>* mycol = s_col + ls * cstr;
       cx<R> src[12];
 #pragma unroll
@@ -595,7 +706,11 @@ hop_kernel(HopArgs a) {
         col_matvec<R>(s_mA, mycol, Ls, s, half, v, false);
       }
     }
-    if constexpr (BDENSE) {  // v += M y, M dense per chirality, through the column in LDS
+    if constexpr (BDENSE && RL == 16) {  // v += M y along the row's diagonals
+      cx<R> y[12];
+      ld_spinor<P>(a.y, fd, r, s, EOFA_SITE, y);
+      row_matvec<R>(s_mA, y, s, v, true);
+    } else if constexpr (BDENSE) {  // v += M y, M dense per chirality, through the column in LDS
       cx<R> y[12];
       ld_spinor<P>(a.y, fd, r, s, EOFA_SITE, y);
       cx<R>* mycol = s_col + ls * cstr;
@@ -612,7 +727,7 @@ hop_kernel(HopArgs a) {
       //   bee y - cee L y (L^T y) + sk u e_{s*}^T y (sk e_{s*} u^T y) on chirality chi
       cx<R> y[12], t[12];
       ld_spinor<P>(a.y, fd, r, s, EOFA_SITE, y);
-      lmul<R, RT::BM == B_MEET>(y, t, nb);
+      lmul<R, RT::BM == B_MEET, RL>(y, t, nb);
       const R bee = (R)a.bee, cee = (R)a.cee;
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
@@ -625,10 +740,10 @@ hop_kernel(HopArgs a) {
         const int chi = (int)sc[2];
         const R us = (R)sc[SCOEF_HEAD + s];
         if (chi > 0)
-          rank_one<R, RT::BM == B_MEET, 0>(y, v, sk, us, g * Ls + Ls - 1, s == Ls - 1, s_col + ls * cstr, s,
+          rank_one<R, RT::BM == B_MEET, 0, RL>(y, v, sk, us, g * Ls + Ls - 1, s == Ls - 1, s_col + ls * cstr, s,
                                            Ls, in_col);
         else
-          rank_one<R, RT::BM == B_MEET, 6>(y, v, sk, us, g * Ls, s == 0, s_col + ls * cstr, s, Ls, in_col);
+          rank_one<R, RT::BM == B_MEET, 6, RL>(y, v, sk, us, g * Ls, s == 0, s_col + ls * cstr, s, Ls, in_col);
       }
     }
 
@@ -693,6 +808,10 @@ int hop_blocks(int prec, int Vh, int Ls, int W) {
   return (Vh + SBk - 1) / SBk;
 }
 
+// the row form (RL = 16) serves Ls = 16 below FP64
+template <int P>
+bool use_rows(int Ls) { return P != P64 && Ls == 16; }
+
 template <int P, int ROLE>
 size_t hop_lds_t(int Ls, int W) {
   using R = typename ST<P>::R;
@@ -702,7 +821,7 @@ size_t hop_lds_t(int Ls, int W) {
   constexpr bool DENSE = RT::AM == A_MAT || RT::AM == A_MATDT || RT::BM == B_DENSE;
   size_t lds = L::links(SBk) + L::nbr(SBk);
   if (DENSE) lds += L::mat(Ls);
-  if (DENSE || RT::BM == B_MEET) lds += L::col(SBk, Ls);
+  if ((DENSE || RT::BM == B_MEET) && !use_rows<P>(Ls)) lds += L::col(SBk, Ls);
   return lds;
 }
 
@@ -732,7 +851,8 @@ size_t hop_lds_p(int role, int Ls, int W) {
 }
 
 size_t hop_lds_bytes(int prec, int role, int Ls, int W) {
-  return prec == P64 ? hop_lds_p<P64>(role, Ls, W) : hop_lds_p<P32>(role, Ls, W);
+  return prec == P64 ? hop_lds_p<P64>(role, Ls, W) : prec == P32 ? hop_lds_p<P32>(role, Ls, W)
+                                                                  : hop_lds_p<P16>(role, Ls, W);
 }
 
 template <int P, int ROLE>
@@ -746,7 +866,10 @@ int launch_hop_t(const HopArgs& a, hipStream_t st, int* nblk_out) {
   HopArgs b = a;
   b.rhs_block = rb;
   b.W = W;
-  auto fn = hop_kernel<P, acc_prec<P>(), ROLE>;
+  void (*fn)(HopArgs) = hop_kernel<P, acc_prec<P>(), ROLE, 0>;
+  if constexpr (P != P64) {
+    if (use_rows<P>(Ls)) fn = hop_kernel<P, acc_prec<P>(), ROLE, 16>;
+  }
   if (lds > 65536) {
     if (hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
         hipSuccess)
