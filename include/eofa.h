@@ -142,6 +142,12 @@ typedef struct {
                           itself, off-parity blocks Dhop and same-parity blocks the dense
                           Ls x Ls D_ee = M_ee D~^-1 per chirality (eofa_cg_solve with
                           precond = 0 only; heatbath and force reject it)                     */
+  int32_t keep_direction; /* CGNR below FP64: 1 = each outer pass after the first keeps the
+                          inner search direction and only replaces the residual by the FP64
+                          one (a reliable update; passes then end at a residual reduction
+                          of at most 0.1 for FP16S, 0.01 for FP32); 0 = each pass restarts
+                          the inner CG from p = r (plain defect correction)                   */
+  int32_t pad2;
 } eofa_solver_params;
 
 typedef struct {

@@ -612,6 +612,13 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
   // factor on the FP64 target), floored at the inner precision's reach.
   double inner_floor = prm->inner_tol;
   if (!(inner_floor > 0.0)) inner_floor = S == P64 ? 0.0 : 1e-4;
+  // A kept direction stays conjugate only while the inner recurrence
+  // residual is close to the true one, i.e. when each pass reduces the
+  // residual by a factor well above the inner precision's unit roundoff
+  // (2^-11 FP16S, 2^-24 FP32): replace the residual every 10x (FP16S) or
+  // 100x (FP32) of reduction.
+  const bool keep = prm->keep_direction && S != P64 && !fixed;
+  if (keep) inner_floor = std::max(inner_floor, S == P16 ? 0.1 : 0.01);
 
   CHK(upload_systems(C, sys, nrhs, st));
   CHK(stage(C, 64 * (size_t)std::max(nrhs, 16)));
@@ -790,7 +797,10 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
       CHK(hop(C, S, F.k4s, a4, st, &nb));
       launch_finalize(FIN_INIT, partial, nb, nrhs, Sst, nullptr, st);
     }
-    launch_convert(PR, S, g, rin, pS, nrhs, st);
+    // p = r starts the inner CG afresh; a reliable update (keep_direction,
+    // after the first pass) keeps the previous pass's direction p, which
+    // stays conjugate to within the inner precision, and replaces only r
+    if (!(keep && outer > 0)) launch_convert(PR, S, g, rin, pS, nrhs, st);
     launch_zero(PR, g, xin, nrhs, st);
 
     if (prm->rhs_block > 0 || prm->waves > 0) {

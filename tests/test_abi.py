@@ -46,7 +46,7 @@ int main(void) {
   printf("%zu %zu %zu %zu\n", sizeof(eofa_action), sizeof(eofa_system), sizeof(eofa_solver_params), sizeof(eofa_solver_stats));
   printf("%zu %zu %zu %zu %zu\n", offsetof(eofa_action, M5), offsetof(eofa_action, bc), offsetof(eofa_solver_params, inner_tol), offsetof(eofa_solver_stats, hop_ms), offsetof(eofa_solver_params, waves));
   printf("%zu %zu %zu\n", offsetof(eofa_solver_params, precond), offsetof(eofa_solver_params, net), offsetof(eofa_solver_stats, fell_back));
-  printf("%zu %zu\n", offsetof(eofa_solver_params, use_guess), offsetof(eofa_solver_params, form));
+  printf("%zu %zu %zu\n", offsetof(eofa_solver_params, use_guess), offsetof(eofa_solver_params, form), offsetof(eofa_solver_params, keep_direction));
   return 0;
 }
 '''
@@ -63,7 +63,8 @@ int main(void) {
                          eofa.SolverParams.inner_tol.offset, eofa.SolverStats.hop_ms.offset,
                          eofa.SolverParams.waves.offset, eofa.SolverParams.precond.offset,
                          eofa.SolverParams.net.offset, eofa.SolverStats.fell_back.offset,
-                         eofa.SolverParams.use_guess.offset, eofa.SolverParams.form.offset]
+                         eofa.SolverParams.use_guess.offset, eofa.SolverParams.form.offset,
+                         eofa.SolverParams.keep_direction.offset]
 
 
 @pytest.mark.parametrize("bad", [
