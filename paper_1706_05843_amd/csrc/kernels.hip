@@ -166,9 +166,12 @@ __device__ __forceinline__ void load_dir(const void* in, const FD& fin, int r, i
 // premix is taken in units of the largest of the three site scales involved
 // (own, s-1, s+1), so every factor is at most 1 and no half overflows. The
 // unit multiplies the FP32 products as they are accumulated.
-template <bool DAG, bool PRE, int RL>
+// YPRE: the last direction has nothing left to prefetch, so its free buffer
+// takes the same-site spinor of a.y that the epilogue needs (yout).
+template <bool DAG, bool PRE, int RL, bool YPRE>
 __device__ __forceinline__ void hop_site_h(const HopArgs& a, const FD& fin, int r, int s, int g, int ls,
-                                           const cx<float>* s_link, const int* s_nbr, cx<float>* acc) {
+                                           const cx<float>* s_link, const int* s_nbr, cx<float>* acc,
+                                           DirIn<P16>& yout) {
   const int Ls = a.Ls;
   float aup = 0.f, alo = 0.f, post = -0.5f;
   int src_up = 0, src_lo = 0;
@@ -189,6 +192,9 @@ __device__ __forceinline__ void hop_site_h(const HopArgs& a, const FD& fin, int 
   for (int dir = 0; dir < 8; ++dir) {
     __builtin_amdgcn_sched_barrier(0);
     if (dir < 7) load_dir<P16>(a.in, fin, r, s, s_nbr[ls * NSTR + dir + 1], (dir & 1) ? b0 : b1);
+    if constexpr (YPRE) {
+      if (dir == 7) load_dir<P16>(a.y, fin, r, s, s_nbr[ls * NSTR + 8], yout);
+    }
     // the next direction's loads leave before this direction's data is
     // touched: without this fence the scheduler hoists the lane exchanges of
     // this direction (which wait for its loads) above them, and nothing overlaps
@@ -288,12 +294,12 @@ __device__ __forceinline__ void hop_site_h(const HopArgs& a, const FD& fin, int 
   for (int c = 0; c < 12; ++c) acc[c] = post * acc[c];
 }
 
-template <int P, bool DAG, bool PRE, int RL>
+template <int P, bool DAG, bool PRE, int RL, bool YPRE>
 __device__ __forceinline__ void hop_site(const HopArgs& a, const FD& fin, int r, int s, int g, int ls,
                                          const cx<typename ST<P>::R>* s_link, const int* s_nbr,
-                                         cx<typename ST<P>::R>* acc) {
+                                         cx<typename ST<P>::R>* acc, DirIn<P16>& yout) {
   if constexpr (P == P16) {
-    hop_site_h<DAG, PRE, RL>(a, fin, r, s, g, ls, s_link, s_nbr, acc);
+    hop_site_h<DAG, PRE, RL, YPRE>(a, fin, r, s, g, ls, s_link, s_nbr, acc, yout);
     return;
   } else {
   using R = typename ST<P>::R;
@@ -568,6 +574,22 @@ struct HopOcc {
   static constexpr int waves = P == P64 ? 3 : (P == P16 ? 5 : 4);
 };
 
+// the same-site spinor of a.y: decoded from the words prefetched with the
+// last hop direction (YPRE), else loaded here
+template <int P, bool YPRE, class R>
+__device__ __forceinline__ void load_y(const void* y, const FD& fd, int r, int s, int site, const DirIn<P16>& pre,
+                                       cx<R>* out) {
+  if constexpr (YPRE) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const h2_t h = __builtin_bit_cast(h2_t, pre.w[c]);
+      out[c] = {pre.sc * (R)(float)h.x, pre.sc * (R)(float)h.y};
+    }
+  } else {
+    ld_spinor<P>(y, fd, r, s, site, out);
+  }
+}
+
 // RL = 16: Ls = 16, each site's s-column is one DPP row and every exchange
 // along s (D~ premix, L, the dense Ls x Ls epilogues, the rank-one sums) is
 // a row rotation; RL = 0: any Ls, exchanges through lane permutes and LDS.
@@ -653,7 +675,11 @@ hop_kernel(HopArgs a) {
     __syncthreads();
 
     cx<R> acc[12];
-    hop_site<P, RT::DAG, RT::PRE, RL>(a, fd, r, s, g, ls, s_link, s_nbr, acc);
+    // FP16S: the same-site y of the B term arrives with the last direction
+    constexpr bool YPRE = P == P16 && RT::BM != B_NONE;
+    DirIn<P16> ypre;
+    hop_site<P, RT::DAG, RT::PRE, RL, YPRE>(a, fd, r, s, g, ls, s_link, s_nbr, acc, ypre);
+    (void)ypre;
     // an unconditional use: stops the hop arithmetic from being sunk into the
     // (live-only) store block, away from the per-direction loads and shuffles
 #pragma unroll
@@ -708,11 +734,11 @@ hop_kernel(HopArgs a) {
     }
     if constexpr (BDENSE && RL == 16) {  // v += M y along the row's diagonals
       cx<R> y[12];
-      ld_spinor<P>(a.y, fd, r, s, EOFA_SITE, y);
+      load_y<P, YPRE>(a.y, fd, r, s, EOFA_SITE, ypre, y);
       row_matvec<R>(s_mA, y, s, v, true);
     } else if constexpr (BDENSE) {  // v += M y, M dense per chirality, through the column in LDS
       cx<R> y[12];
-      ld_spinor<P>(a.y, fd, r, s, EOFA_SITE, y);
+      load_y<P, YPRE>(a.y, fd, r, s, EOFA_SITE, ypre, y);
       cx<R>* mycol = s_col + ls * cstr;
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
@@ -726,7 +752,7 @@ hop_kernel(HopArgs a) {
       // + M_ee y (B_MEE) or + M_ee^T y (B_MEET):
       //   bee y - cee L y (L^T y) + sk u e_{s*}^T y (sk e_{s*} u^T y) on chirality chi
       cx<R> y[12], t[12];
-      ld_spinor<P>(a.y, fd, r, s, EOFA_SITE, y);
+      load_y<P, YPRE>(a.y, fd, r, s, EOFA_SITE, ypre, y);
       lmul<R, RT::BM == B_MEET, RL>(y, t, nb);
       const R bee = (R)a.bee, cee = (R)a.cee;
 #pragma unroll
@@ -1282,19 +1308,8 @@ void launch_cg_update(int ps, int pr, const Geometry& g, void* x, const void* r,
 // ---------------------------------------------------------------------------
 // CG scalar finalisation: one block per right-hand side, fixed summation order
 
-__global__ void finalize_kernel(int mode, const double* __restrict__ partial, int nblk, CgState S, double* out) {
-  const int r = blockIdx.x;
-  __shared__ double red[256];
-  double t = 0.0;
-  for (int j = threadIdx.x; j < nblk; j += blockDim.x) t += partial[(size_t)r * nblk + j];
-  red[threadIdx.x] = t;
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x != 0) return;
-  const double sum = red[0];
+// one CG scalar step for right-hand side r from the reduced sum
+__device__ void finalize_step(int mode, double sum, const CgState& S, int r, double* out) {
   if (mode == FIN_NORM) {
     out[r] = sum;
     return;
@@ -1341,6 +1356,30 @@ __global__ void finalize_kernel(int mode, const double* __restrict__ partial, in
   } else if (rrn <= S.stop[r] || S.iter[r] >= S.max_iter[r]) {
     S.halt[r] = 1;
   }
+}
+
+__global__ void finalize_kernel(int mode, const double* __restrict__ partial, int nblk, CgState S, double* out) {
+  const int r = blockIdx.x;
+  __shared__ double red[256];
+  // eight independent partial sums per thread, so the loads of one thread
+  // are in flight together instead of one memory latency after another
+  const double* pr = partial + (size_t)r * nblk;
+  double t8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int j0 = threadIdx.x; j0 < nblk; j0 += 8 * blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int j = j0 + k * blockDim.x;
+      if (j < nblk) t8[k] += pr[j];
+    }
+  }
+  double t = ((t8[0] + t8[1]) + (t8[2] + t8[3])) + ((t8[4] + t8[5]) + (t8[6] + t8[7]));
+  red[threadIdx.x] = t;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) finalize_step(mode, red[0], S, r, out);
 }
 
 void launch_finalize(int mode, const double* partial, int nblk, int nrhs, CgState s, double* out, hipStream_t st) {
