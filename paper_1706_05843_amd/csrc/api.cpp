@@ -95,7 +95,7 @@ int stage(eofa_ctx* C, size_t bytes) {
 }
 
 size_t mats_per_rhs(const Geometry& g) { return (size_t)NMAT * 2 * g.Ls * g.Ls; }
-size_t scoef_per_rhs(const Geometry& g) { return (size_t)SCOEF_HEAD + g.Ls; }
+size_t scoef_per_rhs(const Geometry& g) { return (size_t)SCOEF_HEAD + 2 * (size_t)g.Ls; }
 
 // Build and upload the fifth-dimension matrices and operator masses of
 // sys[0..nrhs). Cached: a repeat of the same systems uploads nothing.
@@ -118,7 +118,7 @@ int upload_systems(eofa_ctx* C, const eofa_system* sys, int nrhs, hipStream_t st
     const int rc = build_fifth(C->g, C->M5, C->b5, C->c5, sys[r], h.data() + per * r, err);
     if (rc != EOFA_OK) return fail(rc, "right-hand side " + std::to_string(r) + ": " + err);
     h[per * nrhs + r] = sys[r].m_op;
-    build_struct(C->g, C->b5, C->c5, sys[r], h.data() + per * nrhs + nrhs + sper * r);
+    build_struct(C->g, C->M5, C->b5, C->c5, sys[r], h.data() + per * nrhs + nrhs + sper * r);
   }
   if (C->mats_n < n) {
     if (C->mats) HIPCHK(hipFree(C->mats));

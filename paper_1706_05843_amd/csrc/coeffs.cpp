@@ -98,7 +98,7 @@ double sgn(int n) { return (n % 2 != 0) ? -1.0 : 1.0; }
 
 double k_eofa(int Ls, double c, double d, double m_a, double m_b);
 
-void build_struct(const Geometry& g, double b5, double c5, const eofa_system& sys, double* out) {
+void build_struct(const Geometry& g, double M5, double b5, double c5, const eofa_system& sys, double* out) {
   const int n = g.Ls;
   const double c = 0.5 * (b5 + c5), d = 0.5 * (b5 - c5);
   const double Nop = std::pow(c + d, n) + sys.m_op * std::pow(c - d, n);
@@ -114,6 +114,28 @@ void build_struct(const Geometry& g, double b5, double c5, const eofa_system& sy
     else
       out[SCOEF_HEAD + s] = sgn(s + 1) * std::pow(c - d, n - 1 - s) / std::pow(c + d, 2 * n - s) * Nop;
   }
+  // Sherman-Morrison column a (zero when unshifted or A is singular: the
+  // dense matrices of build_fifth report that case as a breakdown)
+  double* a = out + SCOEF_HEAD + n;
+  for (int s = 0; s < n; ++s) a[s] = 0.0;
+  if (out[1] == 0.0) return;
+  const double bee = (c + d) * (4.0 - M5) + 1.0, cee = 1.0 - (c - d) * (4.0 - M5);
+  Mat A(n * n, 0.0), Ainv;
+  for (int s = 0; s < n; ++s) {
+    A[s * n + s] = bee;
+    if (chir > 0)  // L_+: (L y)_s = y_{s-1}, -m y_{Ls-1} at s = 0
+      A[s * n + (s > 0 ? s - 1 : n - 1)] -= cee * (s > 0 ? 1.0 : -sys.m_op);
+    else  // L_-: (L y)_s = y_{s+1}, -m y_0 at s = Ls-1
+      A[s * n + (s < n - 1 ? s + 1 : 0)] -= cee * (s < n - 1 ? 1.0 : -sys.m_op);
+  }
+  if (!invert(A, n, Ainv)) return;
+  std::vector<double> x(n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) x[i] += Ainv[i * n + j] * out[SCOEF_HEAD + j];
+  const int star = chir > 0 ? n - 1 : 0;
+  const double den = 1.0 + out[1] * x[star];
+  if (!std::isfinite(den) || std::fabs(den) < 1e-14) return;
+  for (int s = 0; s < n; ++s) a[s] = -out[1] * x[s] / den;
 }
 
 double k_eofa(int Ls, double c, double d, double m_a, double m_b) {

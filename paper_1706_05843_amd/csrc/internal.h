@@ -45,10 +45,12 @@ int build_fifth(const Geometry& g, double M5, double b5, double c5, const eofa_s
 // host: structured form of the same-parity block of one system,
 //   out[0] = m_op, out[1] = chi beta k(m_a, m_b) (0 if beta = 0), out[2] = chi,
 //   out[3] = 0, out[4 + s] = u_chi(m_op)_s   (App. B.2, eqn delta_rank_one)
-// so that M_ee = bee - cee L(m_op) + out[1] u e_{s*}^T on chirality chi,
-// s* = Ls-1 (chi = +1) or 0 (chi = -1).
+// so that M_ee = A + out[1] u e_{s*}^T on chirality chi, A = bee - cee L(m_op),
+// s* = Ls-1 (chi = +1) or 0 (chi = -1); and the Sherman-Morrison column
+//   out[4 + Ls + s] = a_s = -out[1] x_s / (1 + out[1] x_{s*}),  x = A^-1 u,
+// so that M_ee^-1 = (1 + a e_{s*}^T) A^-1 on chirality chi (0 if unshifted).
 constexpr int SCOEF_HEAD = 4;
-void build_struct(const Geometry& g, double b5, double c5, const eofa_system& sys, double* out);
+void build_struct(const Geometry& g, double M5, double b5, double c5, const eofa_system& sys, double* out);
 // host: EOFA constant k(m_a, m_b) and the Omega_+- columns (App. A)
 double k_eofa(int Ls, double c, double d, double m_a, double m_b);
 void omega_col(int Ls, double c, double d, int chir, double* w /* Ls */);
@@ -108,7 +110,7 @@ struct HopArgs {
   int matA, matB;
   double cpd, cmd;    // c+d, c-d (premix)
   const double* mop;  // [nrhs] operator mass
-  const double* scoef; // [nrhs][SCOEF_HEAD + Ls] structured same-parity coefficients
+  const double* scoef; // [nrhs][SCOEF_HEAD + 2 Ls] structured same-parity coefficients
   double bee, cee;    // (c+d)(4-M5)+1, 1-(c-d)(4-M5)
   const double* alpha;
   const int* halt;    // may be null

@@ -33,9 +33,12 @@ namespace eofa {
 //   A_MAT   v = M h            (dense Ls x Ls per chirality, through LDS)
 //   A_DTT   v = D~^T h         A_NDTT v = -D~^T h   (structured: lane exchange)
 //   A_MATDT v = M D~^T h
+//   A_MINV  v = M_ee^-1 h      A_MINVDT v = M_ee^-T D~^T h   (matA must be
+//           M_ee^-1 / M_ee^-T: dense through LDS, or with Ls = 16 the
+//           structured inverse along the row, see minv_rows)
 // plus the same-site term B y:
 //   B_MEE   + M_ee y           B_MEET + M_ee^T y    (structured: lane exchange)
-enum { A_ID = 0, A_NEG = 1, A_MAT = 2, A_DTT = 3, A_NDTT = 4, A_MATDT = 5 };
+enum { A_ID = 0, A_NEG = 1, A_MAT = 2, A_DTT = 3, A_NDTT = 4, A_MATDT = 5, A_MINV = 6, A_MINVDT = 7 };
 enum { B_NONE = 0, B_MEE = 1, B_MEET = 2, B_DENSE = 3 };
 enum { O_STORE = 0, O_ADDZ = 1, O_RUPD = 2, O_STORE_R = 3 };
 
@@ -52,9 +55,9 @@ struct RoleT;
   };
 EOFA_ROLE(ROLE_DSLASH, false, true, A_ID, B_NONE, O_STORE, false)
 EOFA_ROLE(ROLE_DSLASH_DAG, true, false, A_DTT, B_NONE, O_STORE, false)
-EOFA_ROLE(ROLE_K1, false, true, A_MAT, B_NONE, O_STORE, false)
+EOFA_ROLE(ROLE_K1, false, true, A_MINV, B_NONE, O_STORE, false)
 EOFA_ROLE(ROLE_K2, false, true, A_NEG, B_MEE, O_STORE, true)
-EOFA_ROLE(ROLE_K3, true, false, A_MATDT, B_NONE, O_STORE, false)
+EOFA_ROLE(ROLE_K3, true, false, A_MINVDT, B_NONE, O_STORE, false)
 EOFA_ROLE(ROLE_K4, true, false, A_NDTT, B_MEET, O_RUPD, true)
 EOFA_ROLE(ROLE_K4S, true, false, A_NDTT, B_MEET, O_STORE_R, true)
 EOFA_ROLE(ROLE_SRC, false, true, A_ID, B_NONE, O_ADDZ, false)
@@ -524,6 +527,78 @@ __device__ __forceinline__ cx<R> row_sum(cx<R> v) {
   return v + row_ror<1>(v);
 }
 
+// z <- (1 + rho^N L^N) z on the 6 components of one chirality half, Ls = 16.
+// UP: L = L_+ ((L z)_s = z_{s-1}, -m z_{15} at s = 0), a rotation by N;
+// else L = L_- ((L z)_s = z_{s+1}, -m z_0 at s = 15), a rotation by 16 - N.
+// Lanes whose source wraps around the column take the factor -m.
+template <class R, int N, bool UP>
+__device__ __forceinline__ void scan_step(cx<R>* z, int s, R rhoN, R m) {
+  const bool wrap = UP ? s < N : s > 15 - N;
+  const R f = wrap ? -m * rhoN : rhoN;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const cx<R> t = row_ror<UP ? N : 16 - N>(z[c]);
+    z[c].r = fma(f, t.r, z[c].r);
+    z[c].i = fma(f, t.i, z[c].i);
+  }
+}
+
+// Structured inverse of the same-parity block on a 16-lane row (App. B.2):
+// A = bee (1 - rho L), rho = cee / bee, and L^16 = -m, so
+//   A^-1 = (1 + rho^8 L^8)(1 + rho^4 L^4)(1 + rho^2 L^2)(1 + rho L) / (bee (1 + m rho^16))
+// (the geometric series of rho L, summed in four doublings); the EOFA shift
+// adds the rank-one Sherman-Morrison term on the shifted chirality:
+//   M_ee^-1 = (1 + a e_{s*}^T) A^-1,   M_ee^-T = A^-T (1 + e_{s*} a^T),
+// with a_s from the host. A^-T uses L^T, which for L_+ is L_- in structure
+// and vice versa. TRANS selects M_ee^-T. About 250 VALU operations per lane
+// instead of the 768 of the dense Ls x Ls product.
+template <class R, bool TRANS>
+__device__ __forceinline__ void minv_rows(cx<R>* v, int s, int g, R bee, R cee, R m, R sk, int chi, R a_s) {
+  const R rho = cee / bee;
+  const R rho2 = rho * rho, rho4 = rho2 * rho2, rho8 = rho4 * rho4, rho16 = rho8 * rho8;
+  const R scale = R(1) / (bee * (R(1) + m * rho16));
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    cx<R>* z = v + half * 6;
+    const int chir = half == 0 ? 1 : -1;
+    const bool shifted = sk != R(0) && chi == chir;  // uniform over the block
+    const int star = g * 16 + (chir > 0 ? 15 : 0);
+    if constexpr (TRANS) {
+      if (shifted) {  // z_{s*} += sum_s a_s z_s
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          const cx<R> t = row_sum(a_s * z[c]);
+          if (s == (chir > 0 ? 15 : 0)) z[c] = z[c] + t;
+        }
+      }
+    }
+    // A^-1 uses L_chi; A^-T the other direction
+    if ((chir > 0) != TRANS) {
+      scan_step<R, 1, true>(z, s, rho, m);
+      scan_step<R, 2, true>(z, s, rho2, m);
+      scan_step<R, 4, true>(z, s, rho4, m);
+      scan_step<R, 8, true>(z, s, rho8, m);
+    } else {
+      scan_step<R, 1, false>(z, s, rho, m);
+      scan_step<R, 2, false>(z, s, rho2, m);
+      scan_step<R, 4, false>(z, s, rho4, m);
+      scan_step<R, 8, false>(z, s, rho8, m);
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) z[c] = scale * z[c];
+    if constexpr (!TRANS) {
+      if (shifted) {  // z += a z_{s*}
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          const cx<R> zs = {__shfl(z[c].r, star, 64), __shfl(z[c].i, star, 64)};
+          z[c].r = fma(a_s, zs.r, z[c].r);
+          z[c].i = fma(a_s, zs.i, z[c].i);
+        }
+      }
+    }
+  }
+}
+
 // Rank-one part of the shifted same-parity block on the chirality half H0
 // (0: P_+, 6: P_-), with s* the special fifth-dimension index:
 //   TRANS = false:  v_s += sk u_s y_{s*}              (sk u e_{s*}^T y)
@@ -629,7 +704,10 @@ hop_kernel(HopArgs a) {
   const volatile int* s_self = nullptr;
   const FD fd = {Ls, Vh, a.nrhs};
 
-  constexpr bool DENSE = RT::AM == A_MAT || RT::AM == A_MATDT;
+  // the structured inverse (Ls = 16) needs no matrix in LDS
+  constexpr bool SINV = RL == 16 && (RT::AM == A_MINV || RT::AM == A_MINVDT);
+  constexpr bool DENSE =
+      RT::AM == A_MAT || RT::AM == A_MATDT || (!SINV && (RT::AM == A_MINV || RT::AM == A_MINVDT));
   constexpr bool BDENSE = RT::BM == B_DENSE;  // never together with DENSE: one matrix in LDS
   unsigned char* p = smem;
   cx<R>* s_link = (cx<R>*)p;
@@ -697,7 +775,7 @@ hop_kernel(HopArgs a) {
     const R cpd = (R)a.cpd, cmd = (R)a.cmd;
 
     cx<R> v[12];
-    if constexpr (RT::AM == A_ID || RT::AM == A_MAT) {
+    if constexpr (RT::AM == A_ID || RT::AM == A_MAT || RT::AM == A_MINV) {
 #pragma unroll
       for (int c = 0; c < 12; ++c) v[c] = acc[c];
     } else if constexpr (RT::AM == A_NEG) {
@@ -713,7 +791,13 @@ hop_kernel(HopArgs a) {
         v[c] = sgn * d;
       }
     }
-    if constexpr (DENSE && RL == 16) {  // v <- M v along the row's diagonals
+    if constexpr (SINV) {  // v <- M_ee^-1 v or M_ee^-T v, structured along the row
+      const double* scs = a.scoef + (size_t)r * (SCOEF_HEAD + 2 * Ls);
+      const R a_s = (R)scs[SCOEF_HEAD + Ls + s];
+      minv_rows<R, RT::AM == A_MINVDT>(v, s, g, (R)a.bee, (R)a.cee, (R)a.mop[r], (R)scs[1], (int)scs[2], a_s);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) asm volatile("" : "+v"(v[c].r), "+v"(v[c].i));
+    } else if constexpr (DENSE && RL == 16) {  // v <- M v along the row's diagonals
       cx<R> src[12];
 #pragma unroll
       for (int c = 0; c < 12; ++c) src[c] = v[c];
@@ -760,7 +844,7 @@ hop_kernel(HopArgs a) {
         v[c].r = fma(bee, y[c].r, fma(-cee, t[c].r, v[c].r));
         v[c].i = fma(bee, y[c].i, fma(-cee, t[c].i, v[c].i));
       }
-      const double* sc = a.scoef + (size_t)r * (SCOEF_HEAD + Ls);
+      const double* sc = a.scoef + (size_t)r * (SCOEF_HEAD + 2 * Ls);
       const R sk = (R)sc[1];
       if (sk != R(0)) {  // uniform over the block
         const int chi = (int)sc[2];
@@ -844,7 +928,9 @@ size_t hop_lds_t(int Ls, int W) {
   using RT = RoleT<ROLE>;
   using L = HopLds<R>;
   const int SBk = W * sites_per_wave(Ls);
-  constexpr bool DENSE = RT::AM == A_MAT || RT::AM == A_MATDT || RT::BM == B_DENSE;
+  const bool sinv = use_rows<P>(Ls) && (RT::AM == A_MINV || RT::AM == A_MINVDT);
+  const bool DENSE = RT::AM == A_MAT || RT::AM == A_MATDT || RT::BM == B_DENSE ||
+                     (!sinv && (RT::AM == A_MINV || RT::AM == A_MINVDT));
   size_t lds = L::links(SBk) + L::nbr(SBk);
   if (DENSE) lds += L::mat(Ls);
   if ((DENSE || RT::BM == B_MEET) && !use_rows<P>(Ls)) lds += L::col(SBk, Ls);
