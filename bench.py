@@ -253,7 +253,7 @@ def bench_learned(args, eofa, synth, torch, np):
 
     modes = {
         "plain_fp64": eofa.make_params(tol=1e-10, inner_prec=eofa.FP64),
-        "mixed_fp16s": eofa.make_params(tol=1e-10, inner_prec=eofa.FP16S),
+        "mixed_fp16s": eofa.make_params(tol=1e-10, inner_prec=eofa.FP16S, keep_direction=1),
         "fgcg_identity": eofa.make_params(tol=1e-10, precond=1),
         "fgcg_learned": eofa.make_params(tol=1e-10, precond=1, net=net),
     }
@@ -371,9 +371,10 @@ def bench_heatbath(args, eofa, synth, torch, np):
     ptol = [float(min(1e-5, tol * max(wts) / wl)) for wl in wts] * 2
     res = {}
     ref = None
-    for name, prm, pt in [("batched", eofa.make_params(tol=tol, inner_prec=eofa.FP16S), None),
-                          ("forecast", eofa.make_params(tol=tol, inner_prec=eofa.FP16S, use_guess=1), None),
-                          ("forecast_pole_tol", eofa.make_params(tol=tol, inner_prec=eofa.FP16S, use_guess=1), ptol)]:
+    kd = dict(inner_prec=eofa.FP16S)  # restarted passes: kept directions do not pay off here
+    for name, prm, pt in [("batched", eofa.make_params(tol=tol, **kd), None),
+                          ("forecast", eofa.make_params(tol=tol, use_guess=1, **kd), None),
+                          ("forecast_pole_tol", eofa.make_params(tol=tol, use_guess=1, **kd), ptol)]:
         phi = torch.zeros_like(eta)
         ctx.eofa_heatbath_solve(m1, m2, alpha, beta, eta, phi, prm, pole_tol=pt)  # warm-up
         torch.cuda.synchronize()
@@ -485,7 +486,7 @@ def bench_dense(args, eofa, synth, torch, np):
     for pname in ("fp64", "fp16s"):
         prec = PREC[pname]
         for form, fname in ((0, "cayley"), (1, "dense")):
-            prm = eofa.make_params(tol=1e-10, inner_prec=prec, profile=1, form=form)
+            prm = eofa.make_params(tol=1e-10, inner_prec=prec, profile=1, form=form, keep_direction=1)
             ctx.eofa_cg_solve(system, phi, psi, prm)  # warm-up (autotune)
             torch.cuda.synchronize()
             t0 = time.perf_counter()

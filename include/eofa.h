@@ -145,8 +145,11 @@ typedef struct {
   int32_t keep_direction; /* CGNR below FP64: 1 = each outer pass after the first keeps the
                           inner search direction and only replaces the residual by the FP64
                           one (a reliable update; passes then end at a residual reduction
-                          of at most 0.1 for FP16S, 0.01 for FP32); 0 = each pass restarts
-                          the inner CG from p = r (plain defect correction)                   */
+                          of at most 0.1 for FP16S, 0.01 for FP32; a pass whose |r|^2 grows
+                          1e4x is dropped and, like a pass that reduced the FP64 residual
+                          less than 2x, followed by a restart); 0 = each pass restarts the
+                          inner CG from p = r (plain defect correction). Pays on
+                          well-conditioned systems, costs iterations on ill-conditioned ones */
   int32_t pad2;
 } eofa_solver_params;
 

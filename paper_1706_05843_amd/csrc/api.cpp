@@ -394,7 +394,7 @@ struct Scal {
 
 int alloc_state(eofa_ctx* C, int nrhs, CgState& S) {
   void* b = nullptr;
-  const size_t nd = 7, ni = 5;
+  const size_t nd = 8, ni = 5;
   CHK(ws(C, "cgstate", (nd * sizeof(double) + ni * sizeof(int)) * nrhs + 64, &b));
   double* d = (double*)b;
   S.rr = d;
@@ -404,6 +404,7 @@ int alloc_state(eofa_ctx* C, int nrhs, CgState& S) {
   S.beta = d + 4 * nrhs;
   S.tol2 = d + 5 * nrhs;
   S.norm = d + 6 * nrhs;
+  S.guard = d + 7 * nrhs;
   int* ip = (int*)(d + nd * nrhs);
   S.iter = ip;
   S.max_iter = ip + nrhs;
@@ -678,7 +679,8 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
     launch_zero(P64, g, x, nrhs, st);
   }
 
-  std::vector<double> rro;
+  std::vector<double> rro, rro_prev(nrhs, 0.0);
+  std::vector<int> diverged(nrhs, 0);
   std::vector<int> hbuf(4 * nrhs);
   std::vector<double> hd(2 * nrhs);
   double hop_ms[4] = {0, 0, 0, 0};
@@ -764,9 +766,18 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
     if (all) break;
     if (fixed && outer >= 1) break;
 
+    // Reliable updates keep the previous pass's direction unless that pass
+    // diverged (stopped by its guard) or cut the FP64 residual by less than
+    // 2x: then every right-hand side restarts from p = r (kept directions go
+    // stale on ill-conditioned systems, where a pass is long in FP16).
+    bool restart = !(keep && outer > 0);
+    for (int r = 0; r < nrhs && !restart; ++r)
+      if (!done[r] && (diverged[r] || rro[r] > 0.25 * rro_prev[r])) restart = true;
+    for (int r = 0; r < nrhs; ++r) rro_prev[r] = rro[r];
+
     // inner CGNR in precision S on M^ e = r_o
     std::vector<int> mi(nrhs);
-    std::vector<double> t2(nrhs);
+    std::vector<double> t2(nrhs), gd(nrhs);
     for (int r = 0; r < nrhs; ++r) {
       mi[r] = done[r] ? 0 : (fixed ? prm->fixed_iters : std::max(0, prm->max_iter - iters[r]));
       double it_r = 0.0;
@@ -775,10 +786,13 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
         it_r = std::min(0.5, std::max(inner_floor, need));
       }
       t2[r] = it_r * it_r;
+      // a kept direction may diverge: stop its pass once |r|^2 grows 1e4x
+      gd[r] = restart ? 0.0 : 1e4;
       if (!done[r]) outers[r] += 1;
     }
     CHK(put(C, Sst.max_iter, mi.data(), nrhs * sizeof(int), st));
     CHK(put(C, Sst.tol2, t2.data(), nrhs * sizeof(double), st));
+    CHK(put(C, Sst.guard, gd.data(), nrhs * sizeof(double), st));
     launch_convert(P64, S, g, ro, rS, nrhs, st);
     {
       HopArgs a3 = base_args(C, S, 0, nrhs);
@@ -800,7 +814,7 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
     // p = r starts the inner CG afresh; a reliable update (keep_direction,
     // after the first pass) keeps the previous pass's direction p, which
     // stays conjugate to within the inner precision, and replaces only r
-    if (!(keep && outer > 0)) launch_convert(PR, S, g, rin, pS, nrhs, st);
+    if (restart) launch_convert(PR, S, g, rin, pS, nrhs, st);
     launch_zero(PR, g, xin, nrhs, st);
 
     if (prm->rhs_block > 0 || prm->waves > 0) {
@@ -873,18 +887,23 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
       }
     }
     HIPCHK(hipGetLastError());
-    launch_axpy_to64(PR, g, x, xin, nrhs, st);
     std::vector<int> hi(nrhs), hb(nrhs);
     CHK(fetch(C, Sst.iter, nrhs * sizeof(int), hi.data(), st));
     CHK(fetch(C, Sst.breakdown, nrhs * sizeof(int), hb.data(), st));
+    const size_t bR1 = packed_bytes(PR, g, 1);
     for (int r = 0; r < nrhs; ++r) {
+      diverged[r] = 0;
       if (done[r]) continue;
       iters[r] += hi[r];
-      if (hb[r]) {
+      if (hb[r] == 2) {  // a diverged pass contributes nothing; the next one restarts
+        diverged[r] = 1;
+        HIPCHK(hipMemsetAsync((char*)xin + bR1 * r, 0, bR1, st));
+      } else if (hb[r]) {
         status[r] = EOFA_ERR_BREAKDOWN;
         done[r] = 1;
       }
     }
+    launch_axpy_to64(PR, g, x, xin, nrhs, st);
   }
 
   std::vector<double> re, rodd;

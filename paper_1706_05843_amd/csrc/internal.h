@@ -64,11 +64,13 @@ struct CgState {
   double* beta;
   double* tol2;    // inner_tol^2 per rhs
   double* norm;    // scratch norms (FIN_NORM target)
+  double* guard;   // set before FIN_INIT as a factor, made absolute there: a pass whose
+                   // |r|^2 exceeds it is stopped as diverging (breakdown = 2); 0 = off
   int* iter;
   int* max_iter;
   int* halt;       // 1: this rhs does no more CG work
   int* u2run;      // 1: the x/p update of this iteration runs
-  int* breakdown;  // 1: non-finite or non-positive curvature met
+  int* breakdown;  // 1: non-finite or non-positive curvature met; 2: diverging pass (guard)
 };
 
 enum FinMode { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_NORM = 3 };

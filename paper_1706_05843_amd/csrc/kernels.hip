@@ -918,9 +918,9 @@ int hop_blocks(int prec, int Vh, int Ls, int W) {
   return (Vh + SBk - 1) / SBk;
 }
 
-// the row form (RL = 16) serves Ls = 16 below FP64
+// the row form (RL = 16) serves Ls = 16 at every precision
 template <int P>
-bool use_rows(int Ls) { return P != P64 && Ls == 16; }
+bool use_rows(int Ls) { return Ls == 16; }
 
 template <int P, int ROLE>
 size_t hop_lds_t(int Ls, int W) {
@@ -979,9 +979,7 @@ int launch_hop_t(const HopArgs& a, hipStream_t st, int* nblk_out) {
   b.rhs_block = rb;
   b.W = W;
   void (*fn)(HopArgs) = hop_kernel<P, acc_prec<P>(), ROLE, 0>;
-  if constexpr (P != P64) {
-    if (use_rows<P>(Ls)) fn = hop_kernel<P, acc_prec<P>(), ROLE, 16>;
-  }
+  if (use_rows<P>(Ls)) fn = hop_kernel<P, acc_prec<P>(), ROLE, 16>;
   if (lds > 65536) {
     if (hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
         hipSuccess)
@@ -1403,6 +1401,7 @@ __device__ void finalize_step(int mode, double sum, const CgState& S, int r, dou
   if (mode == FIN_INIT) {
     S.rr[r] = sum;
     S.stop[r] = S.tol2[r] * sum;
+    S.guard[r] *= sum;
     S.iter[r] = 0;
     S.u2run[r] = 0;
     S.breakdown[r] = 0;
@@ -1441,6 +1440,9 @@ __device__ void finalize_step(int mode, double sum, const CgState& S, int r, dou
     S.u2run[r] = 0;
   } else if (rrn <= S.stop[r] || S.iter[r] >= S.max_iter[r]) {
     S.halt[r] = 1;
+  } else if (S.guard[r] > 0.0 && rrn > S.guard[r]) {
+    S.halt[r] = 1;
+    S.breakdown[r] = 2;
   }
 }
 

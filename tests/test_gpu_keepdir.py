@@ -7,7 +7,9 @@ inner CG direction and replace only the residual.
   1e-10-residual solutions of the same system; the light chi1 system
   amplifies the residual difference by its condition number);
 * a batch of systems and the heatbath (which solves through the same driver)
-  give the same results as with restarts.
+  give the same results as with restarts;
+* an ill-conditioned system (m1 = 0.0025) still converges (divergence guard
+  and restart after a pass without progress).
 """
 import numpy as np
 import pytest
@@ -72,3 +74,17 @@ def test_keep_direction_heatbath(setup):
         assert rc == eofa.EOFA_OK
         out[keep] = ph.cpu().numpy()
     assert np.sqrt(norm2(out[1] - out[0]) / norm2(out[0])) < 1e-9
+
+
+def test_keep_direction_light_mass(setup):
+    """An ill-conditioned shifted system (m1 = 0.0025), where kept directions
+    can diverge within a pass: the guard and the progress check keep the solve
+    converging to the FP64 true residual."""
+    act, U, ctx, phi = setup
+    light = System(1.0, 0.0025, 1.0, -1.0, +1)
+    ph = torch.from_numpy(phi[:1]).cuda()
+    psi = torch.zeros_like(ph)
+    rc, st = ctx.eofa_cg_solve([light], ph, psi, eofa.make_params(tol=1e-10, inner_prec=eofa.FP16S,
+                                                                   keep_direction=1))
+    assert rc == eofa.EOFA_OK and st[0]["converged"] == 1
+    assert _res(act, U, light, psi.cpu().numpy()[0], phi[0]) < 1.05e-10

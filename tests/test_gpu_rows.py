@@ -1,8 +1,9 @@
-"""The Ls = 16 row form of the hop kernels (FP32 and FP16S): every exchange
+"""The Ls = 16 row form of the hop kernels (all precisions): every exchange
 along s is a DPP row rotation, M_ee^-1 and M_ee^-T are the structured inverse
 (geometric series of rho L summed in four doublings plus the Sherman-Morrison
 term), the dense blocks of the dense form run along cyclic diagonals.
 
+* mirror mode in FP64: 40 fixed iterations equal the oracle's to 1e-12;
 * mirror mode in FP32: 20 fixed CGNR iterations through K1..K4 against the
   oracle's 20 FP64 iterations, for a +chirality shift (chi2), a -chirality
   shift (beta = -0.5) and no shift (chi1): 1e-4 relative (FP32 rounding of
@@ -42,6 +43,18 @@ def setup():
 
 def _res(act, U, sysm, sol, phi):
     return np.sqrt(norm2(H_system(act, U, sysm, sol) - phi) / norm2(phi))
+
+
+@pytest.mark.parametrize("k", range(3))
+def test_mirror_fp64(setup, k):
+    """FP64: the oracle's iterates to 1e-12, as for the generic form."""
+    act, U, ctx, phi = setup
+    ref = eo.solve_mirror(act, U, SYSTEMS[k], phi[k], iters=40)["psi"]
+    ph = torch.from_numpy(phi[k:k + 1]).cuda()
+    psi = torch.zeros_like(ph)
+    ctx.eofa_cg_solve([SYSTEMS[k]], ph, psi, eofa.make_params(fixed_iters=40))
+    got = psi.cpu().numpy()[0]
+    assert np.sqrt(norm2(got - ref) / norm2(ref)) < 1e-12
 
 
 @pytest.mark.parametrize("k", range(3))
