@@ -649,6 +649,10 @@ def main():
     dom_bytes = role_bytes(dom, prec, Ls, Nh)
     achieved = dom_bytes / (avg_ms * 1e-3) / 1e9
     traffic = traffic_from_profile(args.workload, args.inner, dom)
+    # Wilson-hop flops: 1320 per 4D site per Ls slice (the conventional count, per hop launch)
+    flop_per_launch = 1320.0 * Nh
+    gflops_dom = flop_per_launch / (avg_ms * 1e-3) / 1e9
+    gflops_job = 4 * iters * flop_per_launch / dt / 1e9
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                 kernel=ROLE_NAMES[dom], avg_launch_us=round(avg_ms * 1e3, 2),
@@ -668,6 +672,8 @@ def main():
                                f"links exp(i {eps} H), system H(m2)-Delta_+(m1,m2)P_+ m1={m1} m2={m2}, "
                                f"1 Gaussian RHS, true residual 1e-10",
                    "lattice": list(dims), "Ls": Ls, "nrhs": 1, "inner": args.inner},
+        "dslash_gflops": {"dominant_kernel": round(gflops_dom, 1), "whole_job": round(gflops_job, 1),
+                          "flop_model": "1320 flop per 4D site per Ls slice per hop launch (4 launches per iteration)"},
         "time_to_solution_s": round(ms / 1e3, 5),
         "iters": stats[-1]["iters"], "outer_iters": stats[-1]["outer_iters"],
         "true_resid": stats[-1]["true_resid"],
