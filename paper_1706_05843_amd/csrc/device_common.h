@@ -142,6 +142,60 @@ __device__ __forceinline__ void ld_spinor(const void* base, const FD& f, int r, 
   }
 }
 
+// Streaming (non-temporal) access for fields touched once per kernel (the
+// CG residual and solution): they bypass the cache ways that hold the
+// neighbour spinors the hop re-reads. FP16S fields go through the normal path.
+typedef float f4v_t __attribute__((ext_vector_type(4)));
+typedef double d2v_t __attribute__((ext_vector_type(2)));
+
+template <int P, class R>
+__device__ __forceinline__ void ld_spinor_nt(const void* base, const FD& f, int r, int s, int i, cx<R>* v) {
+  const size_t e0 = eidx(f, r, 0, s, i), qs = qstride(f);
+  if constexpr (P == P32) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const f4v_t t = __builtin_nontemporal_load((const f4v_t*)base + e0 + q * qs);
+      v[2 * q] = {(R)t.x, (R)t.y};
+      v[2 * q + 1] = {(R)t.z, (R)t.w};
+    }
+  } else if constexpr (P == P64) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const d2v_t* pp = (const d2v_t*)base + 2 * (e0 + q * qs);
+      const d2v_t t0 = __builtin_nontemporal_load(pp), t1 = __builtin_nontemporal_load(pp + 1);
+      v[2 * q] = {(R)t0.x, (R)t0.y};
+      v[2 * q + 1] = {(R)t1.x, (R)t1.y};
+    }
+  } else {
+    ld_spinor<P>(base, f, r, s, i, v);
+  }
+}
+
+template <int P, class R>
+__device__ __forceinline__ void st_spinor(void* base, const FD& f, int r, int s, int i, const cx<R>* v);
+
+template <int P, class R>
+__device__ __forceinline__ void st_spinor_nt(void* base, const FD& f, int r, int s, int i, const cx<R>* v) {
+  const size_t e0 = eidx(f, r, 0, s, i), qs = qstride(f);
+  if constexpr (P == P32) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const f4v_t t = {(float)v[2 * q].r, (float)v[2 * q].i, (float)v[2 * q + 1].r, (float)v[2 * q + 1].i};
+      __builtin_nontemporal_store(t, (f4v_t*)base + e0 + q * qs);
+    }
+  } else if constexpr (P == P64) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      d2v_t* pp = (d2v_t*)base + 2 * (e0 + q * qs);
+      const d2v_t t0 = {(double)v[2 * q].r, (double)v[2 * q].i}, t1 = {(double)v[2 * q + 1].r, (double)v[2 * q + 1].i};
+      __builtin_nontemporal_store(t0, pp);
+      __builtin_nontemporal_store(t1, pp + 1);
+    }
+  } else {
+    st_spinor<P>(base, f, r, s, i, v);
+  }
+}
+
 template <int P, class R>
 __device__ __forceinline__ void st_spinor(void* base, const FD& f, int r, int s, int i, const cx<R>* v) {
   if constexpr (P == P16) {

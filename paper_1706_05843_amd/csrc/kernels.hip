@@ -871,7 +871,7 @@ hop_kernel(HopArgs a) {
         using RR = typename ST<PR>::R;
         cx<RR> w[12];
         if constexpr (RT::OM == O_RUPD) {
-          ld_spinor<PR>(a.r, fd, r, s, EOFA_SITE, w);
+          ld_spinor_nt<PR>(a.r, fd, r, s, EOFA_SITE, w);
           const RR al = (RR)a.alpha[r];
 #pragma unroll
           for (int c = 0; c < 12; ++c) {
@@ -882,7 +882,7 @@ hop_kernel(HopArgs a) {
 #pragma unroll
           for (int c = 0; c < 12; ++c) w[c] = {(RR)v[c].r, (RR)v[c].i};
         }
-        st_spinor<PR>(a.r, fd, r, s, EOFA_SITE, w);
+        st_spinor_nt<PR>(a.r, fd, r, s, EOFA_SITE, w);
 #pragma unroll
         for (int c = 0; c < 12; ++c) v[c] = {(R)w[c].r, (R)w[c].i};
       }
@@ -1320,9 +1320,9 @@ __global__ void __launch_bounds__(256) cg_update_kernel(int Ls, int Vh, int nrhs
   using RS = typename ST<PS>::R;
   cx<RS> pv[12];
   cx<RR> xv[12], rv[12];
-  ld_spinor<PS>(p, f, r, s, i, pv);
-  ld_spinor<PR>(x, f, r, s, i, xv);
-  ld_spinor<PR>(rr, f, r, s, i, rv);
+  ld_spinor<PS>(p, f, r, s, i, pv);  // p is re-read by the next hop's neighbours: cached
+  ld_spinor_nt<PR>(x, f, r, s, i, xv);
+  ld_spinor_nt<PR>(rr, f, r, s, i, rv);
   const RR al = (RR)alpha[r], be = (RR)beta[r];
   cx<RS> pn[12];
 #pragma unroll
@@ -1332,7 +1332,7 @@ __global__ void __launch_bounds__(256) cg_update_kernel(int Ls, int Vh, int nrhs
     xv[c].i = fma(al, pc.i, xv[c].i);
     pn[c] = {(RS)fma(be, pc.r, rv[c].r), (RS)fma(be, pc.i, rv[c].i)};
   }
-  st_spinor<PR>(x, f, r, s, i, xv);
+  st_spinor_nt<PR>(x, f, r, s, i, xv);
   st_spinor<PS>(p, f, r, s, i, pn);
 }
 
