@@ -464,16 +464,31 @@ const Form kDense = {ROLE_D1, ROLE_D2, ROLE_D3, ROLE_D4, ROLE_D4S, ROLE_DSRC, RO
                      MAT_DEE_INV, MAT_DEE, MAT_DEE_INV_T, 0, MAT_DEE_T,
                      MAT_DEE_INV, MAT_DEE, false};
 
-// One inner CGNR iteration: K1, K2, alpha, K3, K4, beta, x/p update.
+// Ring of search directions for the batched solution update: iteration k
+// reads p_k from slot k mod R and writes p_{k+1} to the next slot; every F
+// iterations x += sum alpha_j p_j over the last F slots (one pass over x per
+// F iterations instead of one per iteration). R = 16 matches the host poll
+// and graph period, so slot indices repeat identically in every replay.
+struct Ring {
+  char* base = nullptr;
+  size_t slot = 0;           // bytes per slot (all right-hand sides)
+  double* ahist = nullptr;   // [R][nrhs] alpha of each step, 0 if it did not run
+  static constexpr int R = 16, F = 8;
+  void* at(int k) const { return base + (size_t)(k % R) * slot; }
+};
+
+// One inner CGNR iteration k: K1, K2, alpha, K3, K4, beta, x/p update.
 int inner_iteration(eofa_ctx* C, const Form& F, int S, int PR, const HopArgs& k1, const HopArgs& k2,
                     const HopArgs& k3, const HopArgs& k4, int nbh, int nrhs, CgState Sst, double* partial,
-                    void* xin, void* rin, void* pS, hipStream_t st, hipEvent_t* ev) {
+                    void* xin, void* rin, void* pS, hipStream_t st, hipEvent_t* ev, const Ring* ring, int k) {
   const Geometry& g = C->g;
+  HopArgs a1 = k1, a2 = k2;
+  if (ring) a1.in = a2.y = ring->at(k);
   if (ev) HIPCHK(hipEventRecord(ev[0], st));
-  CHK(hop(C, S, F.k1, k1, st));
+  CHK(hop(C, S, F.k1, a1, st));
   if (ev) HIPCHK(hipEventRecord(ev[1], st));
   if (ev) HIPCHK(hipEventRecord(ev[2], st));
-  CHK(hop(C, S, F.k2, k2, st));
+  CHK(hop(C, S, F.k2, a2, st));
   if (ev) HIPCHK(hipEventRecord(ev[3], st));
   launch_finalize(FIN_ALPHA, partial, nbh, nrhs, Sst, nullptr, st);
   if (ev) HIPCHK(hipEventRecord(ev[4], st));
@@ -483,7 +498,15 @@ int inner_iteration(eofa_ctx* C, const Form& F, int S, int PR, const HopArgs& k1
   CHK(hop(C, S, F.k4, k4, st));
   if (ev) HIPCHK(hipEventRecord(ev[7], st));
   launch_finalize(FIN_BETA, partial, nbh, nrhs, Sst, nullptr, st);
-  launch_cg_update(S, PR, g, xin, rin, pS, Sst.alpha, Sst.beta, Sst.u2run, nrhs, st);
+  if (ring) {
+    launch_p_update(S, g, rin, ring->at(k), ring->at(k + 1), Sst.alpha, Sst.beta, Sst.u2run,
+                    ring->ahist + (size_t)(k % Ring::R) * nrhs, nrhs, st);
+    if ((k + 1) % Ring::F == 0)
+      launch_x_flush(S, g, xin, ring->base, ring->slot, (k + 1 - Ring::F) % Ring::R, Ring::F, Ring::R, ring->ahist,
+                     nrhs, st);
+  } else {
+    launch_cg_update(S, PR, g, xin, rin, pS, Sst.alpha, Sst.beta, Sst.u2run, nrhs, st);
+  }
   return EOFA_OK;
 }
 
@@ -643,6 +666,23 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
   double* partial = (double*)partial_v;
   CgState Sst;
   CHK(alloc_state(C, nrhs, Sst));
+  // direction ring (batched x update) when its R slots fit a modest budget
+  // and the poll period is a multiple of R; else the fused per-step update
+  Ring ring_store;
+  const Ring* ring = nullptr;
+  int last_it = 0;  // iterations of the previous pass (its last direction sits in slot last_it mod R)
+  {
+    const size_t ring_bytes = (size_t)Ring::R * bS;
+    if (check % Ring::R == 0 && ring_bytes <= (size_t)8 << 30) {
+      void *rb, *ah;
+      CHK(ws(C, "pring", ring_bytes, &rb));
+      CHK(ws(C, "ahist", sizeof(double) * Ring::R * nrhs, &ah));
+      ring_store.base = (char*)rb;
+      ring_store.slot = bS;
+      ring_store.ahist = (double*)ah;
+      ring = &ring_store;
+    }
+  }
 
   // b = g5 R5 phi, |b|^2
   launch_pack(P64, g, phi, be, 0, nrhs, 1, st);
@@ -814,7 +854,12 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
     // p = r starts the inner CG afresh; a reliable update (keep_direction,
     // after the first pass) keeps the previous pass's direction p, which
     // stays conjugate to within the inner precision, and replaces only r
-    if (restart) launch_convert(PR, S, g, rin, pS, nrhs, st);
+    void* p0 = ring ? ring->at(0) : pS;
+    if (restart) {
+      launch_convert(PR, S, g, rin, p0, nrhs, st);
+    } else if (ring && last_it % Ring::R != 0) {  // the kept direction into slot 0
+      HIPCHK(hipMemcpyAsync(p0, ring->at(last_it), bS, hipMemcpyDeviceToDevice, st));
+    }
     launch_zero(PR, g, xin, nrhs, st);
 
     if (prm->rhs_block > 0 || prm->waves > 0) {
@@ -844,7 +889,7 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
       HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
       for (int k = 0; k < check; ++k) {
         const int rc =
-            inner_iteration(C, F, S, PR, k1, k2, k3, k4, nbh, nrhs, Sst, partial, xin, rin, pS, cs, nullptr);
+            inner_iteration(C, F, S, PR, k1, k2, k3, k4, nbh, nrhs, Sst, partial, xin, rin, pS, cs, nullptr, ring, k);
         if (rc != EOFA_OK) {
           hipGraph_t dead;
           (void)hipStreamEndCapture(cs, &dead);
@@ -875,7 +920,7 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
         // events bracket the kernels and not host launch latency
         const bool prof = prm->profile && timed < max_timed && (it % 8 == 4);
         hipEvent_t* ev = prof ? &C->events[timed * 8] : nullptr;
-        CHK(inner_iteration(C, F, S, PR, k1, k2, k3, k4, nbh, nrhs, Sst, partial, xin, rin, pS, st, ev));
+        CHK(inner_iteration(C, F, S, PR, k1, k2, k3, k4, nbh, nrhs, Sst, partial, xin, rin, pS, st, ev, ring, it));
         if (prof) ++timed;
         ++it;
         if (it % check == 0 || it >= cap) {
@@ -886,6 +931,11 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
         }
       }
     }
+    if (ring && it % Ring::F != 0) {  // the steps since the last batched x update
+      const int rem = it % Ring::F;
+      launch_x_flush(S, g, xin, ring->base, ring->slot, (it - rem) % Ring::R, rem, Ring::R, ring->ahist, nrhs, st);
+    }
+    last_it = it;
     HIPCHK(hipGetLastError());
     std::vector<int> hi(nrhs), hb(nrhs);
     CHK(fetch(C, Sst.iter, nrhs * sizeof(int), hi.data(), st));

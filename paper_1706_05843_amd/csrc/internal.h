@@ -141,6 +141,12 @@ void launch_convert(int pin, int pout, const Geometry& g, const void* in, void* 
 void launch_axpy_to64(int pin, const Geometry& g, void* x64, const void* e, int nrhs, hipStream_t st);
 void launch_zero(int prec, const Geometry& g, void* f, int nrhs, hipStream_t st);
 int launch_norm2(int prec, const Geometry& g, const void* f, int nrhs, double* partial, hipStream_t st);
+// ring form of the CG update: p into the next slot (alpha kept in ahist[nrhs]),
+// and x += sum of kept alpha times the directions of nslots slots
+void launch_p_update(int ps, const Geometry& g, const void* r, const void* p, void* pn, const double* alpha,
+                     const double* beta, const int* u2run, double* ahist, int nrhs, hipStream_t st);
+void launch_x_flush(int ps, const Geometry& g, void* x, const void* ring, size_t slot_bytes, int first, int nslots,
+                    int R, const double* ahist, int nrhs, hipStream_t st);
 void launch_cg_update(int ps, int pr, const Geometry& g, void* x, const void* r, void* p, const double* alpha,
                       const double* beta, const int* u2run, int nrhs, hipStream_t st);
 void launch_finalize(int mode, const double* partial, int nblk, int nrhs, CgState st_, double* out,

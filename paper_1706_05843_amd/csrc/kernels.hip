@@ -1378,6 +1378,93 @@ int launch_norm2(int prec, const Geometry& g, const void* f, int nrhs, double* p
   return nblk;
 }
 
+// CG update with the solution update batched over a ring of directions:
+// p_{k+1} = r + beta p_k goes to the next ring slot, and the step's alpha is
+// kept (0 when the step did not run); a right-hand side whose CG has stopped
+// carries p forward, so the last direction is always in the newest slot.
+template <int PS, int PR>
+__global__ void __launch_bounds__(256) p_update_kernel(int Ls, int Vh, int nrhs, const void* rr, const void* p,
+                                                         void* pn, const double* alpha, const double* beta,
+                                                         const int* u2run, double* ahist) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (idx >= Ls * Vh) return;
+  const bool run = u2run[r] != 0;
+  if (idx == 0) ahist[r] = run ? alpha[r] : 0.0;
+  const int i = idx / Ls, s = idx - i * Ls;
+  const FD f = {Ls, Vh, nrhs};
+  using RR = typename ST<PR>::R;
+  using RS = typename ST<PS>::R;
+  cx<RS> pv[12];
+  ld_spinor<PS>(p, f, r, s, i, pv);
+  if (run) {
+    cx<RR> rv[12];
+    ld_spinor_nt<PR>(rr, f, r, s, i, rv);
+    const RR be = (RR)beta[r];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) pv[c] = {(RS)fma(be, (RR)pv[c].r, rv[c].r), (RS)fma(be, (RR)pv[c].i, rv[c].i)};
+  }
+  st_spinor<PS>(pn, f, r, s, i, pv);
+}
+
+// x += sum over nslots ring slots j of ahist[j] p_j (slots first, first+1, ...
+// mod R); steps that did not run have alpha 0 and are skipped (uniform per
+// right-hand side, so their directions are not read)
+template <int PS, int PR>
+__global__ void __launch_bounds__(256) x_flush_kernel(int Ls, int Vh, int nrhs, void* x, const char* ring,
+                                                        size_t slot_bytes, int first, int nslots, int R,
+                                                        const double* ahist) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (idx >= Ls * Vh) return;
+  const int i = idx / Ls, s = idx - i * Ls;
+  const FD f = {Ls, Vh, nrhs};
+  using RR = typename ST<PR>::R;
+  using RS = typename ST<PS>::R;
+  cx<RR> xv[12];
+  ld_spinor_nt<PR>(x, f, r, s, i, xv);
+  for (int j = 0; j < nslots; ++j) {
+    const int slot = (first + j) % R;
+    const RR a = (RR)ahist[(size_t)slot * nrhs + r];
+    if (a == RR(0)) continue;
+    cx<RS> pv[12];
+    ld_spinor<PS>(ring + slot * slot_bytes, f, r, s, i, pv);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      xv[c].r = fma(a, (RR)pv[c].r, xv[c].r);
+      xv[c].i = fma(a, (RR)pv[c].i, xv[c].i);
+    }
+  }
+  st_spinor_nt<PR>(x, f, r, s, i, xv);
+}
+
+void launch_p_update(int ps, const Geometry& g, const void* r, const void* p, void* pn, const double* alpha,
+                     const double* beta, const int* u2run, double* ahist, int nrhs, hipStream_t st) {
+  if (ps == P64)
+    hipLaunchKernelGGL((p_update_kernel<P64, P64>), EOFA_EW_GRID, g.Ls, g.Vh, nrhs, r, p, pn, alpha, beta, u2run,
+                       ahist);
+  else if (ps == P32)
+    hipLaunchKernelGGL((p_update_kernel<P32, P32>), EOFA_EW_GRID, g.Ls, g.Vh, nrhs, r, p, pn, alpha, beta, u2run,
+                       ahist);
+  else
+    hipLaunchKernelGGL((p_update_kernel<P16, P32>), EOFA_EW_GRID, g.Ls, g.Vh, nrhs, r, p, pn, alpha, beta, u2run,
+                       ahist);
+}
+
+void launch_x_flush(int ps, const Geometry& g, void* x, const void* ring, size_t slot_bytes, int first, int nslots,
+                    int R, const double* ahist, int nrhs, hipStream_t st) {
+  const char* rg = (const char*)ring;
+  if (ps == P64)
+    hipLaunchKernelGGL((x_flush_kernel<P64, P64>), EOFA_EW_GRID, g.Ls, g.Vh, nrhs, x, rg, slot_bytes, first, nslots,
+                       R, ahist);
+  else if (ps == P32)
+    hipLaunchKernelGGL((x_flush_kernel<P32, P32>), EOFA_EW_GRID, g.Ls, g.Vh, nrhs, x, rg, slot_bytes, first, nslots,
+                       R, ahist);
+  else
+    hipLaunchKernelGGL((x_flush_kernel<P16, P32>), EOFA_EW_GRID, g.Ls, g.Vh, nrhs, x, rg, slot_bytes, first, nslots,
+                       R, ahist);
+}
+
 void launch_cg_update(int ps, int pr, const Geometry& g, void* x, const void* r, void* p, const double* alpha,
                       const double* beta, const int* u2run, int nrhs, hipStream_t st) {
   if (ps == P64)
