@@ -97,11 +97,6 @@ struct HopLds {
   static __host__ __device__ size_t col(int SBk, int Ls) { return (size_t)SBk * (Ls * 6 + 1) * sizeof(cx<R>); }
 };
 
-// Dhop (or g5 Dhop g5 when DAG) applied to D~ in (PRE) at the 5D site (s, i)
-// of local site ls. The D~ premix needs P_+ psi at s-1 and P_- psi at s+1 of
-// the same neighbour: the lanes (g, s-1) and (g, s+1) of this wave hold
-// exactly those spinors for the same direction, so they are exchanged across
-// lanes instead of being loaded again.
 // One direction's neighbour spinor as loaded: FP16S keeps the raw half2
 // words and the site scale (decoded inside the arithmetic), else the values.
 template <int P>
@@ -297,6 +292,11 @@ __device__ __forceinline__ void hop_site_h(const HopArgs& a, const FD& fin, int 
   for (int c = 0; c < 12; ++c) acc[c] = post * acc[c];
 }
 
+// Dhop (or g5 Dhop g5 when DAG) applied to D~ in (PRE) at the 5D site (s, i)
+// of local site ls. The D~ premix needs P_+ psi at s-1 and P_- psi at s+1 of
+// the same neighbour: the lanes (g, s-1) and (g, s+1) of this wave hold
+// exactly those spinors for the same direction, so they are exchanged across
+// lanes instead of being loaded again.
 template <int P, bool DAG, bool PRE, int RL, bool YPRE>
 __device__ __forceinline__ void hop_site(const HopArgs& a, const FD& fin, int r, int s, int g, int ls,
                                          const cx<typename ST<P>::R>* s_link, const int* s_nbr,
