@@ -53,10 +53,9 @@ def link_bytes_per_site(prec):
 def role_bytes(role, prec, Ls, Nh):
     """Algorithmic (compulsory) bytes of one launch of an inner hop kernel:
     every input field read once, every output written once, every link once."""
-    E = site_bytes(prec)
-    ER = 192 if prec == 0 else 96  # residual kept in the accumulator precision
+    E = site_bytes(prec)  # the inner residual is kept in the inner precision too
     lk = link_bytes_per_site(prec) / Ls
-    per = {0: 2 * E, 1: 3 * E, 2: 2 * E, 3: 2 * E + 2 * ER}[role] + lk
+    per = {0: 2 * E, 1: 3 * E, 2: 2 * E, 3: 4 * E}[role] + lk
     return per * Nh
 
 

@@ -478,7 +478,7 @@ struct Ring {
 };
 
 // One inner CGNR iteration k: K1, K2, alpha, K3, K4, beta, x/p update.
-int inner_iteration(eofa_ctx* C, const Form& F, int S, int PR, const HopArgs& k1, const HopArgs& k2,
+int inner_iteration(eofa_ctx* C, const Form& F, int S, const HopArgs& k1, const HopArgs& k2,
                     const HopArgs& k3, const HopArgs& k4, int nbh, int nrhs, CgState Sst, double* partial,
                     void* xin, void* rin, void* pS, hipStream_t st, hipEvent_t* ev, const Ring* ring, int k) {
   const Geometry& g = C->g;
@@ -505,7 +505,7 @@ int inner_iteration(eofa_ctx* C, const Form& F, int S, int PR, const HopArgs& k1
       launch_x_flush(S, g, xin, ring->base, ring->slot, (k + 1 - Ring::F) % Ring::R, Ring::F, Ring::R, ring->ahist,
                      nrhs, st);
   } else {
-    launch_cg_update(S, PR, g, xin, rin, pS, Sst.alpha, Sst.beta, Sst.u2run, nrhs, st);
+    launch_cg_update(S, g, xin, rin, pS, Sst.alpha, Sst.beta, Sst.u2run, nrhs, st);
   }
   return EOFA_OK;
 }
@@ -628,7 +628,9 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
   const Geometry& g = C->g;
   const Form& F = prm->form == 1 ? kDense : kCayley;
   const int S = prm->inner_prec;
-  const int PR = S == P64 ? P64 : P32;
+  // the inner residual is kept in the inner precision S, the inner
+  // solution in FP32 (FP64 for FP64 inner solves)
+  const int PX = S == P64 ? P64 : P32;
   const bool fixed = prm->fixed_iters > 0;
   const int max_outer = fixed ? 1 : std::max(1, prm->max_outer);
   const int check = prm->check_every > 0 ? prm->check_every : 16;
@@ -646,7 +648,7 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
 
   CHK(upload_systems(C, sys, nrhs, st));
   CHK(stage(C, 64 * (size_t)std::max(nrhs, 16)));
-  const size_t b64 = packed_bytes(P64, g, nrhs), bS = packed_bytes(S, g, nrhs), bR = packed_bytes(PR, g, nrhs);
+  const size_t b64 = packed_bytes(P64, g, nrhs), bS = packed_bytes(S, g, nrhs), bX = packed_bytes(PX, g, nrhs);
   void *be, *bo, *bt, *x, *ro, *te, *tmp, *rS, *pS, *tS, *wS, *rin, *xin, *partial_v;
   CHK(ws(C, "be", b64, &be));
   CHK(ws(C, "bo", b64, &bo));
@@ -659,8 +661,8 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
   CHK(ws(C, "pS", bS, &pS));
   CHK(ws(C, "tS", bS, &tS));
   CHK(ws(C, "wS", bS, &wS));
-  CHK(ws(C, "rin", bR, &rin));
-  CHK(ws(C, "xin", bR, &xin));
+  CHK(ws(C, "rin", bS, &rin));
+  CHK(ws(C, "xin", bX, &xin));
   const int maxblk = std::max(hop_blocks(P64, g.Vh, g.Ls, 1), (g.Ls * g.Vh + 255) / 256);  // W = 1 has the most blocks
   CHK(ws(C, "partial", sizeof(double) * (size_t)maxblk * nrhs, &partial_v));
   double* partial = (double*)partial_v;
@@ -856,11 +858,11 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
     // stays conjugate to within the inner precision, and replaces only r
     void* p0 = ring ? ring->at(0) : pS;
     if (restart) {
-      launch_convert(PR, S, g, rin, p0, nrhs, st);
+      launch_convert(S, S, g, rin, p0, nrhs, st);
     } else if (ring && last_it % Ring::R != 0) {  // the kept direction into slot 0
       HIPCHK(hipMemcpyAsync(p0, ring->at(last_it), bS, hipMemcpyDeviceToDevice, st));
     }
-    launch_zero(PR, g, xin, nrhs, st);
+    launch_zero(PX, g, xin, nrhs, st);
 
     if (prm->rhs_block > 0 || prm->waves > 0) {
       const int w = prm->waves > 0 ? prm->waves : default_waves(g.Ls);
@@ -889,7 +891,7 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
       HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
       for (int k = 0; k < check; ++k) {
         const int rc =
-            inner_iteration(C, F, S, PR, k1, k2, k3, k4, nbh, nrhs, Sst, partial, xin, rin, pS, cs, nullptr, ring, k);
+            inner_iteration(C, F, S, k1, k2, k3, k4, nbh, nrhs, Sst, partial, xin, rin, pS, cs, nullptr, ring, k);
         if (rc != EOFA_OK) {
           hipGraph_t dead;
           (void)hipStreamEndCapture(cs, &dead);
@@ -920,7 +922,7 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
         // events bracket the kernels and not host launch latency
         const bool prof = prm->profile && timed < max_timed && (it % 8 == 4);
         hipEvent_t* ev = prof ? &C->events[timed * 8] : nullptr;
-        CHK(inner_iteration(C, F, S, PR, k1, k2, k3, k4, nbh, nrhs, Sst, partial, xin, rin, pS, st, ev, ring, it));
+        CHK(inner_iteration(C, F, S, k1, k2, k3, k4, nbh, nrhs, Sst, partial, xin, rin, pS, st, ev, ring, it));
         if (prof) ++timed;
         ++it;
         if (it % check == 0 || it >= cap) {
@@ -940,20 +942,20 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
     std::vector<int> hi(nrhs), hb(nrhs);
     CHK(fetch(C, Sst.iter, nrhs * sizeof(int), hi.data(), st));
     CHK(fetch(C, Sst.breakdown, nrhs * sizeof(int), hb.data(), st));
-    const size_t bR1 = packed_bytes(PR, g, 1);
+    const size_t bX1 = packed_bytes(PX, g, 1);
     for (int r = 0; r < nrhs; ++r) {
       diverged[r] = 0;
       if (done[r]) continue;
       iters[r] += hi[r];
       if (hb[r] == 2) {  // a diverged pass contributes nothing; the next one restarts
         diverged[r] = 1;
-        HIPCHK(hipMemsetAsync((char*)xin + bR1 * r, 0, bR1, st));
+        HIPCHK(hipMemsetAsync((char*)xin + bX1 * r, 0, bX1, st));
       } else if (hb[r]) {
         status[r] = EOFA_ERR_BREAKDOWN;
         done[r] = 1;
       }
     }
-    launch_axpy_to64(PR, g, x, xin, nrhs, st);
+    launch_axpy_to64(PX, g, x, xin, nrhs, st);
   }
 
   std::vector<double> re, rodd;

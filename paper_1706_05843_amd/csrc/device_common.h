@@ -144,13 +144,14 @@ __device__ __forceinline__ void ld_spinor(const void* base, const FD& f, int r, 
 
 // Streaming (non-temporal) access for fields touched once per kernel (the
 // CG residual and solution): they bypass the cache ways that hold the
-// neighbour spinors the hop re-reads. FP16S fields go through the normal path.
+// neighbour spinors the hop re-reads.
 typedef float f4v_t __attribute__((ext_vector_type(4)));
 typedef double d2v_t __attribute__((ext_vector_type(2)));
+typedef unsigned u4v_t __attribute__((ext_vector_type(4)));
 
 template <int P, class R>
 __device__ __forceinline__ void ld_spinor_nt(const void* base, const FD& f, int r, int s, int i, cx<R>* v) {
-  const size_t e0 = eidx(f, r, 0, s, i), qs = qstride(f);
+  const size_t e0 = P == P16 ? qidx16(f, r, 0, s, i) : eidx(f, r, 0, s, i), qs = qstride(f);
   if constexpr (P == P32) {
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
@@ -167,15 +168,59 @@ __device__ __forceinline__ void ld_spinor_nt(const void* base, const FD& f, int 
       v[2 * q + 1] = {(R)t1.x, (R)t1.y};
     }
   } else {
-    ld_spinor<P>(base, f, r, s, i, v);
+    const R sc = (R)__builtin_nontemporal_load(scale_ptr(base, f) + sidx(f, r, s, i));
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const u4v_t q = __builtin_nontemporal_load((const u4v_t*)base + e0 + j * qs);
+      const unsigned w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const h2_t h = __builtin_bit_cast(h2_t, w[k]);
+        v[4 * j + k] = {sc * (R)(float)h.x, sc * (R)(float)h.y};
+      }
+    }
+  }
+}
+
+// FP16S site-spinor: the 12 components as half2 words in units of the
+// largest |component|, which is kept as the site's FP32 scale
+template <bool NT, class R>
+__device__ __forceinline__ void st_spinor16(void* base, const FD& f, int r, int s, int i, const cx<R>* v) {
+  float m = 0.f;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf((float)v[c].r), fabsf((float)v[c].i)));
+  const float inv = m > 0.f ? 1.0f / m : 0.f;
+  unsigned w[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    h2_t h;
+    h.x = (_Float16)((float)v[c].r * inv);
+    h.y = (_Float16)((float)v[c].i * inv);
+    w[c] = __builtin_bit_cast(unsigned int, h);
+  }
+  const size_t e0 = qidx16(f, r, 0, s, i), qs = qstride(f);
+  float* sp = (float*)scale_ptr(base, f) + sidx(f, r, s, i);
+  if constexpr (NT) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const u4v_t q = {w[4 * j], w[4 * j + 1], w[4 * j + 2], w[4 * j + 3]};
+      __builtin_nontemporal_store(q, (u4v_t*)base + e0 + j * qs);
+    }
+    __builtin_nontemporal_store(m, sp);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      ((uint4*)base)[e0 + j * qs] = make_uint4(w[4 * j], w[4 * j + 1], w[4 * j + 2], w[4 * j + 3]);
+    *sp = m;
   }
 }
 
 template <int P, class R>
-__device__ __forceinline__ void st_spinor(void* base, const FD& f, int r, int s, int i, const cx<R>* v);
-
-template <int P, class R>
 __device__ __forceinline__ void st_spinor_nt(void* base, const FD& f, int r, int s, int i, const cx<R>* v) {
+  if constexpr (P == P16) {
+    st_spinor16<true>(base, f, r, s, i, v);
+    return;
+  }
   const size_t e0 = eidx(f, r, 0, s, i), qs = qstride(f);
   if constexpr (P == P32) {
 #pragma unroll
@@ -191,32 +236,13 @@ __device__ __forceinline__ void st_spinor_nt(void* base, const FD& f, int r, int
       __builtin_nontemporal_store(t0, pp);
       __builtin_nontemporal_store(t1, pp + 1);
     }
-  } else {
-    st_spinor<P>(base, f, r, s, i, v);
   }
 }
 
 template <int P, class R>
 __device__ __forceinline__ void st_spinor(void* base, const FD& f, int r, int s, int i, const cx<R>* v) {
   if constexpr (P == P16) {
-    float m = 0.f;
-#pragma unroll
-    for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf((float)v[c].r), fabsf((float)v[c].i)));
-    const float inv = m > 0.f ? 1.0f / m : 0.f;
-    unsigned w[12];
-#pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      h2_t h;
-      h.x = (_Float16)((float)v[c].r * inv);
-      h.y = (_Float16)((float)v[c].i * inv);
-      w[c] = __builtin_bit_cast(unsigned int, h);
-    }
-    const size_t e0 = qidx16(f, r, 0, s, i), qs = qstride(f);
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-      ((uint4*)base)[e0 + j * qs] = make_uint4(w[4 * j], w[4 * j + 1], w[4 * j + 2], w[4 * j + 3]);
-    float* sp = (float*)scale_ptr(base, f);
-    sp[sidx(f, r, s, i)] = m;
+    st_spinor16<false>(base, f, r, s, i, v);
   } else {
     using RS = typename ST<P>::R;
     const size_t e0 = eidx(f, r, 0, s, i), qs = qstride(f);

@@ -83,7 +83,7 @@ enum HopRole {
   ROLE_K2,           // out = B y - Dhop D~ in, |out|^2
   ROLE_K3,           // out = A (g5 Dhop g5 in)
   ROLE_K4,           // r -= alpha (A g5Dhopg5 in + B y), |r|^2
-  ROLE_K4S,          // r  = A g5Dhopg5 in + B y, |r|^2   (r in accumulator precision)
+  ROLE_K4S,          // r  = A g5Dhopg5 in + B y, |r|^2   (r in the field precision)
   ROLE_SRC,          // out = z - Dhop D~ in
   ROLE_RES,          // out = z - (B y - Dhop D~ in), |out|^2
   ROLE_FULLRES,      // out = z - (B y + Dhop D~ in), |out|^2
@@ -104,7 +104,7 @@ struct HopArgs {
   void* out;          // packed, parity p, storage precision
   const void* y;      // packed, parity p (B y term)
   const void* z;      // packed, parity p (ADDZ)
-  void* r;            // packed, parity p, accumulator precision (K4/K4S)
+  void* r;            // packed, parity p, field precision (K4/K4S)
   const void* links;  // [Vh][8][9] complex for output parity p
   const int* nbr;     // [Vh][8] checkerboard index in parity 1-p
   const int* order;   // [Vh] traversal position -> checkerboard index (a permutation)
@@ -147,7 +147,8 @@ void launch_p_update(int ps, const Geometry& g, const void* r, const void* p, vo
                      const double* beta, const int* u2run, double* ahist, int nrhs, hipStream_t st);
 void launch_x_flush(int ps, const Geometry& g, void* x, const void* ring, size_t slot_bytes, int first, int nslots,
                     int R, const double* ahist, int nrhs, hipStream_t st);
-void launch_cg_update(int ps, int pr, const Geometry& g, void* x, const void* r, void* p, const double* alpha,
+// fused CG update: x in sol_prec(ps), the residual in ps (the inner precision)
+void launch_cg_update(int ps, const Geometry& g, void* x, const void* r, void* p, const double* alpha,
                       const double* beta, const int* u2run, int nrhs, hipStream_t st);
 void launch_finalize(int mode, const double* partial, int nblk, int nrhs, CgState st_, double* out,
                      hipStream_t st);

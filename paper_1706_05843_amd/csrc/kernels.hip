@@ -907,9 +907,12 @@ hop_kernel(HopArgs a) {
 
 #undef EOFA_SITE
 
+// precision of the CG residual a hop kernel updates: FP16S inner solves keep
+// it in FP16S too (reliable updates replace it long before its rounding
+// matters), so every field of the FP16S iteration is half width
 template <int P>
 constexpr int acc_prec() {
-  return P == P64 ? P64 : P32;
+  return P;
 }
 
 int hop_blocks(int prec, int Vh, int Ls, int W) {
@@ -1307,8 +1310,9 @@ __global__ void __launch_bounds__(256) norm2_kernel(int Ls, int Vh, int nrhs, co
   block_sum_store(n, partial + (size_t)r * gridDim.x + blockIdx.x);
 }
 
-// x += alpha p;  p = r + beta p   (CG, after the residual update)
-template <int PS, int PR>
+// x += alpha p;  p = r + beta p   (CG, after the residual update; x in PX,
+// the residual in PR)
+template <int PS, int PX, int PR>
 __global__ void __launch_bounds__(256) cg_update_kernel(int Ls, int Vh, int nrhs, void* x, const void* rr, void* p, const double* alpha,
                                  const double* beta, const int* u2run) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1316,12 +1320,12 @@ __global__ void __launch_bounds__(256) cg_update_kernel(int Ls, int Vh, int nrhs
   if (idx >= Ls * Vh || u2run[r] == 0) return;
   const int i = idx / Ls, s = idx - i * Ls;
   const FD f = {Ls, Vh, nrhs};
-  using RR = typename ST<PR>::R;
+  using RR = typename ST<PX>::R;
   using RS = typename ST<PS>::R;
   cx<RS> pv[12];
   cx<RR> xv[12], rv[12];
   ld_spinor<PS>(p, f, r, s, i, pv);  // p is re-read by the next hop's neighbours: cached
-  ld_spinor_nt<PR>(x, f, r, s, i, xv);
+  ld_spinor_nt<PX>(x, f, r, s, i, xv);
   ld_spinor_nt<PR>(rr, f, r, s, i, rv);
   const RR al = (RR)alpha[r], be = (RR)beta[r];
   cx<RS> pn[12];
@@ -1332,7 +1336,7 @@ __global__ void __launch_bounds__(256) cg_update_kernel(int Ls, int Vh, int nrhs
     xv[c].i = fma(al, pc.i, xv[c].i);
     pn[c] = {(RS)fma(be, pc.r, rv[c].r), (RS)fma(be, pc.i, rv[c].i)};
   }
-  st_spinor_nt<PR>(x, f, r, s, i, xv);
+  st_spinor_nt<PX>(x, f, r, s, i, xv);
   st_spinor<PS>(p, f, r, s, i, pn);
 }
 
@@ -1447,7 +1451,7 @@ void launch_p_update(int ps, const Geometry& g, const void* r, const void* p, vo
     hipLaunchKernelGGL((p_update_kernel<P32, P32>), EOFA_EW_GRID, g.Ls, g.Vh, nrhs, r, p, pn, alpha, beta, u2run,
                        ahist);
   else
-    hipLaunchKernelGGL((p_update_kernel<P16, P32>), EOFA_EW_GRID, g.Ls, g.Vh, nrhs, r, p, pn, alpha, beta, u2run,
+    hipLaunchKernelGGL((p_update_kernel<P16, P16>), EOFA_EW_GRID, g.Ls, g.Vh, nrhs, r, p, pn, alpha, beta, u2run,
                        ahist);
 }
 
@@ -1465,14 +1469,17 @@ void launch_x_flush(int ps, const Geometry& g, void* x, const void* ring, size_t
                        R, ahist);
 }
 
-void launch_cg_update(int ps, int pr, const Geometry& g, void* x, const void* r, void* p, const double* alpha,
+void launch_cg_update(int ps, const Geometry& g, void* x, const void* r, void* p, const double* alpha,
                       const double* beta, const int* u2run, int nrhs, hipStream_t st) {
   if (ps == P64)
-    hipLaunchKernelGGL((cg_update_kernel<P64, P64>), EOFA_EW_GRID, g.Ls, g.Vh, nrhs, x, r, p, alpha, beta, u2run);
+    hipLaunchKernelGGL((cg_update_kernel<P64, P64, P64>), EOFA_EW_GRID, g.Ls, g.Vh, nrhs, x, r, p, alpha, beta,
+                       u2run);
   else if (ps == P32)
-    hipLaunchKernelGGL((cg_update_kernel<P32, P32>), EOFA_EW_GRID, g.Ls, g.Vh, nrhs, x, r, p, alpha, beta, u2run);
+    hipLaunchKernelGGL((cg_update_kernel<P32, P32, P32>), EOFA_EW_GRID, g.Ls, g.Vh, nrhs, x, r, p, alpha, beta,
+                       u2run);
   else
-    hipLaunchKernelGGL((cg_update_kernel<P16, P32>), EOFA_EW_GRID, g.Ls, g.Vh, nrhs, x, r, p, alpha, beta, u2run);
+    hipLaunchKernelGGL((cg_update_kernel<P16, P32, P16>), EOFA_EW_GRID, g.Ls, g.Vh, nrhs, x, r, p, alpha, beta,
+                       u2run);
 }
 #undef EOFA_EW_GRID
 
