@@ -79,13 +79,13 @@ enum FinMode { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_NORM = 3 };
 enum HopRole {
   ROLE_DSLASH = 0,   // out = Dhop D~ in
   ROLE_DSLASH_DAG,   // out = D~^T g5 Dhop g5 in
-  ROLE_K1,           // out = A (Dhop D~ in)
-  ROLE_K2,           // out = B y - Dhop D~ in, |out|^2
+  ROLE_K1,           // out = D~ A (Dhop D~ in)   (A = M_ee^-1: K2 / RES then need no D~)
+  ROLE_K2,           // out = B y - Dhop in, |out|^2   (in = D~ t from K1)
   ROLE_K3,           // out = A (g5 Dhop g5 in)
   ROLE_K4,           // r -= alpha (A g5Dhopg5 in + B y), |r|^2
   ROLE_K4S,          // r  = A g5Dhopg5 in + B y, |r|^2   (r in the field precision)
   ROLE_SRC,          // out = z - Dhop D~ in
-  ROLE_RES,          // out = z - (B y - Dhop D~ in), |out|^2
+  ROLE_RES,          // out = z - (B y - Dhop in), |out|^2   (in = D~ t from K1)
   ROLE_FULLRES,      // out = z - (B y + Dhop D~ in), |out|^2
   // dense (non-Cayley) form, App. B.2: off-parity blocks Dhop, same-parity D_ee dense
   ROLE_D1,           // out = A (Dhop in)

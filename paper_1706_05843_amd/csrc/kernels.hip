@@ -33,12 +33,13 @@ namespace eofa {
 //   A_MAT   v = M h            (dense Ls x Ls per chirality, through LDS)
 //   A_DTT   v = D~^T h         A_NDTT v = -D~^T h   (structured: lane exchange)
 //   A_MATDT v = M D~^T h
-//   A_MINV  v = M_ee^-1 h      A_MINVDT v = M_ee^-T D~^T h   (matA must be
+//   A_DMINV v = D~ M_ee^-1 h   A_MINVDT v = M_ee^-T D~^T h   (matA must be
 //           M_ee^-1 / M_ee^-T: dense through LDS, or with Ls = 16 the
-//           structured inverse along the row, see minv_rows)
+//           structured inverse along the row, see minv_rows; D~ and D~^T by
+//           lane exchange)
 // plus the same-site term B y:
 //   B_MEE   + M_ee y           B_MEET + M_ee^T y    (structured: lane exchange)
-enum { A_ID = 0, A_NEG = 1, A_MAT = 2, A_DTT = 3, A_NDTT = 4, A_MATDT = 5, A_MINV = 6, A_MINVDT = 7 };
+enum { A_ID = 0, A_NEG = 1, A_MAT = 2, A_DTT = 3, A_NDTT = 4, A_MATDT = 5, A_DMINV = 6, A_MINVDT = 7 };
 enum { B_NONE = 0, B_MEE = 1, B_MEET = 2, B_DENSE = 3 };
 enum { O_STORE = 0, O_ADDZ = 1, O_RUPD = 2, O_STORE_R = 3 };
 
@@ -55,13 +56,13 @@ struct RoleT;
   };
 EOFA_ROLE(ROLE_DSLASH, false, true, A_ID, B_NONE, O_STORE, false)
 EOFA_ROLE(ROLE_DSLASH_DAG, true, false, A_DTT, B_NONE, O_STORE, false)
-EOFA_ROLE(ROLE_K1, false, true, A_MINV, B_NONE, O_STORE, false)
-EOFA_ROLE(ROLE_K2, false, true, A_NEG, B_MEE, O_STORE, true)
+EOFA_ROLE(ROLE_K1, false, true, A_DMINV, B_NONE, O_STORE, false)
+EOFA_ROLE(ROLE_K2, false, false, A_NEG, B_MEE, O_STORE, true)
 EOFA_ROLE(ROLE_K3, true, false, A_MINVDT, B_NONE, O_STORE, false)
 EOFA_ROLE(ROLE_K4, true, false, A_NDTT, B_MEET, O_RUPD, true)
 EOFA_ROLE(ROLE_K4S, true, false, A_NDTT, B_MEET, O_STORE_R, true)
 EOFA_ROLE(ROLE_SRC, false, true, A_ID, B_NONE, O_ADDZ, false)
-EOFA_ROLE(ROLE_RES, false, true, A_NEG, B_MEE, O_ADDZ, true)
+EOFA_ROLE(ROLE_RES, false, false, A_NEG, B_MEE, O_ADDZ, true)
 EOFA_ROLE(ROLE_FULLRES, false, true, A_ID, B_MEE, O_ADDZ, true)
 // dense (non-Cayley) form: off-parity blocks Dhop alone, same-parity blocks dense
 EOFA_ROLE(ROLE_D1, false, false, A_MAT, B_NONE, O_STORE, false)
@@ -705,9 +706,9 @@ hop_kernel(HopArgs a) {
   const FD fd = {Ls, Vh, a.nrhs};
 
   // the structured inverse (Ls = 16) needs no matrix in LDS
-  constexpr bool SINV = RL == 16 && (RT::AM == A_MINV || RT::AM == A_MINVDT);
+  constexpr bool SINV = RL == 16 && (RT::AM == A_DMINV || RT::AM == A_MINVDT);
   constexpr bool DENSE =
-      RT::AM == A_MAT || RT::AM == A_MATDT || (!SINV && (RT::AM == A_MINV || RT::AM == A_MINVDT));
+      RT::AM == A_MAT || RT::AM == A_MATDT || (!SINV && (RT::AM == A_DMINV || RT::AM == A_MINVDT));
   constexpr bool BDENSE = RT::BM == B_DENSE;  // never together with DENSE: one matrix in LDS
   unsigned char* p = smem;
   cx<R>* s_link = (cx<R>*)p;
@@ -775,7 +776,7 @@ hop_kernel(HopArgs a) {
     const R cpd = (R)a.cpd, cmd = (R)a.cmd;
 
     cx<R> v[12];
-    if constexpr (RT::AM == A_ID || RT::AM == A_MAT || RT::AM == A_MINV) {
+    if constexpr (RT::AM == A_ID || RT::AM == A_MAT || RT::AM == A_DMINV) {
 #pragma unroll
       for (int c = 0; c < 12; ++c) v[c] = acc[c];
     } else if constexpr (RT::AM == A_NEG) {
@@ -815,6 +816,12 @@ hop_kernel(HopArgs a) {
         __syncthreads();
         col_matvec<R>(s_mA, mycol, Ls, s, half, v, false);
       }
+    }
+    if constexpr (RT::AM == A_DMINV) {  // v <- D~ v = (c+d) v + (c-d) L v
+      cx<R> t[12];
+      lmul<R, false, RL>(v, t, nb);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) v[c] = {fma(cmd, t[c].r, cpd * v[c].r), fma(cmd, t[c].i, cpd * v[c].i)};
     }
     if constexpr (BDENSE && RL == 16) {  // v += M y along the row's diagonals
       cx<R> y[12];
@@ -931,9 +938,9 @@ size_t hop_lds_t(int Ls, int W) {
   using RT = RoleT<ROLE>;
   using L = HopLds<R>;
   const int SBk = W * sites_per_wave(Ls);
-  const bool sinv = use_rows<P>(Ls) && (RT::AM == A_MINV || RT::AM == A_MINVDT);
+  const bool sinv = use_rows<P>(Ls) && (RT::AM == A_DMINV || RT::AM == A_MINVDT);
   const bool DENSE = RT::AM == A_MAT || RT::AM == A_MATDT || RT::BM == B_DENSE ||
-                     (!sinv && (RT::AM == A_MINV || RT::AM == A_MINVDT));
+                     (!sinv && (RT::AM == A_DMINV || RT::AM == A_MINVDT));
   size_t lds = L::links(SBk) + L::nbr(SBk);
   if (DENSE) lds += L::mat(Ls);
   if ((DENSE || RT::BM == B_MEET) && !use_rows<P>(Ls)) lds += L::col(SBk, Ls);
@@ -1540,28 +1547,28 @@ __device__ void finalize_step(int mode, double sum, const CgState& S, int r, dou
   }
 }
 
-__global__ void finalize_kernel(int mode, const double* __restrict__ partial, int nblk, CgState S, double* out) {
+__global__ void __launch_bounds__(256) finalize_kernel(int mode, const double* __restrict__ partial, int nblk,
+                                                         CgState S, double* out) {
   const int r = blockIdx.x;
-  __shared__ double red[256];
+  __shared__ double red[4];
   // eight independent partial sums per thread, so the loads of one thread
   // are in flight together instead of one memory latency after another
   const double* pr = partial + (size_t)r * nblk;
   double t8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int j0 = threadIdx.x; j0 < nblk; j0 += 8 * blockDim.x) {
+  for (int j0 = threadIdx.x; j0 < nblk; j0 += 8 * 256) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      const int j = j0 + k * blockDim.x;
+      const int j = j0 + k * 256;
       if (j < nblk) t8[k] += pr[j];
     }
   }
   double t = ((t8[0] + t8[1]) + (t8[2] + t8[3])) + ((t8[4] + t8[5]) + (t8[6] + t8[7]));
-  red[threadIdx.x] = t;
+  // per wave by lane exchange, then the four wave sums
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
   __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) finalize_step(mode, red[0], S, r, out);
+  if (threadIdx.x == 0) finalize_step(mode, (red[0] + red[1]) + (red[2] + red[3]), S, r, out);
 }
 
 void launch_finalize(int mode, const double* partial, int nblk, int nrhs, CgState s, double* out, hipStream_t st) {
