@@ -36,7 +36,7 @@ WORKLOADS = {
     "c1": ((4, 4, 4, 4), 8, 0.3, 0.04, 1000, 2000),
     "c2": ((16, 16, 16, 32), 16, 0.5, 0.04, 1001, 2001),
 }
-ROLE_NAMES = ["K1 Mee^-1.Dhop.D~", "K2 Mee.p - Dhop.D~", "K3 Mee^-T.D~^T.Dhop^dag", "K4 r -= a(Mee^T.w - D~^T.Dhop^dag)"]
+ROLE_NAMES = ["K1 D~.Mee^-1.Dhop.D~", "K2 Mee.p - Dhop.(D~t)", "K3 Mee^-T.D~^T.Dhop^dag", "K4 r -= a(Mee^T.w - D~^T.Dhop^dag)"]
 PREC = {"fp64": 0, "fp32": 1, "fp16s": 2}
 
 
