@@ -5,7 +5,7 @@
   at sampled sites against the oracle's one-site evaluation;
 * 16^3 x 32 x Ls=16 (the mixed-precision workload): the FP16S/FP64 solve of
   the shifted system, its EOFA residual re-measured by the oracle at sampled
-  sites.
+  sites; its inner iteration count against plain FP64 CG.
 """
 import numpy as np
 import pytest
@@ -85,7 +85,8 @@ def test_c3_fp64_dslash_and_adjoint_sampled(c3):
             assert np.abs(got[:, x[3], x[2], x[1], x[0]] - ref).max() < 1e-13 * np.abs(ref).max()
 
 
-def test_c2_mixed_solve_residual_sampled():
+@pytest.fixture(scope="module")
+def c2():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     dims, Ls = (16, 16, 16, 32), 16
@@ -93,6 +94,13 @@ def test_c2_mixed_solve_residual_sampled():
     U = synth.gauge_field(dims, 0.5, seed=1001)
     phi = synth.fermion(dims, Ls, seed=2001, nrhs=1)
     ctx = eofa.Context(eofa.make_action(dims, Ls, M5, B5, C5), torch.from_numpy(U).cuda())
+    yield act, U, phi, ctx
+    ctx.close()
+
+
+def test_c2_mixed_solve_residual_sampled(c2):
+    act, U, phi, ctx = c2
+    dims = act.dims
     sysm = System(1.0, 0.04, 1.0, -1.0, +1)
     ph = torch.from_numpy(phi).cuda()
     psi = torch.zeros_like(ph)
@@ -107,3 +115,26 @@ def test_c2_mixed_solve_residual_sampled():
             den += np.vdot(phi[0][:, x[3], x[2], x[1], x[0]], phi[0][:, x[3], x[2], x[1], x[0]]).real
     # the sampled residual has the size of the global one (1e-10), with room for sampling spread
     assert np.sqrt(num / den) < 1e-9
+
+
+def test_c2_fp16s_iterations_track_fp64(c2):
+    """Every inner vector of an FP16S solve (p, t, w and the residual r) is
+    stored in FP16S. With reliable updates (a new FP64 residual every 10x of
+    reduction, the search direction kept) its inner CG needs about as many
+    iterations as plain FP64 CG on the same system; with restarts (direction
+    dropped every pass) at most a fifth more. Both reach the FP64 true
+    residual."""
+    act, U, phi, ctx = c2
+    sysm = System(1.0, 0.04, 1.0, -1.0, +1)
+    ph = torch.from_numpy(phi).cuda()
+    its = {}
+    for name, prm in [("fp64", eofa.make_params(tol=1e-10, inner_prec=eofa.FP64)),
+                      ("fp16s_keep", eofa.make_params(tol=1e-10, inner_prec=eofa.FP16S, keep_direction=1)),
+                      ("fp16s_restart", eofa.make_params(tol=1e-10, inner_prec=eofa.FP16S))]:
+        psi = torch.zeros_like(ph)
+        rc, st = ctx.eofa_cg_solve([sysm], ph, psi, prm)
+        assert rc == eofa.EOFA_OK and st[0]["converged"] == 1 and st[0]["true_resid"] <= 1e-10, name
+        its[name] = st[0]["iters"]
+    print("inner iterations", its, flush=True)
+    assert its["fp16s_keep"] <= 1.05 * its["fp64"]
+    assert its["fp16s_restart"] <= 1.2 * its["fp64"]
