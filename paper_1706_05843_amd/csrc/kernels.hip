@@ -33,10 +33,9 @@ namespace eofa {
 //   A_MAT   v = M h            (dense Ls x Ls per chirality, through LDS)
 //   A_DTT   v = D~^T h         A_NDTT v = -D~^T h   (structured: lane exchange)
 //   A_MATDT v = M D~^T h
-//   A_DMINV v = D~ M_ee^-1 h   A_MINVDT v = M_ee^-T D~^T h   (matA must be
-//           M_ee^-1 / M_ee^-T: dense through LDS, or with Ls = 16 the
-//           structured inverse along the row, see minv_rows; D~ and D~^T by
-//           lane exchange)
+//   A_DMINV v = D~ M_ee^-1 h   A_MINVDT v = M_ee^-T D~^T h   (the inverse
+//           structured along the column: minv_rows for Ls = 16, minv_cols
+//           otherwise; D~ and D~^T by lane exchange)
 // plus the same-site term B y:
 //   B_MEE   + M_ee y           B_MEET + M_ee^T y    (structured: lane exchange)
 enum { A_ID = 0, A_NEG = 1, A_MAT = 2, A_DTT = 3, A_NDTT = 4, A_MATDT = 5, A_DMINV = 6, A_MINVDT = 7 };
@@ -600,6 +599,93 @@ __device__ __forceinline__ void minv_rows(cx<R>* v, int s, int g, R bee, R cee, 
   }
 }
 
+// The same structured inverse for any Ls, by lane permutes within the
+// column (lanes g*Ls .. g*Ls+Ls-1). The geometric series of x = rho L is
+// summed as a product over the prime factors p_1 p_2 ... of Ls:
+//   sum_{k<Ls} x^k = prod_i (1 + x^{n_i} + ... + x^{(p_i - 1) n_i}),
+//   n_i = p_1 ... p_{i-1},
+// one pass of p_i - 1 shifted copies per factor (every shift below Ls; L^j
+// takes lane s - j, or s + j in the other direction, times -m across the
+// wrap). Ls = 12 = 2 2 3 takes 4 shifted copies per component instead of
+// the 12-term dense product. The rank-one term as in minv_rows; the
+// transposed form's sum over s' goes through the column's LDS slot.
+template <class R, bool TRANS>
+__device__ __forceinline__ void minv_cols(cx<R>* v, int s, int g, int Ls, R bee, R cee, R m, R sk, int chi, R a_s,
+                                          cx<R>* mycol, bool in_col) {
+  const R rho = cee / bee;
+  R rhoLs = R(1);
+  for (int k = 0; k < Ls; ++k) rhoLs *= rho;
+  const R scale = R(1) / (bee * (R(1) + m * rhoLs));
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    cx<R>* z = v + half * 6;
+    const int chir = half == 0 ? 1 : -1;
+    const bool shifted = sk != R(0) && chi == chir;  // uniform over the block
+    const int star_s = chir > 0 ? Ls - 1 : 0;
+    if constexpr (TRANS) {
+      if (shifted) {  // z_{s*} += sum_s a_s z_s
+        __syncthreads();
+        if (in_col)
+#pragma unroll
+          for (int c = 0; c < 6; ++c) mycol[s * 6 + c] = a_s * z[c];
+        __syncthreads();
+        if (in_col && s == star_s) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) {
+            cx<R> t = {R(0), R(0)};
+            for (int q = 0; q < Ls; ++q) t = t + mycol[q * 6 + c];
+            z[c] = z[c] + t;
+          }
+        }
+      }
+    }
+    // A^-1 uses L_chi (lane s takes s - j for L_+, s + j for L_-); A^-T the other
+    const bool up = (chir > 0) != TRANS;
+    int n = 1, rest = Ls;
+    R rn = rho;  // rho^n
+    while (rest > 1) {
+      int p = 2;
+      while (rest % p != 0) ++p;
+      cx<R> add[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) add[c] = {R(0), R(0)};
+      R rj = R(1);
+      for (int k = 1; k < p; ++k) {
+        const int j = k * n;
+        rj *= rn;
+        const int t = up ? s - j : s + j;
+        const bool wrap = up ? t < 0 : t >= Ls;
+        const int src = g * Ls + (wrap ? (up ? t + Ls : t - Ls) : t);
+        const R f = wrap ? -m * rj : rj;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          const cx<R> w = {__shfl(z[c].r, src, 64), __shfl(z[c].i, src, 64)};
+          add[c].r = fma(f, w.r, add[c].r);
+          add[c].i = fma(f, w.i, add[c].i);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 6; ++c) z[c] = z[c] + add[c];
+      rn *= rj;  // rho^(n p) = rho^n rho^((p - 1) n)
+      n *= p;
+      rest /= p;
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) z[c] = scale * z[c];
+    if constexpr (!TRANS) {
+      if (shifted) {  // z += a z_{s*}
+        const int star = g * Ls + star_s;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          const cx<R> zs = {__shfl(z[c].r, star, 64), __shfl(z[c].i, star, 64)};
+          z[c].r = fma(a_s, zs.r, z[c].r);
+          z[c].i = fma(a_s, zs.i, z[c].i);
+        }
+      }
+    }
+  }
+}
+
 // Rank-one part of the shifted same-parity block on the chirality half H0
 // (0: P_+, 6: P_-), with s* the special fifth-dimension index:
 //   TRANS = false:  v_s += sk u_s y_{s*}              (sk u e_{s*}^T y)
@@ -630,7 +716,7 @@ __device__ __forceinline__ void rank_one(const cx<R>* y, cx<R>* v, R sk, R us, i
 #pragma unroll
       for (int c = 0; c < 6; ++c) mycol[s * 6 + c] = us * y[H0 + c];
     __syncthreads();
-    if (is_star) {
+    if (in_col && is_star) {  // idle lanes past the last column read no slot
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
         cx<R> sum = {R(0), R(0)};
@@ -705,10 +791,9 @@ hop_kernel(HopArgs a) {
   const volatile int* s_self = nullptr;
   const FD fd = {Ls, Vh, a.nrhs};
 
-  // the structured inverse (Ls = 16) needs no matrix in LDS
-  constexpr bool SINV = RL == 16 && (RT::AM == A_DMINV || RT::AM == A_MINVDT);
-  constexpr bool DENSE =
-      RT::AM == A_MAT || RT::AM == A_MATDT || (!SINV && (RT::AM == A_DMINV || RT::AM == A_MINVDT));
+  // the structured inverse (any Ls) needs no matrix in LDS
+  constexpr bool SINV = RT::AM == A_DMINV || RT::AM == A_MINVDT;
+  constexpr bool DENSE = RT::AM == A_MAT || RT::AM == A_MATDT;
   constexpr bool BDENSE = RT::BM == B_DENSE;  // never together with DENSE: one matrix in LDS
   unsigned char* p = smem;
   cx<R>* s_link = (cx<R>*)p;
@@ -792,10 +877,14 @@ hop_kernel(HopArgs a) {
         v[c] = sgn * d;
       }
     }
-    if constexpr (SINV) {  // v <- M_ee^-1 v or M_ee^-T v, structured along the row
+    if constexpr (SINV) {  // v <- M_ee^-1 v or M_ee^-T v, structured along the column
       const double* scs = a.scoef + (size_t)r * (SCOEF_HEAD + 2 * Ls);
       const R a_s = (R)scs[SCOEF_HEAD + Ls + s];
-      minv_rows<R, RT::AM == A_MINVDT>(v, s, g, (R)a.bee, (R)a.cee, (R)a.mop[r], (R)scs[1], (int)scs[2], a_s);
+      if constexpr (RL == 16)
+        minv_rows<R, RT::AM == A_MINVDT>(v, s, g, (R)a.bee, (R)a.cee, (R)a.mop[r], (R)scs[1], (int)scs[2], a_s);
+      else
+        minv_cols<R, RT::AM == A_MINVDT>(v, s, g, Ls, (R)a.bee, (R)a.cee, (R)a.mop[r], (R)scs[1], (int)scs[2],
+                                          a_s, s_col + ls * cstr, in_col);
 #pragma unroll
       for (int c = 0; c < 12; ++c) asm volatile("" : "+v"(v[c].r), "+v"(v[c].i));
     } else if constexpr (DENSE && RL == 16) {  // v <- M v along the row's diagonals
@@ -938,12 +1027,12 @@ size_t hop_lds_t(int Ls, int W) {
   using RT = RoleT<ROLE>;
   using L = HopLds<R>;
   const int SBk = W * sites_per_wave(Ls);
-  const bool sinv = use_rows<P>(Ls) && (RT::AM == A_DMINV || RT::AM == A_MINVDT);
-  const bool DENSE = RT::AM == A_MAT || RT::AM == A_MATDT || RT::BM == B_DENSE ||
-                     (!sinv && (RT::AM == A_DMINV || RT::AM == A_MINVDT));
+  const bool DENSE = RT::AM == A_MAT || RT::AM == A_MATDT || RT::BM == B_DENSE;
   size_t lds = L::links(SBk) + L::nbr(SBk);
   if (DENSE) lds += L::mat(Ls);
-  if ((DENSE || RT::BM == B_MEET) && !use_rows<P>(Ls)) lds += L::col(SBk, Ls);
+  // column slots: dense products, and the transposed rank-one sums (B_MEET,
+  // the structured M_ee^-T) when the column is not a DPP row
+  if ((DENSE || RT::BM == B_MEET || RT::AM == A_MINVDT) && !use_rows<P>(Ls)) lds += L::col(SBk, Ls);
   return lds;
 }
 

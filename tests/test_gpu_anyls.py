@@ -1,0 +1,83 @@
+"""The structured same-parity inverse at fifth-dimension extents that are not
+a power of two (App. B.2: M_ee^-1 from the bidiagonal-plus-corner block and
+the Sherman-Morrison term). For Ls != 16 the hop kernels sum the geometric
+series of rho L as a product over the prime factors of Ls by lane permutes
+within the column; Ls = 6 (2 3), 10 (2 5: a pass of four shifted copies) and
+12 (2 2 3, the batched workload's extent) cover the factor patterns (Ls is
+even, as App. A assumes).
+
+* FP64 fixed-iteration solves (K1..K4, the FP64 residual) against the
+  oracle's mirror-mode CGNR of the same systems: 1e-12 relative, for the
+  unshifted system and the shifted systems of both chiralities (the rank-one
+  term in both the inverse and its transpose);
+* FP32 and FP16S solves reach the FP64 true residual 1e-10, re-measured by
+  the oracle on the H form.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import eo
+from oracle.dwf import Action, System, H_system
+from oracle.lattice import norm2
+from paper_1706_05843_amd import eofa, synth
+
+pytestmark = pytest.mark.gpu
+
+M5, B5, C5 = 1.8, 1.5, 0.5
+M1, M2 = 0.04, 1.0
+SYSTEMS = {
+    "chi1": System(M1, M1, M2, 0.0, -1),
+    "chi2": System(M2, M1, M2, -1.0, +1),
+    "lh": System(M1, M1, M2, -0.5, -1),
+}
+DIMS = (4, 2, 2, 4)
+ITERS = 30
+
+_CTX = {}
+
+
+def setup(Ls):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    if Ls not in _CTX:
+        act = Action(DIMS, Ls, M5, B5, C5, (1, 1, 1, -1))
+        U = synth.gauge_field(DIMS, 0.3, seed=300 + Ls)
+        phi = synth.fermion(DIMS, Ls, seed=400 + Ls)
+        ctx = eofa.Context(eofa.make_action(DIMS, Ls, M5, B5, C5), torch.from_numpy(U).cuda())
+        _CTX[Ls] = (act, U, phi, ctx)
+    return _CTX[Ls]
+
+
+def rel2(a, b):
+    return np.sqrt(norm2(a - b) / norm2(b))
+
+
+@pytest.mark.parametrize("name", list(SYSTEMS))
+@pytest.mark.parametrize("Ls", [6, 10, 12])
+def test_mirror_mode_fp64(Ls, name):
+    act, U, phi, ctx = setup(Ls)
+    ref = eo.solve_mirror(act, U, SYSTEMS[name], phi, iters=ITERS)["psi"]
+    psi = torch.zeros(ctx.full_shape(1), dtype=torch.complex128, device="cuda")
+    rc, st = ctx.eofa_cg_solve([SYSTEMS[name]], torch.from_numpy(phi[None]).cuda(), psi,
+                               eofa.make_params(fixed_iters=ITERS))
+    assert st[0]["iters"] == ITERS
+    got = psi.cpu().numpy()[0]
+    assert rel2(got, ref) < 1e-12
+
+
+@pytest.mark.parametrize("prec", [eofa.FP32, eofa.FP16S])
+@pytest.mark.parametrize("Ls", [6, 10, 12])
+def test_converged(Ls, prec):
+    act, U, phi, ctx = setup(Ls)
+    names = list(SYSTEMS)
+    ph = torch.from_numpy(np.stack([phi] * len(names))).cuda()
+    psi = torch.zeros_like(ph)
+    rc, st = ctx.eofa_cg_solve([SYSTEMS[n] for n in names], ph, psi, eofa.make_params(tol=1e-10, inner_prec=prec))
+    assert rc == eofa.EOFA_OK, st
+    got = psi.cpu().numpy()
+    for r, n in enumerate(names):
+        assert st[r]["converged"] == 1 and st[r]["true_resid"] <= 1e-10, (n, st[r])
+        res = np.sqrt(norm2(H_system(act, U, SYSTEMS[n], got[r]) - phi) / norm2(phi))
+        assert res <= 1.05e-10, (n, res)
