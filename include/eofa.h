@@ -210,8 +210,11 @@ int eofa_mooee_inv(eofa_ctx* ctx, const eofa_system* sys, const void* in, void* 
  * (device, complex128, canonical layout; psi is output only unless
  * params->use_guess = 1, then it is also the initial guess). Inner CG in
  * params->inner_prec with an FP64 defect-correction outer loop (Sec. VI A);
- * all right-hand sides iterate together in batched kernels, each with its
- * own CG scalars. stats: host array [nrhs] (may be NULL).                */
+ * every inner CG vector (search direction, residual, operator
+ * intermediates) is stored in the inner precision, the inner solution
+ * increment in FP32 (FP64 for an FP64 inner solve); all right-hand sides
+ * iterate together in batched kernels, each with its own CG scalars.
+ * stats: host array [nrhs] (may be NULL).                                */
 int eofa_cg_solve(eofa_ctx* ctx, const eofa_system* sys, const void* phi, void* psi, int32_t nrhs,
                   const eofa_solver_params* params, eofa_solver_stats* stats, void* stream);
 
