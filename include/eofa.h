@@ -150,7 +150,13 @@ typedef struct {
                           less than 2x, followed by a restart); 0 = each pass restarts the
                           inner CG from p = r (plain defect correction). Pays on
                           well-conditioned systems, costs iterations on ill-conditioned ones */
-  int32_t pad2;
+  int32_t ring_slots;  /* CGNR: search directions kept for the batched solution update
+                          (x += sum of alpha_j p_j every ring_slots / 2 iterations instead of
+                          x += alpha p every iteration; not in the paper, memory traffic
+                          only): 0 = the most of 16, 8, 4 that divide check_every (16 if 0)
+                          and fit a quarter of the free device memory, else the
+                          per-iteration update; 16, 8 or 4 = that many (must divide it);
+                          -1 = the per-iteration update                                    */
 } eofa_solver_params;
 
 typedef struct {

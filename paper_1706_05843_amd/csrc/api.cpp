@@ -465,15 +465,16 @@ const Form kDense = {ROLE_D1, ROLE_D2, ROLE_D3, ROLE_D4, ROLE_D4S, ROLE_DSRC, RO
                      MAT_DEE_INV, MAT_DEE, false};
 
 // Ring of search directions for the batched solution update: iteration k
-// reads p_k from slot k mod R and writes p_{k+1} to the next slot; every F
-// iterations x += sum alpha_j p_j over the last F slots (one pass over x per
-// F iterations instead of one per iteration). R = 16 matches the host poll
-// and graph period, so slot indices repeat identically in every replay.
+// reads p_k from slot k mod R and writes p_{k+1} to the next slot; every
+// F = R / 2 iterations x += sum alpha_j p_j over the last F slots (one pass
+// over x per F iterations instead of one per iteration). R (16, 8 or 4)
+// divides the host poll and graph period, so slot indices repeat
+// identically in every replay.
 struct Ring {
   char* base = nullptr;
   size_t slot = 0;           // bytes per slot (all right-hand sides)
   double* ahist = nullptr;   // [R][nrhs] alpha of each step, 0 if it did not run
-  static constexpr int R = 16, F = 8;
+  int R = 16, F = 8;
   void* at(int k) const { return base + (size_t)(k % R) * slot; }
 };
 
@@ -500,9 +501,9 @@ int inner_iteration(eofa_ctx* C, const Form& F, int S, const HopArgs& k1, const 
   launch_finalize(FIN_BETA, partial, nbh, nrhs, Sst, nullptr, st);
   if (ring) {
     launch_p_update(S, g, rin, ring->at(k), ring->at(k + 1), Sst.alpha, Sst.beta, Sst.u2run,
-                    ring->ahist + (size_t)(k % Ring::R) * nrhs, nrhs, st);
-    if ((k + 1) % Ring::F == 0)
-      launch_x_flush(S, g, xin, ring->base, ring->slot, (k + 1 - Ring::F) % Ring::R, Ring::F, Ring::R, ring->ahist,
+                    ring->ahist + (size_t)(k % ring->R) * nrhs, nrhs, st);
+    if ((k + 1) % ring->F == 0)
+      launch_x_flush(S, g, xin, ring->base, ring->slot, (k + 1 - ring->F) % ring->R, ring->F, ring->R, ring->ahist,
                      nrhs, st);
   } else {
     launch_cg_update(S, g, xin, rin, pS, Sst.alpha, Sst.beta, Sst.u2run, nrhs, st);
@@ -668,21 +669,31 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
   double* partial = (double*)partial_v;
   CgState Sst;
   CHK(alloc_state(C, nrhs, Sst));
-  // direction ring (batched x update) when its R slots fit a modest budget
-  // and the poll period is a multiple of R; else the fused per-step update
+  // direction ring (batched x update): ring_slots slots if given, else the
+  // most slots R in {16, 8, 4} that divide the poll period and fit a quarter
+  // of the device memory not otherwise in use (the ring this context already
+  // holds counts as free); else (or ring_slots = -1) the fused per-step update
   Ring ring_store;
   const Ring* ring = nullptr;
   int last_it = 0;  // iterations of the previous pass (its last direction sits in slot last_it mod R)
-  {
-    const size_t ring_bytes = (size_t)Ring::R * bS;
-    if (check % Ring::R == 0 && ring_bytes <= (size_t)8 << 30) {
+  if (prm->ring_slots >= 0) {
+    size_t free_b = 0, total_b = 0;
+    HIPCHK(hipMemGetInfo(&free_b, &total_b));
+    const auto held = C->pool.find("pring");
+    const size_t avail = (free_b + (held != C->pool.end() ? held->second.n : 0)) / 4;
+    for (int R : {16, 8, 4}) {
+      const size_t ring_bytes = (size_t)R * bS;
+      if (prm->ring_slots > 0 ? R != prm->ring_slots : (check % R != 0 || ring_bytes > avail)) continue;
       void *rb, *ah;
       CHK(ws(C, "pring", ring_bytes, &rb));
-      CHK(ws(C, "ahist", sizeof(double) * Ring::R * nrhs, &ah));
+      CHK(ws(C, "ahist", sizeof(double) * R * nrhs, &ah));
       ring_store.base = (char*)rb;
       ring_store.slot = bS;
       ring_store.ahist = (double*)ah;
+      ring_store.R = R;
+      ring_store.F = R / 2;
       ring = &ring_store;
+      break;
     }
   }
 
@@ -859,7 +870,7 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
     void* p0 = ring ? ring->at(0) : pS;
     if (restart) {
       launch_convert(S, S, g, rin, p0, nrhs, st);
-    } else if (ring && last_it % Ring::R != 0) {  // the kept direction into slot 0
+    } else if (ring && last_it % ring->R != 0) {  // the kept direction into slot 0
       HIPCHK(hipMemcpyAsync(p0, ring->at(last_it), bS, hipMemcpyDeviceToDevice, st));
     }
     launch_zero(PX, g, xin, nrhs, st);
@@ -933,9 +944,9 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
         }
       }
     }
-    if (ring && it % Ring::F != 0) {  // the steps since the last batched x update
-      const int rem = it % Ring::F;
-      launch_x_flush(S, g, xin, ring->base, ring->slot, (it - rem) % Ring::R, rem, Ring::R, ring->ahist, nrhs, st);
+    if (ring && it % ring->F != 0) {  // the steps since the last batched x update
+      const int rem = it % ring->F;
+      launch_x_flush(S, g, xin, ring->base, ring->slot, (it - rem) % ring->R, rem, ring->R, ring->ahist, nrhs, st);
     }
     last_it = it;
     HIPCHK(hipGetLastError());
@@ -1006,6 +1017,10 @@ int check_params(const eofa_solver_params* prm) {
   if (prm->form != 0 && prm->form != 1) return fail(EOFA_ERR_INVALID, "form must be 0 or 1");
   if (prm->form == 1 && prm->precond != 0)
     return fail(EOFA_ERR_INVALID, "the dense form (form = 1) is solved by CGNR only (precond = 0)");
+  const int rs = prm->ring_slots, chk = prm->check_every > 0 ? prm->check_every : 16;
+  if (rs != -1 && rs != 0 && rs != 4 && rs != 8 && rs != 16)
+    return fail(EOFA_ERR_INVALID, "ring_slots must be -1, 0, 4, 8 or 16");
+  if (rs > 0 && chk % rs != 0) return fail(EOFA_ERR_INVALID, "ring_slots must divide check_every");
   return EOFA_OK;
 }
 

@@ -43,7 +43,7 @@ class SolverParams(ctypes.Structure):
                 ("profile", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("rhs_block", ctypes.c_int32),
                 ("waves", ctypes.c_int32), ("precond", ctypes.c_int32), ("fcg_window", ctypes.c_int32),
                 ("net", ctypes.c_void_p), ("use_guess", ctypes.c_int32), ("form", ctypes.c_int32),
-                ("keep_direction", ctypes.c_int32), ("pad2", ctypes.c_int32)]
+                ("keep_direction", ctypes.c_int32), ("ring_slots", ctypes.c_int32)]
 
 
 class SolverStats(ctypes.Structure):
@@ -148,7 +148,7 @@ def make_systems(systems):
 
 def make_params(tol=1e-10, max_iter=100000, max_outer=20, inner_prec=FP64, inner_tol=0.0,
                 fixed_iters=0, check_every=16, profile=0, use_graph=0, rhs_block=0, waves=0,
-                precond=0, net=None, fcg_window=0, use_guess=0, form=0, keep_direction=0):
+                precond=0, net=None, fcg_window=0, use_guess=0, form=0, keep_direction=0, ring_slots=0):
     """Solver parameters; ``net`` (a Net, or None for the identity) is used when precond = 1;
     ``form`` 0 is the Cayley form, 1 the dense comparison form."""
     p = SolverParams()
@@ -156,7 +156,7 @@ def make_params(tol=1e-10, max_iter=100000, max_outer=20, inner_prec=FP64, inner
     p.inner_tol, p.fixed_iters, p.check_every, p.profile = inner_tol, fixed_iters, check_every, profile
     p.use_graph, p.rhs_block, p.waves = use_graph, rhs_block, waves
     p.precond, p.fcg_window, p.use_guess, p.form = precond, fcg_window, use_guess, form
-    p.keep_direction = keep_direction
+    p.keep_direction, p.ring_slots = keep_direction, ring_slots
     p.net = net._h.value if net is not None else None
     p._net_ref = net  # keeps the network alive as long as the parameters
     return p

@@ -46,7 +46,7 @@ int main(void) {
   printf("%zu %zu %zu %zu\n", sizeof(eofa_action), sizeof(eofa_system), sizeof(eofa_solver_params), sizeof(eofa_solver_stats));
   printf("%zu %zu %zu %zu %zu\n", offsetof(eofa_action, M5), offsetof(eofa_action, bc), offsetof(eofa_solver_params, inner_tol), offsetof(eofa_solver_stats, hop_ms), offsetof(eofa_solver_params, waves));
   printf("%zu %zu %zu\n", offsetof(eofa_solver_params, precond), offsetof(eofa_solver_params, net), offsetof(eofa_solver_stats, fell_back));
-  printf("%zu %zu %zu\n", offsetof(eofa_solver_params, use_guess), offsetof(eofa_solver_params, form), offsetof(eofa_solver_params, keep_direction));
+  printf("%zu %zu %zu %zu\n", offsetof(eofa_solver_params, use_guess), offsetof(eofa_solver_params, form), offsetof(eofa_solver_params, keep_direction), offsetof(eofa_solver_params, ring_slots));
   return 0;
 }
 '''
@@ -64,7 +64,7 @@ int main(void) {
                          eofa.SolverParams.waves.offset, eofa.SolverParams.precond.offset,
                          eofa.SolverParams.net.offset, eofa.SolverStats.fell_back.offset,
                          eofa.SolverParams.use_guess.offset, eofa.SolverParams.form.offset,
-                         eofa.SolverParams.keep_direction.offset]
+                         eofa.SolverParams.keep_direction.offset, eofa.SolverParams.ring_slots.offset]
 
 
 @pytest.mark.parametrize("bad", [
@@ -152,7 +152,8 @@ def test_pairs_and_solver_params_validation():
     rc = eofa.lib().eofa_cg_solve(dummy, sysl, dummy, ctypes.c_void_p(32), 1, ctypes.byref(prm), None, None)
     assert rc == eofa.EOFA_ERR_INVALID
 
-    for kw in (dict(form=2), dict(form=1, precond=1)):
+    for kw in (dict(form=2), dict(form=1, precond=1), dict(ring_slots=3), dict(ring_slots=32),
+               dict(ring_slots=-2), dict(ring_slots=16, check_every=8)):
         prm = eofa.make_params(**kw)
         rc = eofa.lib().eofa_cg_solve(dummy, sysl, dummy, ctypes.c_void_p(32), 1, ctypes.byref(prm), None, None)
         assert rc == eofa.EOFA_ERR_INVALID, kw

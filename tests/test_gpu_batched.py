@@ -6,7 +6,11 @@
 * the hop kernels' launch shape (waves and right-hand sides per work-group)
   changes only the order of the partial sums: results agree to 1e-13;
 * a batch of systems with their own (m_op, beta, chi) equals the single
-  solves (1e-14), also in mixed precision.
+  solves (1e-14), also in mixed precision;
+* the batched solution update (a ring of R = 4, 8 or 16 search directions,
+  x updated every R/2 iterations) equals the per-iteration update: the CG
+  iterates are the same, x sums the same increments in another grouping
+  (1e-13 FP64; FP32 solution storage below FP64: 1e-6).
 """
 import numpy as np
 import pytest
@@ -78,3 +82,15 @@ def test_batch_equals_single(setup, prec):
     for r in range(len(SYS)):
         one = solve(ctx, [SYS[r]], phis[r:r + 1], **kw)[2][0]
         assert rel2(batch[r], one) < 1e-14
+
+
+@pytest.mark.parametrize("prec", [eofa.FP64, eofa.FP16S])
+def test_ring_sizes_agree(setup, prec):
+    act, U, phis, ctx = setup
+    kw = dict(fixed_iters=37, inner_prec=prec)  # 37: a partial flush at the end
+    ref = solve(ctx, SYS, phis, ring_slots=-1, **kw)[2]
+    for R in (4, 8, 16):
+        rc, st, got = solve(ctx, SYS, phis, ring_slots=R, **kw)
+        assert rc in (eofa.EOFA_OK, eofa.EOFA_ERR_NOT_CONVERGED) and st[0]["iters"] == 37
+        d = rel2(got, ref)
+        assert d < (1e-13 if prec == eofa.FP64 else 1e-6), (R, d)
