@@ -944,10 +944,10 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
       HIPCHK(hipStreamWaitEvent(st, join, 0));
       HIPCHK(hipEventDestroy(join));
     } else {
-      if (!C->side_stream) {
-        HIPCHK(hipStreamCreateWithFlags(&C->side_stream, hipStreamNonBlocking));
-        for (auto& e : C->side_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-      }
+      // created once per context; a partial failure is completed on the next call
+      if (!C->side_stream) HIPCHK(hipStreamCreateWithFlags(&C->side_stream, hipStreamNonBlocking));
+      for (auto& e : C->side_ev)
+        if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
       while (true) {
         // timed iterations sit between host polls (which drain the queue), so the
         // events bracket the kernels and not host launch latency
