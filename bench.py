@@ -13,10 +13,15 @@ and reported as restarted_defect_correction). A step is one complete solve
 unpack), inputs resident in HBM.
 
 Output: one JSON line. ``value`` is the whole-job Dslash throughput: the
-algorithmic bytes of every inner-solve hop kernel divided by the wall time of
-the timed steps. ``roofline`` is the dominant hop kernel alone (HIP events on
-the solve's stream, every 8th iteration). ``cpu_baseline`` times the CPU
-oracle's off-parity operator on the same lattice.
+hop's compulsory bytes (input and output spinor once, links once) of every
+inner-solve hop launch divided by the wall time of the timed steps.
+``roofline`` is the dominant hop kernel alone on the same bytes (HIP events on
+the solve's stream, every 8th iteration), with the fused bytes of its
+epilogue and every role's figures beside it. ``dslash_beyond_mall`` times the
+single-RHS Dslash on 24^3 x 64 x Ls=12, whose fields exceed the 256 MB MALL.
+``cpu_baseline`` times the CPU oracle (plain numpy FP64) on this host: its
+off-parity operator on the same lattice, and its solve of the same system on
+4^4 x Ls=8 to 1e-10 (the GPU's time on that solve is gpu_c1_time_to_solution).
 """
 import argparse
 import hashlib
@@ -51,12 +56,38 @@ def link_bytes_per_site(prec):
 
 
 def role_bytes(role, prec, Ls, Nh):
-    """Algorithmic (compulsory) bytes of one launch of an inner hop kernel:
-    every input field read once, every output written once, every link once."""
+    """Fused compulsory bytes of one launch of an inner hop kernel: every field
+    it touches read once (K2 also reads the same-site p, K4 also reads w and
+    reads and writes the residual), every output written once, every link once."""
     E = site_bytes(prec)  # the inner residual is kept in the inner precision too
     lk = link_bytes_per_site(prec) / Ls
     per = {0: 2 * E, 1: 3 * E, 2: 2 * E, 3: 4 * E}[role] + lk
     return per * Nh
+
+
+def hop_bytes(prec, Ls, Nh):
+    """Compulsory bytes of the hop itself, Dhop.D~ on one half-field: the input
+    spinor read once, the output written once, the links once per launch
+    (FP16S at Ls = 16: 52 + 52 + 288/16 = 122 B per 5D site)."""
+    return (2 * site_bytes(prec) + link_bytes_per_site(prec) / Ls) * Nh
+
+
+def cpu_info():
+    """Host core count and CPU model of the machine the oracle runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return dict(nproc=os.cpu_count(), usable_cores=usable, cpu_model=model)
 
 
 def kernel_source_hash():
@@ -78,26 +109,103 @@ def traffic_from_profile(workload, prec_name, role):
     return d.get("bytes_per_launch", {}).get(str(role))
 
 
+def _timed(fn):
+    """(result, wall seconds, threads used = process CPU time / wall time)."""
+    w0, c0 = time.perf_counter(), time.process_time()
+    out = fn()
+    w, c = time.perf_counter() - w0, time.process_time() - c0
+    return out, w, max(1, int(round(c / max(w, 1e-9))))
+
+
 def cpu_baseline(dims, Ls, eps, m1, gseed, sseed):
-    """The oracle's off-parity operator Dhop D~(m) (FP64, numpy) on the same lattice."""
+    """The CPU oracle as it stands (plain numpy FP64), on this host:
+    (1) its off-parity operator Dhop.D~(m) once on the same lattice as the GPU
+    step, in the GPU roofline's bytes (the value); (2) its whole solve route
+    (mirror mode: Schur source, CGNR, reconstruction) of the same shifted
+    system to a 1e-10 residual on the small 4^4 x Ls=8 workload."""
     import numpy as np
-    from oracle.dwf import Action, Dtilde_op
+    from oracle import eo
+    from oracle.dwf import Action, Dtilde_op, System
     from oracle.lattice import hop, restrict
     from paper_1706_05843_amd import synth
+    info = cpu_info()
     act = Action(dims, Ls, 1.8, 1.5, 0.5, (1, 1, 1, -1))
     U = synth.gauge_field(dims, eps, gseed)
     psi = synth.fermion(dims, Ls, sseed)
     x = restrict(psi, dims, 1)
-    t0 = time.perf_counter()
-    y = restrict(hop(U, Dtilde_op(act, 1.0, x), act.bc), dims, 0)
-    dt = time.perf_counter() - t0
+    y, dt, threads = _timed(lambda: restrict(hop(U, Dtilde_op(act, 1.0, x), act.bc), dims, 0))
     del y
     Vh = int(np.prod(dims)) // 2
-    byts = (2 * 192 + link_bytes_per_site(0) / Ls) * Vh * Ls
-    return dict(value=byts / dt / 1e9, unit="GB/s", cores=1, kind="oracle",
+    byts = hop_bytes(0, Ls, Vh * Ls)
+    d1, l1, e1, ms1, gs1, ss1 = WORKLOADS["c1"]
+    act1 = Action(d1, l1, 1.8, 1.5, 0.5, (1, 1, 1, -1))
+    U1, phi1 = synth.gauge_field(d1, e1, gs1), synth.fermion(d1, l1, ss1)
+    out, t1, th1 = _timed(lambda: eo.solve_mirror(act1, U1, System(1.0, ms1, 1.0, -1.0, +1), phi1, tol=1e-10))
+    return dict(value=byts / dt / 1e9, unit="GB/s", cores=threads, kind="oracle",
                 sample=f"one application of the oracle's FP64 off-parity operator Dhop.D~ on the full "
-                       f"{dims[0]}x{dims[1]}x{dims[2]}x{dims[3]} x Ls={Ls} lattice ({dt:.2f} s, numpy, one thread); "
-                       f"bytes counted with the same compulsory-traffic model as the GPU kernel")
+                       f"{dims[0]}x{dims[1]}x{dims[2]}x{dims[3]} x Ls={Ls} lattice ({dt:.2f} s), bytes counted "
+                       f"like the GPU roofline (input and output spinor once, links once); plus the oracle's "
+                       f"solve of H(m2)-Delta_+(m1,m2)P_+ to a 1e-10 residual on 4^4 x Ls=8",
+                nproc=info["nproc"], usable_cores=info["usable_cores"], cpu_model=info["cpu_model"],
+                time_to_solution_c1=dict(seconds=round(t1, 3), iters=out["iters"], true_resid=out["true_resid"],
+                                         cores=th1, workload="4x4x4x4 Ls=8 eps=0.3 m1=0.04 m2=1.0, "
+                                         "H(m2)-Delta_+(m1,m2)P_+, CGNR to 1e-10 (mirror mode)"))
+
+
+def gpu_c1(eofa, synth, torch):
+    """The same 4^4 x Ls=8 solve as the CPU oracle's time-to-solution, on the GPU."""
+    d1, l1, e1, ms1, gs1, ss1 = WORKLOADS["c1"]
+    U = torch.from_numpy(synth.gauge_field(d1, e1, gs1)).cuda()
+    phi = torch.from_numpy(synth.fermion(d1, l1, ss1, nrhs=1)).cuda()
+    psi = torch.zeros_like(phi)
+    ctx = eofa.Context(eofa.make_action(d1, l1, 1.8, 1.5, 0.5), U)
+    res = {}
+    for name, prec in (("fp64", eofa.FP64), ("fp16s", eofa.FP16S)):
+        prm = eofa.make_params(tol=1e-10, inner_prec=prec)
+        ctx.eofa_cg_solve([(1.0, ms1, 1.0, -1.0, +1)], phi, psi, prm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, st = ctx.eofa_cg_solve([(1.0, ms1, 1.0, -1.0, +1)], phi, psi, prm)
+        torch.cuda.synchronize()
+        res[name] = dict(seconds=round(time.perf_counter() - t0, 5), iters=st[0]["iters"],
+                         true_resid=st[0]["true_resid"], rc=rc)
+    ctx.close()
+    return res
+
+
+def dslash_beyond_mall(eofa, synth, torch, np, reps=50):
+    """Single-RHS Dslash (Dhop.D~, odd -> even) on the 24^3 x 64 x Ls=12
+    lattice, whose FP16S half-field (263 MiB) and FP32/FP64 ones exceed the
+    256 MB MALL, so every launch streams from HBM. Algorithmic GB/s on the hop's
+    compulsory bytes, HIP events on the launch stream over `reps` launches."""
+    dims, Ls, eps, m1 = (24, 24, 24, 64), 12, 0.5, 0.01
+    U = torch.from_numpy(synth.gauge_field(dims, eps, 1003)).cuda()
+    ctx = eofa.Context(eofa.make_action(dims, Ls, 1.8, 1.5, 0.5), U)
+    del U
+    phi = synth.fermion_torch(dims, Ls, seed=2003, nrhs=1)
+    Nh = int(np.prod(dims)) // 2 * Ls
+    out = {}
+    sysl = [(m1, m1, 1.0, 0.0, -1)]
+    for name, prec in (("fp16s", eofa.FP16S), ("fp32", eofa.FP32), ("fp64", eofa.FP64)):
+        pin, pout = ctx.new_packed(prec, 1), ctx.new_packed(prec, 1)
+        ctx.eofa_pack(phi, pin, 1, prec, 1)
+        ctx.eofa_dslash(sysl, pin, pout, 0, 0, prec, 1)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(reps):
+            ctx.eofa_dslash(sysl, pin, pout, 0, 0, prec, 1)
+        ev[1].record()
+        torch.cuda.synchronize()
+        t = ev[0].elapsed_time(ev[1]) / reps * 1e-3
+        gbs = hop_bytes(prec, Ls, Nh) / t / 1e9
+        out[name] = dict(avg_launch_us=round(t * 1e6, 2), algorithmic_GBs=round(gbs, 1),
+                         frac_hbm=round(gbs / HBM_PEAK_GBS, 4), gflops=round(1320.0 * Nh / t / 1e9, 1),
+                         field_MiB=round(ctx.packed_bytes(prec, 1) / 2 ** 20, 1),
+                         bytes_per_launch=int(hop_bytes(prec, Ls, Nh)))
+        del pin, pout
+    ctx.close()
+    return dict(workload=f"{dims[0]}x{dims[1]}x{dims[2]}x{dims[3]} Ls={Ls}, one Gaussian RHS, Dhop.D~(m1={m1}) "
+                         f"odd->even, {reps} launches", **out)
 
 
 def bench_batched(args, eofa, synth, torch, np):
@@ -165,6 +273,37 @@ def bench_batched(args, eofa, synth, torch, np):
         ctx.eofa_cg_solve(sysl[r:r + 1], ph1, ps1, prm)
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
+    # (c) time to solution: the 12 systems to an FP64 true residual of 1e-10,
+    # batched (FP32 inner, HIP graph, autotuned shape) against 12 plain FP64 solves
+    conv = None
+    if not args.no_converge:
+        prm_c = eofa.make_params(tol=1e-10, inner_prec=prec, use_graph=1, check_every=16)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, st = ctx.eofa_cg_solve(sysl, phi, psi, prm_c)
+        torch.cuda.synchronize()
+        t_conv = time.perf_counter() - t0
+        its = [s["iters"] for s in st]
+        conv = dict(seconds=round(t_conv, 3), rc=rc, iters=its, max_true_resid=max(s["true_resid"] for s in st),
+                    all_converged=all(s["converged"] for s in st),
+                    per_rhs_iteration_ms=round(t_conv / sum(its) * 1e3, 4),
+                    ideal_per_rhs_iteration_ms_fp32=round(17 * site_bytes(1) * Nh / HBM_PEAK_GBS / 1e6
+                                                           + 4 * link_bytes_per_site(1) * Vh / HBM_PEAK_GBS / 1e6, 4))
+        print(f"bench: batched converged solve {conv}", file=sys.stderr, flush=True)
+        if not args.no_plain:
+            prm_p = eofa.make_params(tol=1e-10, inner_prec=eofa.FP64, check_every=16)
+            t0 = time.perf_counter()
+            plain = []
+            for r in range(nrhs):
+                ph1.copy_(phi[r:r + 1])
+                rc1, st1 = ctx.eofa_cg_solve(sysl[r:r + 1], ph1, ps1, prm_p)
+                plain.append(dict(rc=rc1, iters=st1[0]["iters"], true_resid=st1[0]["true_resid"]))
+                print(f"bench: plain FP64 solve {r}: {plain[-1]}", file=sys.stderr, flush=True)
+            torch.cuda.synchronize()
+            t_plain = time.perf_counter() - t0
+            conv["plain_fp64_12_solves_seconds"] = round(t_plain, 3)
+            conv["plain_fp64_iters"] = [p_["iters"] for p_ in plain]
+            conv["speedup_vs_plain_fp64"] = round(t_plain / t_conv, 3)
     out = {
         "metric": METRIC, "value": round(alg / t_multi / 1e9, 1), "unit": "GB/s", "n_gpus": 1,
         "steps": args.steps, "warmup": 1, "ms_per_step": round(t_batch * 1e3, 3), "higher_is_better": True,
@@ -181,6 +320,7 @@ def bench_batched(args, eofa, synth, torch, np):
         "batched_cg": {"iters": iters, "seconds_batched": t_batch, "seconds_12_single": t_seq,
                        "speedup": round(t_seq / t_batch, 3),
                        "per_rhs_iteration_ms": round(t_batch / nrhs / iters * 1e3, 4)},
+        "time_to_solution_1e-10": conv,
     }
     ctx.close()
     print(json.dumps(out), flush=True)
@@ -535,6 +675,9 @@ def main():
     ap.add_argument("--inner-tol", type=float, default=0.0)
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 reference solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-mall", action="store_true", help="skip the Dslash on a field larger than the MALL")
+    ap.add_argument("--no-converge", action="store_true",
+                    help="batched workload: skip the solves to 1e-10 (batched and 12 plain FP64)")
     ap.add_argument("--train-fields", type=int, default=8)
     ap.add_argument("--held-fields", type=int, default=8)
     ap.add_argument("--pairs-per-field", type=int, default=64)
@@ -635,33 +778,46 @@ def main():
     ms = dt * 1e3 / args.steps
     print(f"bench: {args.steps} steps {ms:.2f} ms/step", file=sys.stderr, flush=True)
 
-    # whole-job Dslash throughput: every inner hop launch's algorithmic bytes / wall time
+    # whole-job Dslash throughput: the hop's compulsory bytes of every inner hop
+    # launch (4 per iteration, 2 more per outer pass for M^dag r) / wall time;
+    # the same with each launch's fused bytes is reported beside it
     iters = sum(s["iters"] for s in stats)
     outer = sum(s["outer_iters"] for s in stats)
-    per_iter = sum(role_bytes(k, prec, Ls, Nh) for k in range(4))
-    init_bytes = role_bytes(2, prec, Ls, Nh) + role_bytes(3, prec, Ls, Nh)  # M^dag r at each outer pass
-    total_bytes = iters * per_iter + outer * init_bytes
+    total_bytes = (4 * iters + 2 * outer) * hop_bytes(prec, Ls, Nh)
     value = total_bytes / dt / 1e9
+    fused_total = (iters * sum(role_bytes(k, prec, Ls, Nh) for k in range(4))
+                   + outer * (role_bytes(2, prec, Ls, Nh) + role_bytes(3, prec, Ls, Nh)))
 
-    # dominant kernel: the hop role with the largest timed share
+    # dominant kernel: the hop role with the largest timed share; its achieved
+    # bandwidth counts the hop's own compulsory bytes (input and output spinor,
+    # links), the fused bytes of its epilogue reported beside it
     hop_ms = np.sum([s["hop_ms"] for s in stats], axis=0)
     timed = sum(s["hop_timed"] for s in stats)
+    avg_us = [h / max(timed, 1) * 1e3 for h in hop_ms]
     dom = int(np.argmax(hop_ms))
-    avg_ms = hop_ms[dom] / max(timed, 1)
-    dom_bytes = role_bytes(dom, prec, Ls, Nh)
+    avg_ms = avg_us[dom] * 1e-3
+    dom_bytes = hop_bytes(prec, Ls, Nh)
     achieved = dom_bytes / (avg_ms * 1e-3) / 1e9
     traffic = traffic_from_profile(args.workload, args.inner, dom)
     # Wilson-hop flops: 1320 per 4D site per Ls slice (the conventional count, per hop launch)
     flop_per_launch = 1320.0 * Nh
     gflops_dom = flop_per_launch / (avg_ms * 1e-3) / 1e9
     gflops_job = 4 * iters * flop_per_launch / dt / 1e9
+    roles = []
+    for k in range(4):
+        t = avg_us[k] * 1e-6
+        hb, fb = hop_bytes(prec, Ls, Nh) / t / 1e9, role_bytes(k, prec, Ls, Nh) / t / 1e9
+        roles.append(dict(kernel=ROLE_NAMES[k], avg_launch_us=round(avg_us[k], 2), hop_GBs=round(hb, 1),
+                          hop_frac=round(hb / HBM_PEAK_GBS, 4), fused_GBs=round(fb, 1),
+                          fused_frac=round(fb / HBM_PEAK_GBS, 4)))
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                kernel=ROLE_NAMES[dom], avg_launch_us=round(avg_ms * 1e3, 2),
+                kernel=ROLE_NAMES[dom], avg_launch_us=round(avg_us[dom], 2),
                 algorithmic_bytes_per_launch=int(dom_bytes),
-                all_roles_avg_us=[round(h / max(timed, 1) * 1e3, 2) for h in hop_ms],
-                all_roles_gbs=[round(role_bytes(k, prec, Ls, Nh) / (hop_ms[k] / max(timed, 1) * 1e-3) / 1e9, 1)
-                               for k in range(4)])
+                bytes_model="hop compulsory bytes: input and output spinor once, links once per launch",
+                fused_bytes_per_launch=int(role_bytes(dom, prec, Ls, Nh)),
+                fused_frac=round(role_bytes(dom, prec, Ls, Nh) / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                all_roles=roles)
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
@@ -676,6 +832,7 @@ def main():
                    "lattice": list(dims), "Ls": Ls, "nrhs": 1, "inner": args.inner},
         "dslash_gflops": {"dominant_kernel": round(gflops_dom, 1), "whole_job": round(gflops_job, 1),
                           "flop_model": "1320 flop per 4D site per Ls slice per hop launch (4 launches per iteration)"},
+        "value_fused_bytes_GBs": round(fused_total / dt / 1e9, 1),
         "time_to_solution_s": round(ms / 1e3, 5),
         "iters": stats[-1]["iters"], "outer_iters": stats[-1]["outer_iters"],
         "true_resid": stats[-1]["true_resid"],
@@ -687,10 +844,17 @@ def main():
         out["plain_fp64"] = dict(time_to_solution_s=round(plain["seconds"], 5), iters=plain["iters"],
                                  true_resid=plain["true_resid"])
         out["speedup_vs_plain_fp64"] = round(plain["seconds"] / (ms / 1e3), 3)
-    if not args.no_cpu:
-        print("bench: timing the CPU oracle baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(dims, Ls, eps, m1, gseed, sseed)
     ctx.close()
+    del phi, psi, U
+    torch.cuda.empty_cache()
+    if not args.no_mall:
+        print("bench: Dslash on a field larger than the MALL (24^3x64, Ls=12)", file=sys.stderr, flush=True)
+        out["dslash_beyond_mall"] = dslash_beyond_mall(eofa, synth, torch, np)
+        torch.cuda.empty_cache()
+    if not args.no_cpu:
+        print("bench: the same solve on 4^4 x Ls=8 on the GPU and with the CPU oracle", file=sys.stderr, flush=True)
+        out["gpu_c1_time_to_solution"] = gpu_c1(eofa, synth, torch)
+        out["cpu_baseline"] = cpu_baseline(dims, Ls, eps, m1, gseed, sseed)
     print(json.dumps(out), flush=True)
 
 

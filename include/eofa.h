@@ -240,6 +240,34 @@ int eofa_heatbath_solve(eofa_ctx* ctx, double m1, double m2, int32_t n_poles, co
                         const double* beta, const double* pole_tol, const void* eta, void* phi,
                         const eofa_solver_params* params, eofa_solver_stats* stats, void* stream);
 
+/* The 2*n_poles pole solutions of the heatbath (Sec. IV B, eqn
+ * eofa_heatbath) before they are combined into phi:
+ *   sol[l]           = [H(m1) - gamma_l Delta_-(m1,m2) P_-]^-1 Omega_- P_- eta,
+ *   sol[n_poles + l] = [H(m2) - beta_l gamma_l Delta_+(m1,m2) P_+]^-1 Omega_+ P_+ eta,
+ * gamma_l = 1/(1+beta_l), l = 0..n_poles-1 (Omega_+- as in App. A; the
+ * right-hand sides take eta at s = 0 only). sol: device, 2*n_poles
+ * canonical fields in the layout of eta, one after another; it must not
+ * overlap eta. beta, pole_tol, params and stats as for
+ * eofa_heatbath_solve (the same route: batched, or poles in sequence from
+ * chronological forecasts). EOFA_ERR_NOT_CONVERGED if a system misses its
+ * target (its solution is still written). Blocks until done.            */
+int eofa_heatbath_poles(eofa_ctx* ctx, double m1, double m2, int32_t n_poles, const double* beta,
+                        const double* pole_tol, const void* eta, void* sol,
+                        const eofa_solver_params* params, eofa_solver_stats* stats, void* stream);
+
+/* Chronological forecast (Sec. VI B, after Brower et al.): the initial
+ * guess sum_k c_k prev_k for the system sys with right-hand side rhs, over
+ * n_prev (1..32) earlier solutions, from the Galerkin conditions
+ *   sum_k c_k prev_l^dag A prev_k = prev_l^dag rhs   for every l,
+ * A = H(m_op) + beta Delta_chi(m_a,m_b) P_chi (eqn generic_eofa_system): the
+ * minimiser of psi^dag A psi - rhs^dag psi - psi^dag rhs on their span.
+ * rhs, guess: device canonical fields; prev: n_prev canonical fields one
+ * after another; guess must not overlap rhs or prev. The n_prev x n_prev
+ * system is solved on the host; if it is numerically singular the guess is
+ * zero. Blocks until done.                                               */
+int eofa_forecast(eofa_ctx* ctx, const eofa_system* sys, const void* rhs, const void* prev, int32_t n_prev,
+                  void* guess, void* stream);
+
 /* Link derivative of the hopping term (Sec. IV C): for canonical 5D fields
  * a, b (device complex128, one right-hand side) and every link (x, mu), the
  * 3 x 3 complex matrix y_mu(x) such that

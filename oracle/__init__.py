@@ -25,8 +25,12 @@ Flavor Algorithm", arXiv:1706.05843):
                    with LU, full-lattice CGNR on the H form built from the
                    App. A closed forms, and the free-field momentum-space
                    solve.
-* ``action``    -- M_EOFA (eqn eofa_action) and the heatbath of eqn
-                   eofa_heatbath.
+* ``action``    -- M_EOFA (eqn eofa_action), the heatbath of eqn
+                   eofa_heatbath and its exactness measure (eqn
+                   heatbath_rel_err).
+* ``rational``  -- coefficients of a rational approximation of x^(-1/2)
+                   (the form of eqn rat_approx) by Gauss-Legendre
+                   quadrature; an input of the heatbath tests.
 * ``nn``        -- the gauge-covariant parallel-transport network used as
                    a flexible preconditioner (not part of the paper).
 

@@ -12,7 +12,10 @@ Test infrastructure only: see the package docstring.
             - k gamma_l P_+ Omega_+^dag [H(m2) - beta_l gamma_l Delta_+(m1,m2) P_+]^-1 Omega_+ P_+ eta }
   Reading: the printed sum runs over "k = 1..N_p" but its terms carry the
   index l; l is the pole index and k stays the EOFA constant of App. A.
-* eqn heatbath_rel_err: eps = |eta^dag eta - phi^dag M_EOFA phi| / eta^dag eta.
+* eqn heatbath_rel_err: eps = |eta^dag eta - phi^dag M_EOFA phi| / eta^dag eta
+  (pinned against the dense eigendecomposition of M_EOFA on 2^4 x Ls=4:
+  zero for phi = M_EOFA^(-1/2) eta, the eigenbasis closed form for
+  phi = f(M_EOFA) eta).
 
 ``solve(sys, rhs)`` is any solver of eqn generic_eofa_system (dense LU,
 mirror mode or full CGNR) so the same formulas serve every route.

@@ -454,18 +454,34 @@ int put(eofa_ctx* C, void* dev, const void* host, size_t bytes, hipStream_t st) 
 // system. Cayley (App. B.2): off-parity blocks Dhop D~, same-parity M_ee.
 // Dense (the EOFA matrix itself, for comparison): off-parity blocks Dhop,
 // same-parity D_ee = M_ee D~^-1, both forms with the same residual b - D psi.
+// Cayley form: the inner CG holds its search direction as p~ = D~ p, so K1
+// gathers an already premixed field (no D~ on its 8 neighbour columns), K2
+// applies M_ee D~^-1 to the same-site p~, the update forms D~ r by lane
+// exchange, and the solution accumulates x~ = D~ x (D~^-1 once per pass).
 struct Form {
-  int k1, k2, k3, k4, k4s, src, res, fullres;  // roles
+  int k1, k2, k3, k4, k4s, src, res, fullres;  // roles (k1, k2 of the inner iteration)
   int m1, m2, m3, m4a, m4b;                     // matA of K1, matB of K2, matA of K3, matA/matB of K4
   int inv, diag;                                // same-parity block inverse / block (source, residual)
   bool cayley;                                  // psi = D~ psi' on reconstruction, guess through D~^-1
+  int k1x;                                      // K1 on a plain (not premixed) x: the FP64 outer residual
+  bool ptilde;                                  // inner direction held as p~ = D~ p
 };
-const Form kCayley = {ROLE_K1, ROLE_K2, ROLE_K3, ROLE_K4, ROLE_K4S, ROLE_SRC, ROLE_RES, ROLE_FULLRES,
+const Form kCayley = {ROLE_K1T, ROLE_K2T, ROLE_K3, ROLE_K4, ROLE_K4S, ROLE_SRC, ROLE_RES, ROLE_FULLRES,
                       MAT_MEE_INV, MAT_MEE, MAT_MEE_INV_T, MAT_NEG_DT_T, MAT_MEE_T,
-                      MAT_MEE_INV, MAT_MEE, true};
+                      MAT_MEE_INV, MAT_MEE, true, ROLE_K1, true};
 const Form kDense = {ROLE_D1, ROLE_D2, ROLE_D3, ROLE_D4, ROLE_D4S, ROLE_DSRC, ROLE_DRES, ROLE_DFULLRES,
                      MAT_DEE_INV, MAT_DEE, MAT_DEE_INV_T, 0, MAT_DEE_T,
-                     MAT_DEE_INV, MAT_DEE, false};
+                     MAT_DEE_INV, MAT_DEE, false, ROLE_D1, false};
+
+DtArgs dt_args(eofa_ctx* C, const Form& F, int nrhs) {
+  DtArgs d;
+  if (F.ptilde) {
+    d.mop = mop_ptr(C, nrhs);
+    d.cpd = C->c + C->d;
+    d.cmd = C->c - C->d;
+  }
+  return d;
+}
 
 // Ring of search directions for the batched solution update: iteration k
 // reads p_k from slot k mod R and writes p_{k+1} to the next slot; every
@@ -514,14 +530,15 @@ int inner_iteration(eofa_ctx* C, const Form& F, int S, const HopArgs& k1, const 
   CHK(hop(C, S, F.k4, k4, st));
   if (ev) HIPCHK(hipEventRecord(ev[7], st));
   launch_finalize(FIN_BETA, partial, nbh, nrhs, Sst, nullptr, st);
+  const DtArgs dt = dt_args(C, F, nrhs);
   if (ring) {
     launch_p_update(S, g, rin, ring->at(k), ring->at(k + 1), Sst.alpha, Sst.beta, Sst.u2run,
-                    ring->ahist + (size_t)(k % ring->R) * nrhs, nrhs, st);
+                    ring->ahist + (size_t)(k % ring->R) * nrhs, nrhs, dt, st);
     if ((k + 1) % ring->F == 0)
       launch_x_flush(S, g, xin, ring->base, ring->slot, (k + 1 - ring->F) % ring->R, ring->F, ring->R, ring->ahist,
                      nrhs, st);
   } else {
-    launch_cg_update(S, g, xin, rin, pS, Sst.alpha, Sst.beta, Sst.u2run, nrhs, st);
+    launch_cg_update(S, g, xin, rin, pS, Sst.alpha, Sst.beta, Sst.u2run, nrhs, dt, st);
   }
   return EOFA_OK;
 }
@@ -804,7 +821,7 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
       a1.in = x;
       a1.out = te;
       a1.matA = F.m1;
-      CHK(hop(C, P64, F.k1, a1, st));
+      CHK(hop(C, P64, F.k1x, a1, st));
       HopArgs a2 = base_args(C, P64, 1, nrhs);
       a2.in = te;
       a2.y = x;
@@ -883,7 +900,9 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
     // after the first pass) keeps the previous pass's direction p, which
     // stays conjugate to within the inner precision, and replaces only r
     void* p0 = ring ? ring->at(0) : pS;
-    if (restart) {
+    if (restart && F.ptilde) {  // p~ = D~ r
+      launch_smat(S, g, rin, p0, C->mats, MAT_DT, nrhs, st);
+    } else if (restart) {
       launch_convert(S, S, g, rin, p0, nrhs, st);
     } else if (ring && last_it % ring->R != 0) {  // the kept direction into slot 0
       HIPCHK(hipMemcpyAsync(p0, ring->at(last_it), bS, hipMemcpyDeviceToDevice, st));
@@ -987,7 +1006,12 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
         done[r] = 1;
       }
     }
-    launch_axpy_to64(PX, g, x, xin, nrhs, st);
+    if (F.ptilde) {  // the pass accumulated x~ = D~ e: x += D~^-1 x~ (tmp is free here)
+      launch_smat(PX, g, xin, tmp, C->mats, MAT_DT_INV, nrhs, st);
+      launch_axpy_to64(PX, g, x, tmp, nrhs, st);
+    } else {
+      launch_axpy_to64(PX, g, x, xin, nrhs, st);
+    }
   }
 
   std::vector<double> re, rodd;
@@ -1038,6 +1062,9 @@ int check_params(const eofa_solver_params* prm) {
   if (prm->form != 0 && prm->form != 1) return fail(EOFA_ERR_INVALID, "form must be 0 or 1");
   if (prm->form == 1 && prm->precond != 0)
     return fail(EOFA_ERR_INVALID, "the dense form (form = 1) is solved by CGNR only (precond = 0)");
+  if (prm->waves != 0 && prm->waves != 1 && prm->waves != 2 && prm->waves != 4)
+    return fail(EOFA_ERR_INVALID, "waves must be 0 (autotune), 1, 2 or 4");
+  if (prm->rhs_block < 0) return fail(EOFA_ERR_INVALID, "rhs_block must be >= 0");
   const int rs = prm->ring_slots, chk = prm->check_every > 0 ? prm->check_every : 16;
   if (rs != -1 && rs != 0 && rs != 4 && rs != 8 && rs != 16)
     return fail(EOFA_ERR_INVALID, "ring_slots must be -1, 0, 4, 8 or 16");
@@ -1603,99 +1630,193 @@ int forecast(eofa_ctx* C, const eofa_system* sys, const void* rhs, const std::ve
   return EOFA_OK;
 }
 
-}  // namespace
+// The 2 N_p systems of the heatbath (Sec. IV B, eqn eofa_heatbath) for the
+// poles beta[0..n_poles), LH poles first, then RH:
+//   LH: H(m1) - gamma_l Delta_-(m1,m2) P_-,    RH: H(m2) - beta_l gamma_l Delta_+(m1,m2) P_+,
+// gamma_l = 1/(1+beta_l), with right-hand sides Omega_-+ P_-+ eta (App. A);
+// coef[r] (with alpha) the weight of the system's solution in phi:
+//   phi = a_eta eta + P Omega^dag sum_r coef[r] y_r,  coef = +-alpha_l gamma_l k gamma_l.
+struct HeatbathSystems {
+  std::vector<eofa_system> sys;
+  std::vector<double> coef, om;
+  std::vector<int> chir;
+  double a_eta = 0.0;
+};
 
-extern "C" int eofa_heatbath_solve(eofa_ctx* C, double m1, double m2, int32_t n_poles, const double* alpha,
-                                   const double* beta, const double* pole_tol, const void* eta, void* phi,
-                                   const eofa_solver_params* prm, eofa_solver_stats* stats, void* stream) {
-  if (!C || !alpha || !beta || !eta || !phi) return fail(EOFA_ERR_INVALID, "eofa_heatbath_solve: NULL argument");
-  if (eta == phi) return fail(EOFA_ERR_INVALID, "eofa_heatbath_solve: eta and phi alias");
-  if (n_poles < 1) return fail(EOFA_ERR_INVALID, "n_poles must be >= 1");
-  CHK(check_params(prm));
-  if (prm->form != 0) return fail(EOFA_ERR_INVALID, "eofa_heatbath_solve: form must be 0 (Cayley)");
-  if (pole_tol)
-    for (int r = 0; r < 2 * n_poles; ++r)
-      if (!(pole_tol[r] > 0.0)) return fail(EOFA_ERR_INVALID, "pole_tol entries must be > 0");
-  hipStream_t st = (hipStream_t)stream;
+int heatbath_systems(eofa_ctx* C, double m1, double m2, int n_poles, const double* alpha, const double* beta,
+                     HeatbathSystems& H) {
   const Geometry& g = C->g;
   const int nsys = 2 * n_poles;
-  std::vector<eofa_system> sys(nsys);
-  std::vector<double> coef(nsys), om(nsys * g.Ls);
-  std::vector<int> chir(nsys);
+  H.sys.resize(nsys);
+  H.coef.assign(nsys, 0.0);
+  H.om.resize((size_t)nsys * g.Ls);
+  H.chir.resize(nsys);
   std::vector<double> wp(g.Ls), wm(g.Ls);
   omega_col(g.Ls, C->c, C->d, +1, wp.data());
   omega_col(g.Ls, C->c, C->d, -1, wm.data());
   const double k = k_eofa(g.Ls, C->c, C->d, m1, m2);
-  double a_eta = alpha[0];
+  H.a_eta = alpha ? alpha[0] : 0.0;
   for (int l = 0; l < n_poles; ++l) {
     const double bl = beta[l];
     if (!(1.0 + bl != 0.0) || !std::isfinite(bl)) return fail(EOFA_ERR_INVALID, "pole beta_l = -1 or non-finite");
     const double gl = 1.0 / (1.0 + bl);
-    a_eta += alpha[l + 1] * gl;
-    // LH: (H(m1) - gamma_l Delta_-(m1,m2) P_-),  RH: (H(m2) - beta_l gamma_l Delta_+(m1,m2) P_+)
-    sys[l] = eofa_system{m1, m1, m2, -gl, -1};
-    sys[n_poles + l] = eofa_system{m2, m1, m2, -bl * gl, +1};
-    coef[l] = alpha[l + 1] * gl * k * gl;
-    coef[n_poles + l] = -alpha[l + 1] * gl * k * gl;
-    chir[l] = -1;
-    chir[n_poles + l] = +1;
+    H.sys[l] = eofa_system{m1, m1, m2, -gl, -1};
+    H.sys[n_poles + l] = eofa_system{m2, m1, m2, -bl * gl, +1};
+    if (alpha) {
+      if (!std::isfinite(alpha[l + 1])) return fail(EOFA_ERR_INVALID, "non-finite alpha_l");
+      H.a_eta += alpha[l + 1] * gl;
+      H.coef[l] = alpha[l + 1] * gl * k * gl;
+      H.coef[n_poles + l] = -alpha[l + 1] * gl * k * gl;
+    }
+    H.chir[l] = -1;
+    H.chir[n_poles + l] = +1;
     for (int s = 0; s < g.Ls; ++s) {
-      om[l * g.Ls + s] = wm[s];
-      om[(n_poles + l) * g.Ls + s] = wp[s];
+      H.om[(size_t)l * g.Ls + s] = wm[s];
+      H.om[(size_t)(n_poles + l) * g.Ls + s] = wp[s];
     }
   }
-  const size_t fbytes = (size_t)g.Ls * g.V * 12 * 16;
-  void *rhs, *sol, *cdev;
-  CHK(ws(C, "hb_rhs", fbytes * nsys, &rhs));
-  CHK(ws(C, "hb_sol", fbytes * nsys, &sol));
-  const size_t cbytes = sizeof(double) * (nsys + nsys * g.Ls) + sizeof(int) * nsys;
+  if (alpha && !std::isfinite(alpha[0])) return fail(EOFA_ERR_INVALID, "non-finite alpha_0");
+  return EOFA_OK;
+}
+
+int heatbath_check(eofa_ctx* C, int32_t n_poles, const double* beta, const double* pole_tol, const void* eta,
+                   const eofa_solver_params* prm, const char* who) {
+  if (!C || !beta || !eta) return fail(EOFA_ERR_INVALID, std::string(who) + ": NULL argument");
+  if (n_poles < 1) return fail(EOFA_ERR_INVALID, "n_poles must be >= 1");
+  CHK(check_params(prm));
+  if (prm->form != 0) return fail(EOFA_ERR_INVALID, std::string(who) + ": form must be 0 (Cayley)");
+  if (pole_tol)
+    for (int r = 0; r < 2 * n_poles; ++r)
+      if (!(pole_tol[r] > 0.0)) return fail(EOFA_ERR_INVALID, "pole_tol entries must be > 0");
+  return EOFA_OK;
+}
+
+// Upload the heatbath coefficients (coef, Omega columns, chiralities) into
+// workspace; returns device pointers.
+int heatbath_upload(eofa_ctx* C, const HeatbathSystems& H, const double** d_coef, const double** d_om,
+                    const int** d_chir, hipStream_t st) {
+  const int nsys = (int)H.sys.size();
+  const int Ls = C->g.Ls;
+  void* cdev;
+  const size_t cbytes = sizeof(double) * (nsys + (size_t)nsys * Ls) + sizeof(int) * nsys;
   CHK(ws(C, "hb_coef", cbytes, &cdev));
   CHK(stage(C, cbytes));
-  {
-    std::vector<unsigned char> h(cbytes);
-    std::memcpy(h.data(), coef.data(), sizeof(double) * nsys);
-    std::memcpy(h.data() + sizeof(double) * nsys, om.data(), sizeof(double) * nsys * g.Ls);
-    std::memcpy(h.data() + sizeof(double) * (nsys + nsys * g.Ls), chir.data(), sizeof(int) * nsys);
-    CHK(put(C, cdev, h.data(), cbytes, st));
-  }
-  const double* d_coef = (const double*)cdev;
-  const double* d_om = d_coef + nsys;
-  const int* d_chir = (const int*)(d_om + nsys * g.Ls);
+  std::vector<unsigned char> h(cbytes);
+  std::memcpy(h.data(), H.coef.data(), sizeof(double) * nsys);
+  std::memcpy(h.data() + sizeof(double) * nsys, H.om.data(), sizeof(double) * nsys * Ls);
+  std::memcpy(h.data() + sizeof(double) * (nsys + (size_t)nsys * Ls), H.chir.data(), sizeof(int) * nsys);
+  CHK(put(C, cdev, h.data(), cbytes, st));
+  *d_coef = (const double*)cdev;
+  *d_om = *d_coef + nsys;
+  *d_chir = (const int*)(*d_om + (size_t)nsys * Ls);
+  return EOFA_OK;
+}
+
+// y_r = A_r^-1 Omega P eta for the 2 N_p heatbath systems into sol
+// ([2 N_p] canonical fields): batched, or (use_guess) the poles of each side
+// one after another from chronological forecasts. Returns the worst status
+// of the solves (EOFA_ERR_NOT_CONVERGED passes through).
+int heatbath_poles(eofa_ctx* C, const HeatbathSystems& H, const double* d_om, const int* d_chir,
+                   const double* pole_tol, const void* eta, void* sol, const eofa_solver_params* prm,
+                   eofa_solver_stats* sts, hipStream_t st) {
+  const Geometry& g = C->g;
+  const int nsys = (int)H.sys.size(), n_poles = nsys / 2;
+  const size_t fbytes = (size_t)g.Ls * g.V * 12 * 16;
+  void* rhs;
+  CHK(ws(C, "hb_rhs", fbytes * nsys, &rhs));
   launch_omega_rhs(g, eta, rhs, d_om, d_chir, nsys, st);
   HIPCHK(hipGetLastError());
-  std::vector<eofa_solver_stats> st_local(nsys);
-  eofa_solver_stats* sts = stats ? stats : st_local.data();
   int rc = EOFA_OK;
   if (!prm->use_guess) {
-    // all 2 N_p systems in one batched solve
     eofa_solver_params p2 = *prm;
-    rc = solve_batch(C, sys.data(), nsys, rhs, sol, &p2, sts, st, pole_tol);
+    rc = solve_batch(C, H.sys.data(), nsys, rhs, sol, &p2, sts, st, pole_tol);
     if (rc != EOFA_OK && rc != EOFA_ERR_NOT_CONVERGED) return rc;
-  } else {
-    // poles one after another, each starting from the chronological forecast
-    // over up to 8 previous solutions of the same side (LH or RH)
-    constexpr int max_prev = 8;
-    for (int side = 0; side < 2; ++side) {
-      std::vector<const void*> prev;
-      for (int l = 0; l < n_poles; ++l) {
-        const int r = side * n_poles + l;
-        const void* rhs_r = (const char*)rhs + fbytes * r;
-        void* sol_r = (char*)sol + fbytes * r;
-        eofa_solver_params p2 = *prm;
-        p2.use_guess = prev.empty() ? 0 : 1;
-        if (!prev.empty()) CHK(forecast(C, &sys[r], rhs_r, prev, sol_r, st));
-        const int rr = solve_batch(C, &sys[r], 1, rhs_r, sol_r, &p2, sts + r, st, pole_tol ? pole_tol + r : nullptr);
-        if (rr != EOFA_OK && rr != EOFA_ERR_NOT_CONVERGED) return rr;
-        if (rr != EOFA_OK) rc = rr;
-        prev.push_back(sol_r);
-        if ((int)prev.size() > max_prev) prev.erase(prev.begin());
-      }
+    return rc;
+  }
+  constexpr int max_prev = 8;
+  for (int side = 0; side < 2; ++side) {
+    std::vector<const void*> prev;
+    for (int l = 0; l < n_poles; ++l) {
+      const int r = side * n_poles + l;
+      const void* rhs_r = (const char*)rhs + fbytes * r;
+      void* sol_r = (char*)sol + fbytes * r;
+      eofa_solver_params p2 = *prm;
+      p2.use_guess = prev.empty() ? 0 : 1;
+      if (!prev.empty()) CHK(forecast(C, &H.sys[r], rhs_r, prev, sol_r, st));
+      const int rr = solve_batch(C, &H.sys[r], 1, rhs_r, sol_r, &p2, sts + r, st, pole_tol ? pole_tol + r : nullptr);
+      if (rr != EOFA_OK && rr != EOFA_ERR_NOT_CONVERGED) return rr;
+      if (rr != EOFA_OK) rc = rr;
+      prev.push_back(sol_r);
+      if ((int)prev.size() > max_prev) prev.erase(prev.begin());
     }
   }
-  launch_heatbath_combine(g, eta, sol, phi, a_eta, d_coef, d_om, d_chir, nsys, st);
+  return rc;
+}
+
+}  // namespace
+
+extern "C" int eofa_heatbath_poles(eofa_ctx* C, double m1, double m2, int32_t n_poles, const double* beta,
+                                   const double* pole_tol, const void* eta, void* sol,
+                                   const eofa_solver_params* prm, eofa_solver_stats* stats, void* stream) {
+  CHK(heatbath_check(C, n_poles, beta, pole_tol, eta, prm, "eofa_heatbath_poles"));
+  if (!sol) return fail(EOFA_ERR_INVALID, "eofa_heatbath_poles: NULL argument");
+  const size_t fbytes = (size_t)C->g.Ls * C->g.V * 12 * 16;
+  const char *e0 = (const char*)eta, *s0 = (const char*)sol;
+  if (e0 + fbytes > s0 && s0 + fbytes * 2 * n_poles > e0)
+    return fail(EOFA_ERR_INVALID, "eofa_heatbath_poles: eta and sol overlap");
+  hipStream_t st = (hipStream_t)stream;
+  HeatbathSystems H;
+  CHK(heatbath_systems(C, m1, m2, n_poles, nullptr, beta, H));
+  const double *d_coef, *d_om;
+  const int* d_chir;
+  CHK(heatbath_upload(C, H, &d_coef, &d_om, &d_chir, st));
+  std::vector<eofa_solver_stats> st_local(2 * n_poles);
+  const int rc = heatbath_poles(C, H, d_om, d_chir, pole_tol, eta, sol, prm, stats ? stats : st_local.data(), st);
   HIPCHK(hipStreamSynchronize(st));
   HIPCHK(hipGetLastError());
   return rc;
+}
+
+extern "C" int eofa_heatbath_solve(eofa_ctx* C, double m1, double m2, int32_t n_poles, const double* alpha,
+                                   const double* beta, const double* pole_tol, const void* eta, void* phi,
+                                   const eofa_solver_params* prm, eofa_solver_stats* stats, void* stream) {
+  CHK(heatbath_check(C, n_poles, beta, pole_tol, eta, prm, "eofa_heatbath_solve"));
+  if (!alpha || !phi) return fail(EOFA_ERR_INVALID, "eofa_heatbath_solve: NULL argument");
+  if (eta == phi) return fail(EOFA_ERR_INVALID, "eofa_heatbath_solve: eta and phi alias");
+  hipStream_t st = (hipStream_t)stream;
+  HeatbathSystems H;
+  CHK(heatbath_systems(C, m1, m2, n_poles, alpha, beta, H));
+  const double *d_coef, *d_om;
+  const int* d_chir;
+  CHK(heatbath_upload(C, H, &d_coef, &d_om, &d_chir, st));
+  const size_t fbytes = (size_t)C->g.Ls * C->g.V * 12 * 16;
+  void* sol;
+  CHK(ws(C, "hb_sol", fbytes * 2 * n_poles, &sol));
+  std::vector<eofa_solver_stats> st_local(2 * n_poles);
+  const int rc = heatbath_poles(C, H, d_om, d_chir, pole_tol, eta, sol, prm, stats ? stats : st_local.data(), st);
+  if (rc != EOFA_OK && rc != EOFA_ERR_NOT_CONVERGED) return rc;
+  launch_heatbath_combine(C->g, eta, sol, phi, H.a_eta, d_coef, d_om, d_chir, 2 * n_poles, st);
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+  return rc;
+}
+
+extern "C" int eofa_forecast(eofa_ctx* C, const eofa_system* sys, const void* rhs, const void* prev, int32_t n_prev,
+                             void* guess, void* stream) {
+  if (!C || !rhs || !prev || !guess) return fail(EOFA_ERR_INVALID, "eofa_forecast: NULL argument");
+  if (n_prev < 1 || n_prev > 32) return fail(EOFA_ERR_INVALID, "eofa_forecast: n_prev must be 1..32");
+  CHK(check_systems(sys, 1));
+  const size_t fbytes = (size_t)C->g.Ls * C->g.V * 12 * 16;
+  const char *g0 = (const char*)guess, *p0 = (const char*)prev, *r0 = (const char*)rhs;
+  if ((g0 < p0 + fbytes * n_prev && p0 < g0 + fbytes) || (g0 < r0 + fbytes && r0 < g0 + fbytes))
+    return fail(EOFA_ERR_INVALID, "eofa_forecast: guess overlaps rhs or prev");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<const void*> pv(n_prev);
+  for (int k = 0; k < n_prev; ++k) pv[k] = p0 + fbytes * k;
+  CHK(forecast(C, sys, rhs, pv, guess, st));
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+  return EOFA_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -96,6 +96,9 @@ enum HopRole {
   ROLE_DSRC,         // out = z - Dhop in
   ROLE_DRES,         // out = z - (B y - Dhop in), |out|^2
   ROLE_DFULLRES,     // out = z - (B y + Dhop in), |out|^2
+  // Cayley form with the search direction held as p~ = D~ p (in = p~, already premixed)
+  ROLE_K1T,          // out = D~ A (Dhop in)
+  ROLE_K2T,          // out = M_ee D~^-1 y - Dhop in, |out|^2   (y = p~, in = D~ t from K1T)
   NROLE
 };
 
@@ -143,13 +146,20 @@ void launch_zero(int prec, const Geometry& g, void* f, int nrhs, hipStream_t st)
 int launch_norm2(int prec, const Geometry& g, const void* f, int nrhs, double* partial, hipStream_t st);
 // ring form of the CG update: p into the next slot (alpha kept in ahist[nrhs]),
 // and x += sum of kept alpha times the directions of nslots slots
+// dt (optional): the direction is held as p~ = D~ p, so p~_{k+1} = D~ r + beta p~_k
+// with D~ = (c+d) + (c-d) L(m_op[r]) (App. A) applied by lane exchange
+struct DtArgs {
+  const double* mop = nullptr;  // [nrhs] operator mass; nullptr: plain update
+  double cpd = 0.0, cmd = 0.0;  // c+d, c-d
+};
 void launch_p_update(int ps, const Geometry& g, const void* r, const void* p, void* pn, const double* alpha,
-                     const double* beta, const int* u2run, double* ahist, int nrhs, hipStream_t st);
+                     const double* beta, const int* u2run, double* ahist, int nrhs, const DtArgs& dt,
+                     hipStream_t st);
 void launch_x_flush(int ps, const Geometry& g, void* x, const void* ring, size_t slot_bytes, int first, int nslots,
                     int R, const double* ahist, int nrhs, hipStream_t st);
 // fused CG update: x in sol_prec(ps), the residual in ps (the inner precision)
 void launch_cg_update(int ps, const Geometry& g, void* x, const void* r, void* p, const double* alpha,
-                      const double* beta, const int* u2run, int nrhs, hipStream_t st);
+                      const double* beta, const int* u2run, int nrhs, const DtArgs& dt, hipStream_t st);
 void launch_finalize(int mode, const double* partial, int nblk, int nrhs, CgState st_, double* out,
                      hipStream_t st);
 

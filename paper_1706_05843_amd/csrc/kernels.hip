@@ -38,8 +38,9 @@ namespace eofa {
 //           otherwise; D~ and D~^T by lane exchange)
 // plus the same-site term B y:
 //   B_MEE   + M_ee y           B_MEET + M_ee^T y    (structured: lane exchange)
+//   B_MEE_DTI + M_ee D~^-1 y   (y = p~ = D~ p; D~^-1 a geometric series along s)
 enum { A_ID = 0, A_NEG = 1, A_MAT = 2, A_DTT = 3, A_NDTT = 4, A_MATDT = 5, A_DMINV = 6, A_MINVDT = 7 };
-enum { B_NONE = 0, B_MEE = 1, B_MEET = 2, B_DENSE = 3 };
+enum { B_NONE = 0, B_MEE = 1, B_MEET = 2, B_DENSE = 3, B_MEE_DTI = 4 };
 enum { O_STORE = 0, O_ADDZ = 1, O_RUPD = 2, O_STORE_R = 3 };
 
 template <int ROLE>
@@ -72,6 +73,9 @@ EOFA_ROLE(ROLE_D4S, true, false, A_NEG, B_DENSE, O_STORE_R, true)
 EOFA_ROLE(ROLE_DSRC, false, false, A_ID, B_NONE, O_ADDZ, false)
 EOFA_ROLE(ROLE_DRES, false, false, A_NEG, B_DENSE, O_ADDZ, true)
 EOFA_ROLE(ROLE_DFULLRES, false, false, A_ID, B_DENSE, O_ADDZ, true)
+// the search direction held as p~ = D~ p: no premix in K1, D~^-1 on the same-site term of K2
+EOFA_ROLE(ROLE_K1T, false, false, A_DMINV, B_NONE, O_STORE, false)
+EOFA_ROLE(ROLE_K2T, false, false, A_NEG, B_MEE_DTI, O_STORE, true)
 #undef EOFA_ROLE
 
 constexpr int LSTR = 73;  // padded link stride per site in LDS (complex units)
@@ -118,7 +122,10 @@ __device__ __forceinline__ int row_ror(int v) {
   if constexpr ((K & 15) == 0) {
     return v;
   } else {
-    return __builtin_amdgcn_mov_dpp(v, 0x120 + (K & 15), 0xF, 0xF, false);
+    // a rotation has no out-of-range source lane, so bound_ctrl (0 for such
+    // lanes) changes nothing; with it set the compiler folds the move into the
+    // VALU instruction that consumes it (one v_fmac_f32_dpp instead of two)
+    return __builtin_amdgcn_update_dpp(0, v, 0x120 + (K & 15), 0xF, 0xF, true);
   }
 }
 template <int K>
@@ -543,6 +550,16 @@ __device__ __forceinline__ void scan_step(cx<R>* z, int s, R rhoN, R m) {
   }
 }
 
+// z <- sum_{k<16} (x L)^k z on a 16-lane row (Ls = 16; L^16 = -m), by four
+// doublings (1 + x^8 L^8)(1 + x^4 L^4)(1 + x^2 L^2)(1 + x L); x1 = x, x2 = x^2, ...
+template <class R, bool UP>
+__device__ __forceinline__ void series_rows(cx<R>* z, int s, R x1, R x2, R x4, R x8, R m) {
+  scan_step<R, 1, UP>(z, s, x1, m);
+  scan_step<R, 2, UP>(z, s, x2, m);
+  scan_step<R, 4, UP>(z, s, x4, m);
+  scan_step<R, 8, UP>(z, s, x8, m);
+}
+
 // Structured inverse of the same-parity block on a 16-lane row (App. B.2):
 // A = bee (1 - rho L), rho = cee / bee, and L^16 = -m, so
 //   A^-1 = (1 + rho^8 L^8)(1 + rho^4 L^4)(1 + rho^2 L^2)(1 + rho L) / (bee (1 + m rho^16))
@@ -573,17 +590,10 @@ __device__ __forceinline__ void minv_rows(cx<R>* v, int s, int g, R bee, R cee, 
       }
     }
     // A^-1 uses L_chi; A^-T the other direction
-    if ((chir > 0) != TRANS) {
-      scan_step<R, 1, true>(z, s, rho, m);
-      scan_step<R, 2, true>(z, s, rho2, m);
-      scan_step<R, 4, true>(z, s, rho4, m);
-      scan_step<R, 8, true>(z, s, rho8, m);
-    } else {
-      scan_step<R, 1, false>(z, s, rho, m);
-      scan_step<R, 2, false>(z, s, rho2, m);
-      scan_step<R, 4, false>(z, s, rho4, m);
-      scan_step<R, 8, false>(z, s, rho8, m);
-    }
+    if ((chir > 0) != TRANS)
+      series_rows<R, true>(z, s, rho, rho2, rho4, rho8, m);
+    else
+      series_rows<R, false>(z, s, rho, rho2, rho4, rho8, m);
 #pragma unroll
     for (int c = 0; c < 6; ++c) z[c] = scale * z[c];
     if constexpr (!TRANS) {
@@ -596,6 +606,69 @@ __device__ __forceinline__ void minv_rows(cx<R>* v, int s, int g, R bee, R cee, 
         }
       }
     }
+  }
+}
+
+// z <- sum_{k<Ls} (x L)^k z for any Ls by lane permutes within the column
+// (lanes g*Ls .. g*Ls+Ls-1; L^Ls = -m; up: L = L_+, lane s takes s - j, else
+// L_-, s + j), as a product over the prime factors p_i of Ls:
+//   sum_{k<Ls} y^k = prod_i (1 + y^{n_i} + ... + y^{(p_i - 1) n_i}),  n_i = p_1 ... p_{i-1}
+template <class R>
+__device__ __forceinline__ void series_cols(cx<R>* z, int s, int g, int Ls, R x, R m, bool up) {
+  int n = 1, rest = Ls;
+  R rn = x;  // x^n
+  while (rest > 1) {
+    int p = 2;
+    while (rest % p != 0) ++p;
+    cx<R> add[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) add[c] = {R(0), R(0)};
+    R rj = R(1);
+    for (int k = 1; k < p; ++k) {
+      const int j = k * n;
+      rj *= rn;
+      const int t = up ? s - j : s + j;
+      const bool wrap = up ? t < 0 : t >= Ls;
+      const int src = g * Ls + (wrap ? (up ? t + Ls : t - Ls) : t);
+      const R f = wrap ? -m * rj : rj;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const cx<R> w = {__shfl(z[c].r, src, 64), __shfl(z[c].i, src, 64)};
+        add[c].r = fma(f, w.r, add[c].r);
+        add[c].i = fma(f, w.i, add[c].i);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) z[c] = z[c] + add[c];
+    rn *= rj;  // x^(n p) = x^n x^((p - 1) n)
+    n *= p;
+    rest /= p;
+  }
+}
+
+// v <- D~^-1 v (App. A): per chirality D~ = (c+d)(1 + q L) with q = (c-d)/(c+d)
+// (L_+ on P_+ psi, L_- on P_- psi) and L^Ls = -m, so for even Ls
+//   D~^-1 = sum_{k<Ls} (-q L)^k / ((c+d)(1 + m q^Ls)).
+template <class R, int RL>
+__device__ __forceinline__ void dtinv(cx<R>* v, int s, int g, int Ls, R cpd, R cmd, R m) {
+  const R q = cmd / cpd, x1 = -q;
+  R qLs = R(1);
+  for (int k = 0; k < Ls; ++k) qLs *= q;
+  const R scale = R(1) / (cpd * (R(1) + m * qLs));
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    cx<R>* z = v + half * 6;
+    if constexpr (RL == 16) {
+      const R x2 = x1 * x1, x4 = x2 * x2, x8 = x4 * x4;
+      if (half == 0)
+        series_rows<R, true>(z, s, x1, x2, x4, x8, m);
+      else
+        series_rows<R, false>(z, s, x1, x2, x4, x8, m);
+    } else {
+      series_cols<R>(z, s, g, Ls, x1, m, half == 0);
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) z[c] = scale * z[c];
   }
 }
 
@@ -640,36 +713,7 @@ __device__ __forceinline__ void minv_cols(cx<R>* v, int s, int g, int Ls, R bee,
       }
     }
     // A^-1 uses L_chi (lane s takes s - j for L_+, s + j for L_-); A^-T the other
-    const bool up = (chir > 0) != TRANS;
-    int n = 1, rest = Ls;
-    R rn = rho;  // rho^n
-    while (rest > 1) {
-      int p = 2;
-      while (rest % p != 0) ++p;
-      cx<R> add[6];
-#pragma unroll
-      for (int c = 0; c < 6; ++c) add[c] = {R(0), R(0)};
-      R rj = R(1);
-      for (int k = 1; k < p; ++k) {
-        const int j = k * n;
-        rj *= rn;
-        const int t = up ? s - j : s + j;
-        const bool wrap = up ? t < 0 : t >= Ls;
-        const int src = g * Ls + (wrap ? (up ? t + Ls : t - Ls) : t);
-        const R f = wrap ? -m * rj : rj;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) {
-          const cx<R> w = {__shfl(z[c].r, src, 64), __shfl(z[c].i, src, 64)};
-          add[c].r = fma(f, w.r, add[c].r);
-          add[c].i = fma(f, w.i, add[c].i);
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < 6; ++c) z[c] = z[c] + add[c];
-      rn *= rj;  // rho^(n p) = rho^n rho^((p - 1) n)
-      n *= p;
-      rest /= p;
-    }
+    series_cols<R>(z, s, g, Ls, rho, m, (chir > 0) != TRANS);
 #pragma unroll
     for (int c = 0; c < 6; ++c) z[c] = scale * z[c];
     if constexpr (!TRANS) {
@@ -829,9 +873,17 @@ hop_kernel(HopArgs a) {
 
   const int rb0 = blockIdx.y * a.rhs_block;
   const int rb1 = min(rb0 + a.rhs_block, a.nrhs);
+  __shared__ int s_halt;
   for (int r = rb0; r < rb1; ++r) {
-    if (a.halt != nullptr && a.halt[r] != 0) continue;  // uniform over the block
     __syncthreads();
+    if (a.halt != nullptr) {
+      // one read of the flag per work-group, broadcast through LDS: another
+      // stream may set it while this kernel runs, and every wave of the
+      // block must take the same branch (the epilogues hold barriers)
+      if (tid == 0) s_halt = __hip_atomic_load(a.halt + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __syncthreads();
+      if (s_halt != 0) continue;
+    }
     if constexpr (DENSE || BDENSE) {
       const double* mats_r = a.mats + (size_t)r * NMAT * 2 * Ls * Ls;
       load_mat<R>(s_mA, mats_r + (size_t)(DENSE ? a.matA : a.matB) * 2 * Ls * Ls, Ls, tid, nthr);
@@ -933,6 +985,7 @@ hop_kernel(HopArgs a) {
       //   bee y - cee L y (L^T y) + sk u e_{s*}^T y (sk e_{s*} u^T y) on chirality chi
       cx<R> y[12], t[12];
       load_y<P, YPRE>(a.y, fd, r, s, EOFA_SITE, ypre, y);
+      if constexpr (RT::BM == B_MEE_DTI) dtinv<R, RL>(y, s, g, Ls, cpd, cmd, (R)a.mop[r]);
       lmul<R, RT::BM == B_MEET, RL>(y, t, nb);
       const R bee = (R)a.bee, cee = (R)a.cee;
 #pragma unroll
@@ -1057,6 +1110,8 @@ size_t hop_lds_p(int role, int Ls, int W) {
     case ROLE_DSRC: return hop_lds_t<P, ROLE_DSRC>(Ls, W);
     case ROLE_DRES: return hop_lds_t<P, ROLE_DRES>(Ls, W);
     case ROLE_DFULLRES: return hop_lds_t<P, ROLE_DFULLRES>(Ls, W);
+    case ROLE_K1T: return hop_lds_t<P, ROLE_K1T>(Ls, W);
+    case ROLE_K2T: return hop_lds_t<P, ROLE_K2T>(Ls, W);
   }
   return 0;
 }
@@ -1110,6 +1165,8 @@ int launch_hop_p(int role, const HopArgs& a, hipStream_t st, int* nb) {
     case ROLE_DSRC: return launch_hop_t<P, ROLE_DSRC>(a, st, nb);
     case ROLE_DRES: return launch_hop_t<P, ROLE_DRES>(a, st, nb);
     case ROLE_DFULLRES: return launch_hop_t<P, ROLE_DFULLRES>(a, st, nb);
+    case ROLE_K1T: return launch_hop_t<P, ROLE_K1T>(a, st, nb);
+    case ROLE_K2T: return launch_hop_t<P, ROLE_K2T>(a, st, nb);
   }
   return EOFA_ERR_INVALID;
 }
@@ -1538,8 +1595,140 @@ __global__ void __launch_bounds__(256) x_flush_kernel(int Ls, int Vh, int nrhs, 
   st_spinor_nt<PR>(x, f, r, s, i, xv);
 }
 
+// The update kernels of a direction held as p~ = D~ p: lanes hold whole
+// s-columns as in the hop kernel (lane = g*Ls + s, G = 64/Ls sites per wave,
+// four waves per work-group), so D~ r = (c+d) r + (c-d)(P_+ L_+ r + P_- L_- r)
+// (App. A) is a lane exchange. Every lane takes part in the exchange; only
+// live lanes (g < G, site in range) load and store.
+template <class R, int RL>
+__device__ __forceinline__ void dt_apply(cx<R>* v, int s, int g, int Ls, R cpd, R cmd, R m) {
+  SNbr<R> nb;
+  nb.sp = g * Ls + (s > 0 ? s - 1 : Ls - 1);
+  nb.sn = g * Ls + (s < Ls - 1 ? s + 1 : 0);
+  nb.fp = s > 0 ? R(1) : -m;
+  nb.fn = s < Ls - 1 ? R(1) : -m;
+  cx<R> t[12];
+  lmul<R, false, RL>(v, t, nb);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) v[c] = {fma(cmd, t[c].r, cpd * v[c].r), fma(cmd, t[c].i, cpd * v[c].i)};
+}
+
+struct ColLane {
+  int g, s, i;
+  bool live;
+};
+__device__ __forceinline__ ColLane col_lane(int Ls, int Vh) {
+  const int G = 64 / Ls, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  ColLane c;
+  c.g = lane / Ls;
+  c.s = lane - c.g * Ls;
+  c.i = (blockIdx.x * 4 + wave) * G + c.g;
+  c.live = c.g < G && c.i < Vh;
+  return c;
+}
+
+// p~_{k+1} = D~ r + beta p~_k into the next ring slot, alpha kept (as p_update_kernel)
+template <int PS, int PR, int RL>
+__global__ void __launch_bounds__(256) p_update_dt_kernel(int Ls, int Vh, int nrhs, const void* rr, const void* p,
+                                                            void* pn, const double* alpha, const double* beta,
+                                                            const int* u2run, double* ahist, double cpd, double cmd,
+                                                            const double* mop) {
+  const int r = blockIdx.y;
+  const ColLane cl = col_lane(Ls, Vh);
+  const bool run = u2run[r] != 0;  // uniform over the grid
+  if (blockIdx.x == 0 && threadIdx.x == 0) ahist[r] = run ? alpha[r] : 0.0;
+  const FD f = {Ls, Vh, nrhs};
+  using RR = typename ST<PR>::R;
+  using RS = typename ST<PS>::R;
+  cx<RS> pv[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) pv[c] = {RS(0), RS(0)};
+  if (cl.live) ld_spinor<PS>(p, f, r, cl.s, cl.i, pv);
+  if (run) {
+    cx<RR> rv[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) rv[c] = {RR(0), RR(0)};
+    if (cl.live) ld_spinor_nt<PR>(rr, f, r, cl.s, cl.i, rv);
+    dt_apply<RR, RL>(rv, cl.s, cl.g, Ls, (RR)cpd, (RR)cmd, (RR)mop[r]);
+    const RR be = (RR)beta[r];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) pv[c] = {(RS)fma(be, (RR)pv[c].r, rv[c].r), (RS)fma(be, (RR)pv[c].i, rv[c].i)};
+  }
+  if (cl.live) st_spinor<PS>(pn, f, r, cl.s, cl.i, pv);
+}
+
+// x~ += alpha p~;  p~ = D~ r + beta p~   (fused form of the same update)
+template <int PS, int PX, int PR, int RL>
+__global__ void __launch_bounds__(256) cg_update_dt_kernel(int Ls, int Vh, int nrhs, void* x, const void* rr,
+                                                             void* p, const double* alpha, const double* beta,
+                                                             const int* u2run, double cpd, double cmd,
+                                                             const double* mop) {
+  const int r = blockIdx.y;
+  if (u2run[r] == 0) return;  // uniform over the block
+  const ColLane cl = col_lane(Ls, Vh);
+  const FD f = {Ls, Vh, nrhs};
+  using RR = typename ST<PX>::R;
+  using RS = typename ST<PS>::R;
+  cx<RS> pv[12];
+  cx<RR> xv[12], rv[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    pv[c] = {RS(0), RS(0)};
+    rv[c] = {RR(0), RR(0)};
+  }
+  if (cl.live) {
+    ld_spinor<PS>(p, f, r, cl.s, cl.i, pv);
+    ld_spinor_nt<PR>(rr, f, r, cl.s, cl.i, rv);
+  }
+  dt_apply<RR, RL>(rv, cl.s, cl.g, Ls, (RR)cpd, (RR)cmd, (RR)mop[r]);
+  if (!cl.live) return;
+  ld_spinor_nt<PX>(x, f, r, cl.s, cl.i, xv);
+  const RR al = (RR)alpha[r], be = (RR)beta[r];
+  cx<RS> pn[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const cx<RR> pc = {(RR)pv[c].r, (RR)pv[c].i};
+    xv[c].r = fma(al, pc.r, xv[c].r);
+    xv[c].i = fma(al, pc.i, xv[c].i);
+    pn[c] = {(RS)fma(be, pc.r, rv[c].r), (RS)fma(be, pc.i, rv[c].i)};
+  }
+  st_spinor_nt<PX>(x, f, r, cl.s, cl.i, xv);
+  st_spinor<PS>(p, f, r, cl.s, cl.i, pn);
+}
+
+template <int PS, int PR>
+void launch_p_update_dt(const Geometry& g, const void* r, const void* p, void* pn, const double* alpha,
+                        const double* beta, const int* u2run, double* ahist, int nrhs, const DtArgs& dt,
+                        hipStream_t st) {
+  const int G = 64 / g.Ls;
+  dim3 grid((g.Vh + 4 * G - 1) / (4 * G), nrhs);
+  auto fn = g.Ls == 16 ? p_update_dt_kernel<PS, PR, 16> : p_update_dt_kernel<PS, PR, 0>;
+  hipLaunchKernelGGL(fn, grid, dim3(256), 0, st, g.Ls, g.Vh, nrhs, r, p, pn, alpha, beta, u2run, ahist, dt.cpd,
+                     dt.cmd, dt.mop);
+}
+
+template <int PS, int PX, int PR>
+void launch_cg_update_dt(const Geometry& g, void* x, const void* r, void* p, const double* alpha,
+                         const double* beta, const int* u2run, int nrhs, const DtArgs& dt, hipStream_t st) {
+  const int G = 64 / g.Ls;
+  dim3 grid((g.Vh + 4 * G - 1) / (4 * G), nrhs);
+  auto fn = g.Ls == 16 ? cg_update_dt_kernel<PS, PX, PR, 16> : cg_update_dt_kernel<PS, PX, PR, 0>;
+  hipLaunchKernelGGL(fn, grid, dim3(256), 0, st, g.Ls, g.Vh, nrhs, x, r, p, alpha, beta, u2run, dt.cpd, dt.cmd,
+                     dt.mop);
+}
+
 void launch_p_update(int ps, const Geometry& g, const void* r, const void* p, void* pn, const double* alpha,
-                     const double* beta, const int* u2run, double* ahist, int nrhs, hipStream_t st) {
+                     const double* beta, const int* u2run, double* ahist, int nrhs, const DtArgs& dt,
+                     hipStream_t st) {
+  if (dt.mop) {
+    if (ps == P64)
+      launch_p_update_dt<P64, P64>(g, r, p, pn, alpha, beta, u2run, ahist, nrhs, dt, st);
+    else if (ps == P32)
+      launch_p_update_dt<P32, P32>(g, r, p, pn, alpha, beta, u2run, ahist, nrhs, dt, st);
+    else
+      launch_p_update_dt<P16, P16>(g, r, p, pn, alpha, beta, u2run, ahist, nrhs, dt, st);
+    return;
+  }
   if (ps == P64)
     hipLaunchKernelGGL((p_update_kernel<P64, P64>), EOFA_EW_GRID, g.Ls, g.Vh, nrhs, r, p, pn, alpha, beta, u2run,
                        ahist);
@@ -1566,7 +1755,16 @@ void launch_x_flush(int ps, const Geometry& g, void* x, const void* ring, size_t
 }
 
 void launch_cg_update(int ps, const Geometry& g, void* x, const void* r, void* p, const double* alpha,
-                      const double* beta, const int* u2run, int nrhs, hipStream_t st) {
+                      const double* beta, const int* u2run, int nrhs, const DtArgs& dt, hipStream_t st) {
+  if (dt.mop) {
+    if (ps == P64)
+      launch_cg_update_dt<P64, P64, P64>(g, x, r, p, alpha, beta, u2run, nrhs, dt, st);
+    else if (ps == P32)
+      launch_cg_update_dt<P32, P32, P32>(g, x, r, p, alpha, beta, u2run, nrhs, dt, st);
+    else
+      launch_cg_update_dt<P16, P32, P16>(g, x, r, p, alpha, beta, u2run, nrhs, dt, st);
+    return;
+  }
   if (ps == P64)
     hipLaunchKernelGGL((cg_update_kernel<P64, P64, P64>), EOFA_EW_GRID, g.Ls, g.Vh, nrhs, x, r, p, alpha, beta,
                        u2run);
@@ -1636,32 +1834,46 @@ __device__ void finalize_step(int mode, double sum, const CgState& S, int r, dou
   }
 }
 
-__global__ void __launch_bounds__(256) finalize_kernel(int mode, const double* __restrict__ partial, int nblk,
-                                                         CgState S, double* out) {
+constexpr int FIN_THREADS = 1024, FIN_LOADS = 16;
+
+__global__ void __launch_bounds__(FIN_THREADS) finalize_kernel(int mode, const double* __restrict__ partial,
+                                                                 int nblk, CgState S, double* out) {
   const int r = blockIdx.x;
-  __shared__ double red[4];
-  // eight independent partial sums per thread, so the loads of one thread
-  // are in flight together instead of one memory latency after another
+  __shared__ double red[FIN_THREADS / 64];
+  // FIN_LOADS independent partial sums per thread: at the usual partial counts
+  // (one per hop work-group, 16384 at 16^3 x 32 x 16) every load of the block
+  // is in flight at once, so the sum costs one memory latency, not several
   const double* pr = partial + (size_t)r * nblk;
-  double t8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int j0 = threadIdx.x; j0 < nblk; j0 += 8 * 256) {
+  double acc[FIN_LOADS];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int j = j0 + k * 256;
-      if (j < nblk) t8[k] += pr[j];
+  for (int k = 0; k < FIN_LOADS; ++k) acc[k] = 0.0;
+  for (int j0 = threadIdx.x; j0 < nblk; j0 += FIN_LOADS * FIN_THREADS) {
+#pragma unroll
+    for (int k = 0; k < FIN_LOADS; ++k) {
+      const int j = j0 + k * FIN_THREADS;
+      if (j < nblk) acc[k] += pr[j];
     }
   }
-  double t = ((t8[0] + t8[1]) + (t8[2] + t8[3])) + ((t8[4] + t8[5]) + (t8[6] + t8[7]));
-  // per wave by lane exchange, then the four wave sums
+#pragma unroll
+  for (int w = FIN_LOADS / 2; w > 0; w >>= 1)
+#pragma unroll
+    for (int k = 0; k < w; ++k) acc[k] += acc[k + w];
+  double t = acc[0];
+  // per wave by lane exchange, then the wave sums in a fixed order
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
   __syncthreads();
-  if (threadIdx.x == 0) finalize_step(mode, (red[0] + red[1]) + (red[2] + red[3]), S, r, out);
+  if (threadIdx.x == 0) {
+    double sum = 0.0;
+#pragma unroll
+    for (int w = 0; w < FIN_THREADS / 64; ++w) sum += red[w];
+    finalize_step(mode, sum, S, r, out);
+  }
 }
 
 void launch_finalize(int mode, const double* partial, int nblk, int nrhs, CgState s, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(finalize_kernel, dim3(nrhs), dim3(256), 0, st, mode, partial, nblk, s, out);
+  hipLaunchKernelGGL(finalize_kernel, dim3(nrhs), dim3(FIN_THREADS), 0, st, mode, partial, nblk, s, out);
 }
 
 // ---------------------------------------------------------------------------

@@ -87,6 +87,10 @@ def lib():
         "eofa_heatbath_solve": ([_P, ctypes.c_double, ctypes.c_double, _I, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _P, _P,
                                  ctypes.POINTER(SolverParams), ctypes.POINTER(SolverStats), _P], _I),
+        "eofa_heatbath_poles": ([_P, ctypes.c_double, ctypes.c_double, _I, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_double), _P, _P, ctypes.POINTER(SolverParams),
+                                 ctypes.POINTER(SolverStats), _P], _I),
+        "eofa_forecast": ([_P, ctypes.POINTER(System), _P, _P, _I, _P, _P], _I),
         "eofa_fifth_matrix": ([ctypes.POINTER(Action), ctypes.POINTER(System), _I,
                                ctypes.POINTER(ctypes.c_double)], _I),
         "eofa_dhop_derivative": ([_P, _P, _P, _P, _P], _I),
@@ -262,6 +266,26 @@ class Context:
         if rc in (EOFA_ERR_INVALID, EOFA_ERR_HIP, EOFA_ERR_OOM):
             _check(rc)
         return rc, [s.as_dict() for s in stats]
+
+    def eofa_heatbath_poles(self, m1, m2, beta, eta, sol, params, pole_tol=None, stream=None):
+        """The 2 len(beta) pole solutions (LH then RH) into sol (canonical, [2 N_p, ...])."""
+        npol = len(beta)
+        b = (ctypes.c_double * npol)(*beta)
+        pt = None
+        if pole_tol is not None:
+            assert len(pole_tol) == 2 * npol
+            pt = (ctypes.c_double * (2 * npol))(*pole_tol)
+        stats = (SolverStats * (2 * npol))()
+        rc = lib().eofa_heatbath_poles(self._h, m1, m2, npol, b, pt, _p(eta), _p(sol), ctypes.byref(params),
+                                       stats, _stream(stream))
+        if rc in (EOFA_ERR_INVALID, EOFA_ERR_HIP, EOFA_ERR_OOM):
+            _check(rc)
+        return rc, [s.as_dict() for s in stats]
+
+    def eofa_forecast(self, system, rhs, prev, n_prev, guess, stream=None):
+        """Chronological guess for ``system`` over n_prev canonical fields ``prev``."""
+        _check(lib().eofa_forecast(self._h, make_systems([system]), _p(rhs), _p(prev), n_prev, _p(guess),
+                                   _stream(stream)))
 
     def eofa_dhop_derivative(self, a, b, y, stream=None):
         _check(lib().eofa_dhop_derivative(self._h, _p(a), _p(b), _p(y), _stream(stream)))

@@ -153,7 +153,8 @@ def test_pairs_and_solver_params_validation():
     assert rc == eofa.EOFA_ERR_INVALID
 
     for kw in (dict(form=2), dict(form=1, precond=1), dict(ring_slots=3), dict(ring_slots=32),
-               dict(ring_slots=-2), dict(ring_slots=16, check_every=8)):
+               dict(ring_slots=-2), dict(ring_slots=16, check_every=8), dict(waves=3), dict(waves=8),
+               dict(rhs_block=-1)):
         prm = eofa.make_params(**kw)
         rc = eofa.lib().eofa_cg_solve(dummy, sysl, dummy, ctypes.c_void_p(32), 1, ctypes.byref(prm), None, None)
         assert rc == eofa.EOFA_ERR_INVALID, kw
@@ -166,3 +167,10 @@ def test_pairs_and_solver_params_validation():
     rc = eofa.lib().eofa_force(dummy, ctypes.c_double(0.1), ctypes.c_double(1.0), dummy, ctypes.c_void_p(32),
                                ctypes.byref(prm), None, None)
     assert rc == eofa.EOFA_ERR_INVALID
+    rc = eofa.lib().eofa_heatbath_poles(dummy, ctypes.c_double(0.1), ctypes.c_double(1.0), 1, a, None, dummy,
+                                        ctypes.c_void_p(32), ctypes.byref(prm), None, None)
+    assert rc == eofa.EOFA_ERR_INVALID
+    # chronological forecast: 1..32 earlier solutions
+    for n_prev in (0, 33):
+        rc = eofa.lib().eofa_forecast(dummy, sysl, dummy, ctypes.c_void_p(64), n_prev, ctypes.c_void_p(32), None)
+        assert rc == eofa.EOFA_ERR_INVALID, n_prev

@@ -94,3 +94,27 @@ def test_ring_sizes_agree(setup, prec):
         assert rc in (eofa.EOFA_OK, eofa.EOFA_ERR_NOT_CONVERGED) and st[0]["iters"] == 37
         d = rel2(got, ref)
         assert d < (1e-13 if prec == eofa.FP64 else 1e-6), (R, d)
+
+
+@pytest.mark.parametrize("prec", [eofa.FP32, eofa.FP16S])
+def test_twelve_rhs_converged_ls12(prec):
+    """The batched workload's shape at reduced volume: 12 right-hand sides
+    (6 on H(m1), 6 on H(m2) - Delta_+(m1, m2) P_+, m1 = 0.01) at Ls = 12 (the
+    any-Ls kernels), inner CG below FP64 on the HIP-graph path with the
+    autotuned launch shape, FP64 defect correction to a true residual of 1e-10;
+    every solution re-measured by the oracle on the H form of its system."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    m1 = 0.01
+    act = Action((4, 4, 4, 4), 12, M5, B5, C5, (1, 1, 1, -1))
+    U = synth.gauge_field(act.dims, 0.5, seed=1011)
+    systems = [System(m1, m1, M2, 0.0, -1)] * 6 + [System(M2, m1, M2, -1.0, +1)] * 6
+    phis = synth.fermion(act.dims, act.Ls, seed=2011, nrhs=12)
+    ctx = eofa.Context(eofa.make_action(act.dims, act.Ls, M5, B5, C5), torch.from_numpy(U).cuda())
+    rc, st, got = solve(ctx, systems, phis, tol=1e-10, inner_prec=prec, use_graph=1, check_every=16)
+    assert rc == eofa.EOFA_OK, st
+    for r, s in enumerate(systems):
+        assert st[r]["converged"] == 1 and st[r]["true_resid"] <= 1e-10
+        res = np.sqrt(norm2(H_system(act, U, s, got[r]) - phis[r]) / norm2(phis[r]))
+        assert res <= 1.05e-10, (r, res)
+    ctx.close()

@@ -13,7 +13,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 from oracle import action as oaction, eo, site
-from oracle.dwf import Action, System, Dtilde_op, H_system, apply_s
+from oracle.dwf import Action, System, Dtilde_op, H_system, apply_s, g5R5
 from oracle import fifth
 from oracle.lattice import hop, restrict, norm2
 from paper_1706_05843_amd import eofa, synth
@@ -198,19 +198,51 @@ def c1ctx():
     return eofa.Context(eofa.make_action(act.dims, act.Ls, M5, B5, C5, act.bc), dev(U))
 
 
+_FLOOR = {}
+
+
+def noise_floor(name, iters, draws=2):
+    """How far the oracle's own mirror-mode solve moves after ``iters`` CGNR
+    steps when every Schur-operator application is perturbed by half an ulp
+    of relative noise (2^-53, independent per entry): the reproducibility
+    limit of the FP64 recurrence itself. Largest over ``draws`` seeds of the
+    solution difference and of the residual-space difference
+    |(H + beta Delta P)(psi_noisy - psi)| / |phi|."""
+    key = (name, iters)
+    if key not in _FLOOR:
+        act, U, phi, out = oracle_c1(name)
+        sys_ = SYSTEMS[name]
+        S = eo.SchurSystem(act, U, sys_)
+        b = g5R5(phi)
+        bt = S.schur_source(b)
+        ref = eo.solve_mirror(act, U, sys_, phi, iters=iters)["psi"]
+        worst_d, worst_r = 0.0, 0.0
+        for seed in range(draws):
+            rng = np.random.default_rng(7 + seed)
+
+            def noisy(f):
+                def g(x):
+                    y = f(x)
+                    return y * (1.0 + 2.0 ** -53 * rng.standard_normal(y.shape))
+                return g
+            xo, _, _ = eo.cgnr(noisy(S.mhat), noisy(S.mhat_adj), bt, iters=iters)
+            psi = Dtilde_op(act, sys_.m_op, S.reconstruct(xo, b))
+            worst_d = max(worst_d, rel2(psi, ref))
+            worst_r = max(worst_r, np.sqrt(norm2(H_system(act, U, sys_, psi - ref)) / norm2(phi)))
+        _FLOOR[key] = (worst_d, worst_r)
+    return _FLOOR[key]
+
+
 @pytest.mark.parametrize("name", list(SYSTEMS))
 def test_cg_mirror_mode_fp64(c1ctx, name):
-    """Fixed iteration count: the same recurrences as the oracle, 1e-12.
+    """Fixed iteration count: the same recurrences as the oracle.
 
-    40 iterations: solution difference <= 1e-12 relative for every system.
-    The oracle's converged count: the residual-space difference
-    |(H + beta Delta P)(psi_gpu - psi_oracle)| / |phi| <= 1e-12 for every
-    system, and the solution difference <= 1e-12 for the unshifted and
-    heatbath systems. For the shifted system (H(m2) - Delta_+ P_+) the late
-    CGNR steps amplify rounding by ~1e4-1e5 (oracle against itself with 1-ulp
-    noise per operator, five draws: 5e-12 .. 1.4e-11 in the solution and
-    6e-12 .. 1.6e-11 in residual space at 116 iterations), so at its
-    converged count both differences are bounded by 1e-10 instead."""
+    40 iterations: solution and residual-space differences <= 1e-12 for
+    every system. The oracle's converged count: 1e-12 for the unshifted and
+    heatbath systems; for the shifted system (H(m2) - Delta_+ P_+) the late
+    CGNR steps amplify rounding by ~1e4-1e5, so there both differences are
+    bounded by 3x the oracle's own spread under half-ulp noise per operator
+    application (noise_floor; measured 5e-12 .. 1.4e-11), at least 1e-12."""
     act, U, phi, out = oracle_c1(name)
     for iters in (40, out["iters"]):
         ref = out["psi"] if iters == out["iters"] else eo.solve_mirror(act, U, SYSTEMS[name], phi, iters=iters)["psi"]
@@ -220,9 +252,13 @@ def test_cg_mirror_mode_fp64(c1ctx, name):
         got = host(psi)[0]
         d = rel2(got, ref)
         rdiff = np.sqrt(norm2(H_system(act, U, SYSTEMS[name], got - ref)) / norm2(phi))
-        bound = 1e-10 if (iters == out["iters"] and name == "chi2") else 1e-12
-        assert rdiff < bound, (iters, rdiff, bound)
-        assert d < bound, (iters, d, bound)
+        bd, br = 1e-12, 1e-12
+        if iters == out["iters"] and name == "chi2":
+            fd, fr = noise_floor(name, iters)
+            bd, br = max(1e-12, 3.0 * fd), max(1e-12, 3.0 * fr)
+            print(f"chi2 at {iters} iterations: gpu {d:.3e} / {rdiff:.3e}, oracle noise floor {fd:.3e} / {fr:.3e}")
+        assert rdiff < br, (iters, rdiff, br)
+        assert d < bd, (iters, d, bd)
 
 
 @pytest.mark.parametrize("name", list(SYSTEMS))
@@ -242,6 +278,27 @@ def test_cg_converged(c1ctx, name, prec):
     assert rel2(got, out["psi"]) < 1e-7
 
 
+@pytest.mark.parametrize("prec", [eofa.FP16S, eofa.FP32])
+def test_wide_range_source(c1ctx, prec):
+    """A source whose 5D sites are scaled by 10^u, u uniform in [-20, 30]
+    (entries up to ~1e30, 50 orders of magnitude between sites): FP16 values
+    with one FP32 scale per site hold every site in range (the FP32 inner
+    solution and the FP64 outer loop too), and the shifted system still
+    reaches an FP64 true residual of 1e-10, re-measured by the oracle."""
+    act, U, phi, _ = oracle_c1("chi2")
+    rng = np.random.default_rng(2300)
+    scale = 10.0 ** rng.uniform(-20.0, 30.0, size=phi.shape[:-2])
+    src = phi * scale[..., None, None]
+    psi = torch.zeros(c1ctx.full_shape(1), dtype=torch.complex128, device="cuda")
+    rc, st = c1ctx.eofa_cg_solve([SYSTEMS["chi2"]], dev(src[None]), psi,
+                                 eofa.make_params(tol=1e-10, inner_prec=prec))
+    assert rc == eofa.EOFA_OK and st[0]["converged"] == 1, st
+    got = host(psi)[0]
+    assert np.all(np.isfinite(got)) and np.abs(got).max() > 1e28
+    res = np.sqrt(norm2(H_system(act, U, SYSTEMS["chi2"], got) - src) / norm2(src))
+    assert res <= 1.05e-10, res
+
+
 def test_cg_batched_equals_single(c1ctx):
     """Three different systems in one batched solve = three single solves."""
     names = list(SYSTEMS)
@@ -258,52 +315,96 @@ def test_cg_batched_equals_single(c1ctx):
         assert rel2(batched[r], host(one)[0]) < 1e-14
 
 
-def test_heatbath_matches_oracle(c1ctx):
-    """eqn eofa_heatbath: 2 N_p batched solves on the GPU vs the oracle formula."""
-    act, U, _, _ = oracle_c1("chi1")
-    eta = synth.fermion(act.dims, act.Ls, seed=2100)
-    alpha = [0.35, 0.2, 0.9]
-    beta = [0.05, 2.0]
+HB_ALPHA, HB_BETA = [0.35, 0.2, 0.9], [0.05, 2.0]
+_HB = {}
 
-    def solve(sys, rhs):
-        return eo.solve_mirror(act, U, sys, rhs, tol=1e-12)["psi"]
 
-    ref = oaction.heatbath(act, M1, M2, alpha, beta, eta, solve)
+def oracle_heatbath():
+    """eqn eofa_heatbath by the oracle (mirror-mode solves at 1e-12) for
+    HB_ALPHA, HB_BETA and eta (seed 2100) at the small workload."""
+    if "phi" not in _HB:
+        act, U, _, _ = oracle_c1("chi1")
+        eta = synth.fermion(act.dims, act.Ls, seed=2100)
+
+        def solve(sys_, rhs):
+            return eo.solve_mirror(act, U, sys_, rhs, tol=1e-12)["psi"]
+
+        _HB["eta"] = eta
+        _HB["phi"] = oaction.heatbath(act, M1, M2, HB_ALPHA, HB_BETA, eta, solve)
+    return _HB["eta"], _HB["phi"]
+
+
+@pytest.mark.parametrize("use_guess", [0, 1])
+def test_heatbath_matches_oracle(c1ctx, use_guess):
+    """eqn eofa_heatbath on the GPU vs the oracle formula at the same alpha,
+    beta and eta: all 2 N_p systems batched (use_guess = 0), or the poles of
+    each side in sequence from chronological forecasts (Sec. VI B)."""
+    eta, ref = oracle_heatbath()
     phi = torch.zeros(c1ctx.full_shape(1), dtype=torch.complex128, device="cuda")
-    prm = eofa.make_params(tol=1e-11)
-    rc, st = c1ctx.eofa_heatbath_solve(M1, M2, alpha, beta, dev(eta[None]), phi, prm)
+    prm = eofa.make_params(tol=1e-11, use_guess=use_guess)
+    rc, st = c1ctx.eofa_heatbath_solve(M1, M2, HB_ALPHA, HB_BETA, dev(eta[None]), phi, prm)
     assert rc == eofa.EOFA_OK
     assert all(s["converged"] for s in st)
     assert rel2(host(phi)[0], ref) < 1e-9
 
 
 def test_heatbath_forecast_and_pole_tol(c1ctx):
-    """Poles solved one after another from chronological forecasts (Sec. VI B)
-    give the batched phi with fewer iterations; per-pole tolerances are met."""
+    """Sec. VI B: poles solved one after another from chronological forecasts
+    need fewer iterations than the batched solve (the first pole of each side
+    has no forecast), and per-pole tolerances are met: every pole solution
+    from eofa_heatbath_poles is re-measured by the oracle on the H form of its
+    system, (H(m_op) + beta Delta_chi P_chi) y = Omega P eta."""
     act, U, _, _ = oracle_c1("chi1")
-    eta = dev(synth.fermion(act.dims, act.Ls, seed=2101)[None])
-    alpha = [0.35, 0.2, 0.3, 0.5, 0.9]
+    eta_h = synth.fermion(act.dims, act.Ls, seed=2101)
+    eta = dev(eta_h[None])
     beta = [0.01, 0.1, 0.5, 2.0]
-    ph_b = torch.zeros(c1ctx.full_shape(1), dtype=torch.complex128, device="cuda")
-    rc, st_b = c1ctx.eofa_heatbath_solve(M1, M2, alpha, beta, eta, ph_b, eofa.make_params(tol=1e-11))
+    n = len(beta)
+    sol_b = torch.zeros(c1ctx.full_shape(2 * n), dtype=torch.complex128, device="cuda")
+    rc, st_b = c1ctx.eofa_heatbath_poles(M1, M2, beta, eta, sol_b, eofa.make_params(tol=1e-11))
     assert rc == eofa.EOFA_OK
-    ph_f = torch.zeros_like(ph_b)
-    rc, st_f = c1ctx.eofa_heatbath_solve(M1, M2, alpha, beta, eta, ph_f,
-                                          eofa.make_params(tol=1e-11, use_guess=1))
+    sol_f = torch.zeros_like(sol_b)
+    rc, st_f = c1ctx.eofa_heatbath_poles(M1, M2, beta, eta, sol_f, eofa.make_params(tol=1e-11, use_guess=1))
     assert rc == eofa.EOFA_OK and all(s["converged"] for s in st_f)
-    assert rel2(host(ph_f)[0], host(ph_b)[0]) < 1e-9
     it_b, it_f = [s["iters"] for s in st_b], [s["iters"] for s in st_f]
     print("heatbath iterations per pole: batched", it_b, "forecast", it_f)
-    n = len(beta)
-    assert it_f[0] == it_b[0] and it_f[n] == it_b[n]  # first pole of each side: no forecast
+    assert it_f[0] == it_b[0] and it_f[n] == it_b[n]
     assert sum(it_f) < sum(it_b)
     ptol = [1e-6, 1e-8, 1e-10, 1e-11, 1e-7, 1e-9, 1e-10, 1e-11]
-    ph_t = torch.zeros_like(ph_b)
-    rc, st_t = c1ctx.eofa_heatbath_solve(M1, M2, alpha, beta, eta, ph_t, eofa.make_params(tol=1e-11),
-                                          pole_tol=ptol)
+    sol_t = torch.zeros_like(sol_b)
+    rc, st_t = c1ctx.eofa_heatbath_poles(M1, M2, beta, eta, sol_t, eofa.make_params(tol=1e-11, use_guess=1),
+                                         pole_tol=ptol)
     assert rc == eofa.EOFA_OK
+    W = oaction._omega_ops(act)
+    rhs = [W["Wm"](eta_h), W["Wp"](eta_h)]
+    for sols, tols in ((host(sol_f), [1e-11] * (2 * n)), (host(sol_t), ptol)):
+        for r in range(2 * n):
+            l, side = r % n, r // n
+            sys_ = oaction.heatbath_systems(M1, M2, beta[l])[side]
+            res = np.sqrt(norm2(H_system(act, U, sys_, sols[r]) - rhs[side]) / norm2(rhs[side]))
+            assert res <= 1.05 * tols[r], (r, res, tols[r])
     for s, t in zip(st_t, ptol):
         assert s["converged"] == 1 and s["true_resid"] <= t
+
+
+def test_forecast_matches_oracle(c1ctx):
+    """eofa_forecast against oracle.action.chronological_guess (Sec. VI B) on
+    the same right-hand side and the same earlier fields (three random fields
+    and one oracle solution of a neighbouring pole), for a heatbath system."""
+    act, U, _, _ = oracle_c1("chi1")
+    sys_ = oaction.heatbath_systems(M1, M2, 0.3)[0]
+    eta = synth.fermion(act.dims, act.Ls, seed=2102)
+    rhs = oaction._omega_ops(act)["Wm"](eta)
+    prev = [synth.fermion(act.dims, act.Ls, seed=2110 + k) for k in range(3)]
+    near = oaction.heatbath_systems(M1, M2, 0.25)[0]
+    prev.append(eo.solve_mirror(act, U, near, rhs, tol=1e-10)["psi"])
+    ref = oaction.chronological_guess(lambda x: H_system(act, U, sys_, x), rhs, prev)
+    guess = torch.zeros(c1ctx.full_shape(1), dtype=torch.complex128, device="cuda")
+    c1ctx.eofa_forecast(sys_, dev(rhs[None]), dev(np.stack(prev)), len(prev), guess)
+    got = host(guess)[0]
+    assert rel2(got, ref) < 1e-10, rel2(got, ref)
+    # a guess from the neighbouring pole's solution is a good start
+    res = np.sqrt(norm2(H_system(act, U, sys_, got) - rhs) / norm2(rhs))
+    assert res < 0.2, res
 
 
 # --- errors ----------------------------------------------------------------------
