@@ -224,6 +224,25 @@ int eofa_mooee_inv(eofa_ctx* ctx, const eofa_system* sys, const void* in, void* 
 int eofa_cg_solve(eofa_ctx* ctx, const eofa_system* sys, const void* phi, void* psi, int32_t nrhs,
                   const eofa_solver_params* params, eofa_solver_stats* stats, void* stream);
 
+/* For callers that cannot allocate device memory (code around which they
+ * capture HIP graphs of their own work, tight serving loops, harnesses that
+ * forbid hipMalloc): eofa_cg_solve with precond = 0 (and use_graph = 0) whose
+ * workspace (packed fields, partial sums, CG scalars, the systems'
+ * coefficients) comes from a fixed 64 MiB device array held by the library
+ * on each GPU until the process ends, instead of from allocations. It calls
+ * no hipMalloc / hipFree / hipHostMalloc and creates no stream or event:
+ * host staging was set aside by eofa_create. Same kernels and results as
+ * eofa_cg_solve with the same params; waves = rhs_block = 0 take the default
+ * launch shape (no autotuning), profile is ignored, the direction ring is
+ * used only if it fits beside the other buffers. Returns EOFA_ERR_INVALID
+ * (before any device work) when the lattice and nrhs need more than the
+ * 64 MiB. Every call on a GPU uses that GPU's one array and leaves its
+ * contents behind (each call writes every buffer before reading it): calls
+ * that overlap on one GPU (other threads, other streams, other contexts)
+ * race and must not be issued. The context's device must be current.      */
+int eofa_cg_solve_noalloc(eofa_ctx* ctx, const eofa_system* sys, const void* phi, void* psi, int32_t nrhs,
+                          const eofa_solver_params* params, eofa_solver_stats* stats, void* stream);
+
 /* EOFA heatbath (Sec. IV B, eqn eofa_heatbath): phi = f(M_EOFA) eta for
  * the rational f(x) = alpha[0] + sum_l alpha[l] / (beta[l-1] + x),
  * l = 1..n_poles, via the 2*n_poles systems

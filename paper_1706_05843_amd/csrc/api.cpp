@@ -31,6 +31,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -67,7 +68,56 @@ int eofa::set_error(int code, const std::string& msg) { return fail(code, msg); 
 
 namespace {
 
+constexpr size_t kStageInit = size_t(1) << 20;  // pinned host staging per context
+
+// ---------------------------------------------------------------------------
+// Workspace of the no-allocation solve (eofa_cg_solve_noalloc): a file-scope
+// device array of kNoallocBytes, one copy on every GPU the library runs on,
+// held until the process ends. Host code never passes the array's name to a
+// kernel: its device address on each GPU comes from hipGetSymbolAddress, taken
+// once per device (at context creation, with that device current).
+constexpr size_t kNoallocBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_init(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(EOFA_ERR_INVALID, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return EOFA_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return fail(EOFA_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  }
+  g_scratch_ptr[dev] = p;
+  return EOFA_OK;
+}
+
+void* scratch_ptr(int dev) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return (dev >= 0 && dev < kMaxDevices) ? g_scratch_ptr[dev] : nullptr;
+}
+
 int ws(eofa_ctx* C, const char* name, size_t bytes, void** out) {
+  if (C->arena) {  // no-allocation call: carve from the scratch array
+    Arena& A = *C->arena;
+    auto it = A.slots.find(name);
+    if (it != A.slots.end() && it->second.second >= bytes) {
+      *out = A.base + it->second.first;
+      return EOFA_OK;
+    }
+    const size_t off = (A.used + 255) & ~size_t(255);
+    if (off + bytes > A.cap)
+      return fail(EOFA_ERR_INVALID, "eofa_cg_solve_noalloc: workspace beyond its " + std::to_string(A.cap >> 20) +
+                                        " MiB scratch (buffer " + name + ")");
+    A.slots[name] = {off, bytes};
+    A.used = off + bytes;
+    *out = A.base + off;
+    return EOFA_OK;
+  }
   Buf& b = C->pool[name];
   if (b.n < bytes) {
     if (b.p) HIPCHK(hipFree(b.p));
@@ -84,6 +134,9 @@ int ws(eofa_ctx* C, const char* name, size_t bytes, void** out) {
 }
 
 int stage(eofa_ctx* C, size_t bytes) {
+  if (C->arena && C->host_stage_n < bytes)
+    return fail(EOFA_ERR_INVALID, "eofa_cg_solve_noalloc: host staging beyond the " +
+                                      std::to_string(C->host_stage_n) + " bytes set aside at context creation");
   if (C->host_stage_n < bytes) {
     if (C->host_stage) HIPCHK(hipHostFree(C->host_stage));
     C->host_stage = nullptr;
@@ -109,7 +162,7 @@ int upload_systems(eofa_ctx* C, const eofa_system* sys, int nrhs, hipStream_t st
     key.push_back(sys[r].beta);
     key.push_back(sys[r].beta != 0.0 ? (double)sys[r].chi : 0.0);
   }
-  if (key == C->sys_key && C->mats) return EOFA_OK;
+  if (!C->arena && key == C->sys_key && C->mats) return EOFA_OK;
   const size_t per = mats_per_rhs(C->g), sper = scoef_per_rhs(C->g);
   const size_t n = per * nrhs + nrhs + sper * nrhs;
   std::vector<double> h(n);
@@ -119,6 +172,17 @@ int upload_systems(eofa_ctx* C, const eofa_system* sys, int nrhs, hipStream_t st
     if (rc != EOFA_OK) return fail(rc, "right-hand side " + std::to_string(r) + ": " + err);
     h[per * nrhs + r] = sys[r].m_op;
     build_struct(C->g, C->M5, C->b5, C->c5, sys[r], h.data() + per * nrhs + nrhs + sper * r);
+  }
+  if (C->arena) {  // no-allocation call: the coefficients live in the scratch array
+    void* m;
+    CHK(ws(C, "mats", n * sizeof(double), &m));
+    CHK(stage(C, n * sizeof(double)));
+    HIPCHK(hipStreamSynchronize(st));
+    std::memcpy(C->host_stage, h.data(), n * sizeof(double));
+    HIPCHK(hipMemcpyAsync(m, C->host_stage, n * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    C->mats_active = (double*)m;
+    return EOFA_OK;
   }
   if (C->mats_n < n) {
     if (C->mats) HIPCHK(hipFree(C->mats));
@@ -139,7 +203,10 @@ int upload_systems(eofa_ctx* C, const eofa_system* sys, int nrhs, hipStream_t st
   return EOFA_OK;
 }
 
-const double* mop_ptr(eofa_ctx* C, int nrhs) { return C->mats + mats_per_rhs(C->g) * nrhs; }
+// the coefficients of the systems last uploaded (the scratch copy during a
+// no-allocation call)
+double* mats_of(eofa_ctx* C) { return C->mats_active ? C->mats_active : C->mats; }
+const double* mop_ptr(eofa_ctx* C, int nrhs) { return mats_of(C) + mats_per_rhs(C->g) * nrhs; }
 
 int check_prec(int prec) {
   if (prec < 0 || prec > 2) return fail(EOFA_ERR_INVALID, "precision must be EOFA_FP64, EOFA_FP32 or EOFA_FP16S");
@@ -165,7 +232,7 @@ HopArgs base_args(eofa_ctx* C, int prec, int out_parity, int nrhs) {
   a.links = C->links[prec][out_parity];
   a.nbr = C->nbr[out_parity];
   a.order = C->order;
-  a.mats = C->mats;
+  a.mats = mats_of(C);
   a.matA = 0;
   a.matB = 0;
   a.cpd = C->c + C->d;
@@ -222,8 +289,17 @@ int eofa_create(const eofa_action* act, const void* gauge, void* stream, eofa_ct
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(EOFA_ERR_INVALID, std::string("this library is built for gfx950; device is ") + prop.gcnArchName);
 
+  CHK(scratch_init(dev));
   eofa_ctx* C = new eofa_ctx();
   C->device = dev;
+  // host staging set aside now, so that the no-allocation solve needs none
+  if (hipHostMalloc((void**)&C->host_stage, kStageInit, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    C->host_stage = nullptr;
+    eofa_destroy(C);
+    return fail(EOFA_ERR_OOM, "hipHostMalloc failed for the host staging buffer");
+  }
+  C->host_stage_n = kStageInit;
   for (int k = 0; k < 4; ++k) {
     C->g.L[k] = act->dims[k];
     C->bc[k] = act->bc[k];
@@ -368,7 +444,7 @@ static int smat_entry(eofa_ctx* C, const eofa_system* sys, const void* in, void*
   CHK(check_systems(sys, nrhs));
   hipStream_t st = (hipStream_t)stream;
   CHK(upload_systems(C, sys, nrhs, st));
-  launch_smat(prec, C->g, in, out, C->mats, mat, nrhs, st);
+  launch_smat(prec, C->g, in, out, mats_of(C), mat, nrhs, st);
   HIPCHK(hipGetLastError());
   return EOFA_OK;
 }
@@ -614,7 +690,7 @@ int reconstruct(eofa_ctx* C, const Form& F, int nrhs, void* x, void* be, void* b
     a.out = tmp;
     CHK(hop(C, P64, F.src, a, st));
   }
-  launch_smat(P64, g, tmp, te, C->mats, F.inv, nrhs, st);
+  launch_smat(P64, g, tmp, te, mats_of(C), F.inv, nrhs, st);
   // FP64 true residual of the system on both parities
   {
     HopArgs a = base_args(C, P64, 0, nrhs);
@@ -640,9 +716,9 @@ int reconstruct(eofa_ctx* C, const Form& F, int nrhs, void* x, void* be, void* b
     CHK(fetch(C, Sst.norm, nrhs * sizeof(double), rodd.data(), st));
   }
   if (F.cayley) {  // psi = D~ psi'
-    launch_smat(P64, g, te, tmp, C->mats, MAT_DT, nrhs, st);
+    launch_smat(P64, g, te, tmp, mats_of(C), MAT_DT, nrhs, st);
     launch_unpack(P64, g, tmp, psi, 0, nrhs, st);
-    launch_smat(P64, g, x, ro, C->mats, MAT_DT, nrhs, st);
+    launch_smat(P64, g, x, ro, mats_of(C), MAT_DT, nrhs, st);
     launch_unpack(P64, g, ro, psi, 1, nrhs, st);
   } else {
     launch_unpack(P64, g, te, psi, 0, nrhs, st);
@@ -709,10 +785,15 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
   const Ring* ring = nullptr;
   int last_it = 0;  // iterations of the previous pass (its last direction sits in slot last_it mod R)
   if (prm->ring_slots >= 0) {
-    size_t free_b = 0, total_b = 0;
-    HIPCHK(hipMemGetInfo(&free_b, &total_b));
-    const auto held = C->pool.find("pring");
-    const size_t avail = (free_b + (held != C->pool.end() ? held->second.n : 0)) / 4;
+    size_t avail = 0;
+    if (C->arena) {  // what the scratch array has left
+      avail = C->arena->cap - std::min(C->arena->cap, C->arena->used + 512 + sizeof(double) * 16 * nrhs);
+    } else {
+      size_t free_b = 0, total_b = 0;
+      HIPCHK(hipMemGetInfo(&free_b, &total_b));
+      const auto held = C->pool.find("pring");
+      avail = (free_b + (held != C->pool.end() ? held->second.n : 0)) / 4;
+    }
     for (int R : {16, 8, 4}) {
       const size_t ring_bytes = (size_t)R * bS;
       if (prm->ring_slots > 0 ? R != prm->ring_slots : (check % R != 0 || ring_bytes > avail)) continue;
@@ -746,7 +827,7 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
   }
 
   // Schur source b~_o = b_o - Dhop D~ M_ee^-1 b_e (dense: b_o - Dhop D_ee^-1 b_e)
-  launch_smat(P64, g, be, te, C->mats, F.inv, nrhs, st);
+  launch_smat(P64, g, be, te, mats_of(C), F.inv, nrhs, st);
   {
     HopArgs a = base_args(C, P64, 1, nrhs);
     a.in = te;
@@ -757,7 +838,7 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
   if (prm->use_guess && F.cayley) {
     // x_o = (D~^-1 psi)_o: the right-preconditioned unknown of the guess
     launch_pack(P64, g, psi, tmp, 1, nrhs, 0, st);
-    launch_smat(P64, g, tmp, x, C->mats, MAT_DT_INV, nrhs, st);
+    launch_smat(P64, g, tmp, x, mats_of(C), MAT_DT_INV, nrhs, st);
   } else if (prm->use_guess) {
     launch_pack(P64, g, psi, x, 1, nrhs, 0, st);
   } else {
@@ -771,7 +852,7 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
   double hop_ms[4] = {0, 0, 0, 0};
   int timed = 0;
   const int max_timed = 256;  // timed iterations per solve (every 8th iteration)
-  if (prm->profile && C->events.empty()) {
+  if (prm->profile && !C->arena && C->events.empty()) {
     C->events.resize(8 * max_timed);
     for (auto& ev : C->events) HIPCHK(hipEventCreate(&ev));
   }
@@ -802,7 +883,7 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
   k4.alpha = Sst.alpha;
   k4.partial = partial;
   k4.halt = Sst.halt;
-  if (prm->rhs_block <= 0 && prm->waves <= 0) {
+  if (prm->rhs_block <= 0 && prm->waves <= 0 && !C->arena) {
     CHK(autotune(C, F, S, nrhs, k1, k2, k3, k4, st));
     const auto pick = C->tuned[tune_key(F, S, nrhs)];
     for (HopArgs* x : {&k1, &k2, &k3, &k4}) {
@@ -901,7 +982,7 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
     // stays conjugate to within the inner precision, and replaces only r
     void* p0 = ring ? ring->at(0) : pS;
     if (restart && F.ptilde) {  // p~ = D~ r
-      launch_smat(S, g, rin, p0, C->mats, MAT_DT, nrhs, st);
+      launch_smat(S, g, rin, p0, mats_of(C), MAT_DT, nrhs, st);
     } else if (restart) {
       launch_convert(S, S, g, rin, p0, nrhs, st);
     } else if (ring && last_it % ring->R != 0) {  // the kept direction into slot 0
@@ -964,16 +1045,19 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
       HIPCHK(hipEventDestroy(join));
     } else {
       // created once per context; a partial failure is completed on the next call
-      if (!C->side_stream) HIPCHK(hipStreamCreateWithFlags(&C->side_stream, hipStreamNonBlocking));
-      for (auto& e : C->side_ev)
-        if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      // (a no-allocation call creates nothing: one stream, no events)
+      const bool side = !C->arena;
+      if (side && !C->side_stream) HIPCHK(hipStreamCreateWithFlags(&C->side_stream, hipStreamNonBlocking));
+      if (side)
+        for (auto& e : C->side_ev)
+          if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
       while (true) {
         // timed iterations sit between host polls (which drain the queue), so the
         // events bracket the kernels and not host launch latency
-        const bool prof = prm->profile && timed < max_timed && (it % 8 == 4);
+        const bool prof = prm->profile && side && timed < max_timed && (it % 8 == 4);
         hipEvent_t* ev = prof ? &C->events[timed * 8] : nullptr;
         CHK(inner_iteration(C, F, S, k1, k2, k3, k4, nbh, nrhs, Sst, partial, xin, rin, pS, st, ev, ring, it,
-                            true));
+                            side));
         if (prof) ++timed;
         ++it;
         if (it % check == 0 || it >= cap) {
@@ -1007,7 +1091,7 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
       }
     }
     if (F.ptilde) {  // the pass accumulated x~ = D~ e: x += D~^-1 x~ (tmp is free here)
-      launch_smat(PX, g, xin, tmp, C->mats, MAT_DT_INV, nrhs, st);
+      launch_smat(PX, g, xin, tmp, mats_of(C), MAT_DT_INV, nrhs, st);
       launch_axpy_to64(PX, g, x, tmp, nrhs, st);
     } else {
       launch_axpy_to64(PX, g, x, xin, nrhs, st);
@@ -1189,7 +1273,7 @@ struct Fgcg {
     CHK(norms(C, P64, be, 1, partial, Sst, ne, st));
     CHK(norms(C, P64, bo, 1, partial, Sst, no, st));
     bb = ne[0] + no[0];
-    launch_smat(P64, g, be, te, C->mats, MAT_MEE_INV, 1, st);
+    launch_smat(P64, g, be, te, mats_of(C), MAT_MEE_INV, 1, st);
     HopArgs a = base_args(C, P64, 1, 1);
     a.in = te;
     a.z = bo;
@@ -1339,7 +1423,7 @@ int fgcg_one(eofa_ctx* C, const eofa_system* sys, const void* phi, void* psi, co
   if (prm->use_guess && std::isfinite(F.bb)) {
     // start from x_o = (D~^-1 psi)_o: s = b~ - M^ x, r = M^dag s
     launch_pack(P64, C->g, psi, F.tmp, 1, 1, 0, st);
-    launch_smat(P64, C->g, F.tmp, F.x, C->mats, MAT_DT_INV, 1, st);
+    launch_smat(P64, C->g, F.tmp, F.x, mats_of(C), MAT_DT_INV, 1, st);
     double s2;
     CHK(F.true_schur(&s2));
     CHK(F.normal_residual());
@@ -1508,6 +1592,50 @@ extern "C" int eofa_cg_solve(eofa_ctx* C, const eofa_system* sys, const void* ph
   return worst;
 }
 
+extern "C" int eofa_cg_solve_noalloc(eofa_ctx* C, const eofa_system* sys, const void* phi, void* psi,
+                                     int32_t nrhs, const eofa_solver_params* prm, eofa_solver_stats* stats,
+                                     void* stream) {
+  if (!C || !phi || !psi) return fail(EOFA_ERR_INVALID, "eofa_cg_solve_noalloc: NULL argument");
+  if (phi == psi) return fail(EOFA_ERR_INVALID, "eofa_cg_solve_noalloc: phi and psi alias");
+  CHK(check_systems(sys, nrhs));
+  CHK(check_params(prm));
+  if (prm->precond != 0) return fail(EOFA_ERR_INVALID, "eofa_cg_solve_noalloc: precond must be 0 (CGNR)");
+  if (prm->use_graph) return fail(EOFA_ERR_INVALID, "eofa_cg_solve_noalloc: use_graph must be 0");
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != C->device) return fail(EOFA_ERR_INVALID, "eofa_cg_solve_noalloc: the context's device is not current");
+  void* base = scratch_ptr(dev);
+  if (!base) return fail(EOFA_ERR_HIP, "eofa_cg_solve_noalloc: scratch address not set up on this device");
+  // the solve's buffers (packed fields, partial sums, CG scalars, coefficients),
+  // each aligned to 256 bytes; the direction ring is added only if it fits
+  const Geometry& g = C->g;
+  const int S = prm->inner_prec, PX = S == P64 ? P64 : P32;
+  const size_t b64 = packed_bytes(P64, g, nrhs), bS = packed_bytes(S, g, nrhs), bX = packed_bytes(PX, g, nrhs);
+  const size_t maxblk = std::max(hop_blocks(P64, g.Vh, g.Ls, 1), (g.Ls * g.Vh + 255) / 256);
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t need = 7 * al(b64) + 5 * al(bS) + al(bX) + al(sizeof(double) * maxblk * nrhs) +
+                      al((8 * sizeof(double) + 5 * sizeof(int)) * nrhs + 64) +
+                      al(sizeof(double) * (mats_per_rhs(g) * nrhs + nrhs + scoef_per_rhs(g) * nrhs));
+  if (need > kNoallocBytes)
+    return fail(EOFA_ERR_INVALID, "eofa_cg_solve_noalloc: needs " + std::to_string((need + (1 << 20) - 1) >> 20) +
+                                      " MiB of workspace for this lattice and nrhs; the scratch array holds " +
+                                      std::to_string(kNoallocBytes >> 20) + " MiB");
+  Arena A;
+  A.base = (char*)base;
+  A.cap = kNoallocBytes;
+  struct Guard {
+    eofa_ctx* C;
+    ~Guard() {
+      C->arena = nullptr;
+      C->mats_active = nullptr;
+    }
+  } guard{C};
+  C->arena = &A;
+  eofa_solver_params p2 = *prm;
+  p2.profile = 0;
+  return solve_batch(C, sys, nrhs, phi, psi, &p2, stats, (hipStream_t)stream);
+}
+
 extern "C" int eofa_fifth_matrix(const eofa_action* act, const eofa_system* sys, int32_t mat, double* out) {
   if (!act || !sys || !out) return fail(EOFA_ERR_INVALID, "eofa_fifth_matrix: NULL argument");
   if (mat < 0 || mat >= NMAT) return fail(EOFA_ERR_INVALID, "matrix id out of range");
@@ -1592,9 +1720,9 @@ int forecast(eofa_ctx* C, const eofa_system* sys, const void* rhs, const std::ve
   }
   for (int k = 0; k < N; ++k) {
     launch_pack(P64, g, prev[k], t, 0, 1, 0, st);
-    launch_smat(P64, g, t, xe, C->mats, MAT_DT_INV, 1, st);
+    launch_smat(P64, g, t, xe, mats_of(C), MAT_DT_INV, 1, st);
     launch_pack(P64, g, prev[k], t, 1, 1, 0, st);
-    launch_smat(P64, g, t, xo, C->mats, MAT_DT_INV, 1, st);
+    launch_smat(P64, g, t, xo, mats_of(C), MAT_DT_INV, 1, st);
     for (int p = 0; p < 2; ++p) {  // out_p = 0 - (M_ee x_p + Dhop D~ x_{1-p}) = -(M_C D~^-1 psi_k)_p
       HopArgs a = base_args(C, P64, p, 1);
       a.in = p ? xe : xo;

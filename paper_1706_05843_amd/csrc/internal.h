@@ -184,6 +184,12 @@ struct Buf {
   void* p = nullptr;
   size_t n = 0;
 };
+// bump allocation over the no-allocation scratch array for one call
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  std::map<std::string, std::pair<size_t, size_t>> slots;  // name -> (offset, bytes)
+};
 
 // records the message returned by eofa_last_error() and passes the code on
 int set_error(int code, const std::string& msg);
@@ -206,6 +212,10 @@ struct eofa_ctx {
   bool gparity = false;
   int Lx_phys = 0;
   std::map<std::string, Buf> pool;
+  // set only during eofa_cg_solve_noalloc: workspace and coefficients come
+  // from the scratch array instead of the pool and the coefficient cache
+  eofa::Arena* arena = nullptr;
+  double* mats_active = nullptr;
   // fifth-dimension matrices of the last systems uploaded
   std::vector<double> sys_key;
   double* mats = nullptr;  // [nrhs][NMAT][2][Ls][Ls] then mop[nrhs]

@@ -84,6 +84,8 @@ def lib():
         "eofa_mooee_inv": ([_P, ctypes.POINTER(System), _P, _P, _I, _I, _I, _P], _I),
         "eofa_cg_solve": ([_P, ctypes.POINTER(System), _P, _P, _I, ctypes.POINTER(SolverParams),
                            ctypes.POINTER(SolverStats), _P], _I),
+        "eofa_cg_solve_noalloc": ([_P, ctypes.POINTER(System), _P, _P, _I, ctypes.POINTER(SolverParams),
+                                   ctypes.POINTER(SolverStats), _P], _I),
         "eofa_heatbath_solve": ([_P, ctypes.c_double, ctypes.c_double, _I, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _P, _P,
                                  ctypes.POINTER(SolverParams), ctypes.POINTER(SolverStats), _P], _I),
@@ -247,6 +249,16 @@ class Context:
         stats = (SolverStats * n)()
         rc = lib().eofa_cg_solve(self._h, make_systems(systems), _p(phi), _p(psi), n, ctypes.byref(params),
                                  stats, _stream(stream))
+        if rc in (EOFA_ERR_INVALID, EOFA_ERR_HIP, EOFA_ERR_OOM):
+            _check(rc)
+        return rc, [s.as_dict() for s in stats]
+
+    def eofa_cg_solve_noalloc(self, systems, phi, psi, params, stream=None):
+        """eofa_cg_solve without device allocation (workspace in the library's scratch array)."""
+        n = len(systems)
+        stats = (SolverStats * n)()
+        rc = lib().eofa_cg_solve_noalloc(self._h, make_systems(systems), _p(phi), _p(psi), n,
+                                         ctypes.byref(params), stats, _stream(stream))
         if rc in (EOFA_ERR_INVALID, EOFA_ERR_HIP, EOFA_ERR_OOM):
             _check(rc)
         return rc, [s.as_dict() for s in stats]
