@@ -384,9 +384,6 @@ int eofa_destroy(eofa_ctx* C) {
   if (C->host_stage) (void)hipHostFree(C->host_stage);
   for (auto ev : C->events) (void)hipEventDestroy(ev);
   if (C->cap_stream) (void)hipStreamDestroy(C->cap_stream);
-  for (auto ev : C->side_ev)
-    if (ev) (void)hipEventDestroy(ev);
-  if (C->side_stream) (void)hipStreamDestroy(C->side_stream);
   delete C;
   return EOFA_OK;
 }
@@ -573,14 +570,12 @@ struct Ring {
   void* at(int k) const { return base + (size_t)(k % R) * slot; }
 };
 
-// One inner CGNR iteration k: K1, K2, alpha, K3, K4, beta, x/p update.
-// side: alpha (which only K4 needs) is finalized on C->side_stream while K3
-// runs (K3 writes no partial sums; a right-hand side that alpha halts gets a
-// K3 output nobody reads), joined before K4. Eager launches only.
+// One inner CGNR iteration k: K1, K2, alpha, K3, K4, beta, x/p update, all on
+// one stream (the alpha finalize on a second stream beside K3 cost two
+// cross-stream waits, about 6 us each, more than the finalize itself).
 int inner_iteration(eofa_ctx* C, const Form& F, int S, const HopArgs& k1, const HopArgs& k2,
                     const HopArgs& k3, const HopArgs& k4, int nbh, int nrhs, CgState Sst, double* partial,
-                    void* xin, void* rin, void* pS, hipStream_t st, hipEvent_t* ev, const Ring* ring, int k,
-                    bool side) {
+                    void* xin, void* rin, void* pS, hipStream_t st, hipEvent_t* ev, const Ring* ring, int k) {
   const Geometry& g = C->g;
   HopArgs a1 = k1, a2 = k2;
   if (ring) a1.in = a2.y = ring->at(k);
@@ -590,18 +585,10 @@ int inner_iteration(eofa_ctx* C, const Form& F, int S, const HopArgs& k1, const 
   if (ev) HIPCHK(hipEventRecord(ev[2], st));
   CHK(hop(C, S, F.k2, a2, st));
   if (ev) HIPCHK(hipEventRecord(ev[3], st));
-  if (side) {
-    HIPCHK(hipEventRecord(C->side_ev[0], st));
-    HIPCHK(hipStreamWaitEvent(C->side_stream, C->side_ev[0], 0));
-    launch_finalize(FIN_ALPHA, partial, nbh, nrhs, Sst, nullptr, C->side_stream);
-    HIPCHK(hipEventRecord(C->side_ev[1], C->side_stream));
-  } else {
-    launch_finalize(FIN_ALPHA, partial, nbh, nrhs, Sst, nullptr, st);
-  }
+  launch_finalize(FIN_ALPHA, partial, nbh, nrhs, Sst, nullptr, st);
   if (ev) HIPCHK(hipEventRecord(ev[4], st));
   CHK(hop(C, S, F.k3, k3, st));
   if (ev) HIPCHK(hipEventRecord(ev[5], st));
-  if (side) HIPCHK(hipStreamWaitEvent(st, C->side_ev[1], 0));
   if (ev) HIPCHK(hipEventRecord(ev[6], st));
   CHK(hop(C, S, F.k4, k4, st));
   if (ev) HIPCHK(hipEventRecord(ev[7], st));
@@ -1017,8 +1004,7 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
       HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
       for (int k = 0; k < check; ++k) {
         const int rc =
-            inner_iteration(C, F, S, k1, k2, k3, k4, nbh, nrhs, Sst, partial, xin, rin, pS, cs, nullptr, ring, k,
-                            false);
+            inner_iteration(C, F, S, k1, k2, k3, k4, nbh, nrhs, Sst, partial, xin, rin, pS, cs, nullptr, ring, k);
         if (rc != EOFA_OK) {
           hipGraph_t dead;
           (void)hipStreamEndCapture(cs, &dead);
@@ -1044,20 +1030,13 @@ int solve_batch(eofa_ctx* C, const eofa_system* sys, int nrhs, const void* phi, 
       HIPCHK(hipStreamWaitEvent(st, join, 0));
       HIPCHK(hipEventDestroy(join));
     } else {
-      // created once per context; a partial failure is completed on the next call
-      // (a no-allocation call creates nothing: one stream, no events)
-      const bool side = !C->arena;
-      if (side && !C->side_stream) HIPCHK(hipStreamCreateWithFlags(&C->side_stream, hipStreamNonBlocking));
-      if (side)
-        for (auto& e : C->side_ev)
-          if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
       while (true) {
         // timed iterations sit between host polls (which drain the queue), so the
-        // events bracket the kernels and not host launch latency
-        const bool prof = prm->profile && side && timed < max_timed && (it % 8 == 4);
+        // events bracket the kernels and not host launch latency (a
+        // no-allocation call creates no events and times nothing)
+        const bool prof = prm->profile && !C->arena && timed < max_timed && (it % 8 == 4);
         hipEvent_t* ev = prof ? &C->events[timed * 8] : nullptr;
-        CHK(inner_iteration(C, F, S, k1, k2, k3, k4, nbh, nrhs, Sst, partial, xin, rin, pS, st, ev, ring, it,
-                            side));
+        CHK(inner_iteration(C, F, S, k1, k2, k3, k4, nbh, nrhs, Sst, partial, xin, rin, pS, st, ev, ring, it));
         if (prof) ++timed;
         ++it;
         if (it % check == 0 || it >= cap) {

@@ -227,10 +227,6 @@ struct eofa_ctx {
   // inner hop kernels, keyed by precision * 4096 + nrhs
   std::map<int, std::pair<int, int>> tuned;
   hipStream_t cap_stream = nullptr;  // non-blocking stream for HIP graph capture
-  // non-blocking stream (default priority) on which the alpha finalize of an
-  // eager inner iteration runs beside K3, joined before K4 by side_ev[1]
-  hipStream_t side_stream = nullptr;
-  hipEvent_t side_ev[2] = {nullptr, nullptr};
 };
 
 namespace eofa {

@@ -173,6 +173,11 @@ __device__ __forceinline__ void load_dir(const void* in, const FD& fin, int r, i
 // unit multiplies the FP32 products as they are accumulated.
 // YPRE: the last direction has nothing left to prefetch, so its free buffer
 // takes the same-site spinor of a.y that the epilogue needs (yout).
+// FP16S gather: directions whose loads are in flight ahead of the one being
+// computed, and the occupancy (waves per SIMD) the register budget is set for
+constexpr int kPfd16 = 1;
+constexpr int kOcc16 = 5;
+
 template <bool DAG, bool PRE, int RL, bool YPRE>
 __device__ __forceinline__ void hop_site_h(const HopArgs& a, const FD& fin, int r, int s, int g, int ls,
                                            const cx<float>* s_link, const int* s_nbr, cx<float>* acc,
@@ -191,20 +196,24 @@ __device__ __forceinline__ void hop_site_h(const HopArgs& a, const FD& fin, int 
   }
 #pragma unroll
   for (int c = 0; c < 12; ++c) acc[c] = {0.f, 0.f};
-  DirIn<P16> b0, b1;
-  load_dir<P16>(a.in, fin, r, s, s_nbr[ls * NSTR], b0);
+  // the neighbour spinors of the next kPfd16 directions are in flight while
+  // one direction is computed (kPfd16 + 1 buffers in registers)
+  DirIn<P16> buf[kPfd16 + 1];
+#pragma unroll
+  for (int d = 0; d < kPfd16; ++d) load_dir<P16>(a.in, fin, r, s, s_nbr[ls * NSTR + d], buf[d]);
 #pragma unroll
   for (int dir = 0; dir < 8; ++dir) {
     __builtin_amdgcn_sched_barrier(0);
-    if (dir < 7) load_dir<P16>(a.in, fin, r, s, s_nbr[ls * NSTR + dir + 1], (dir & 1) ? b0 : b1);
+    if (dir + kPfd16 < 8)
+      load_dir<P16>(a.in, fin, r, s, s_nbr[ls * NSTR + dir + kPfd16], buf[(dir + kPfd16) % (kPfd16 + 1)]);
     if constexpr (YPRE) {
-      if (dir == 7) load_dir<P16>(a.y, fin, r, s, s_nbr[ls * NSTR + 8], yout);
+      if (dir + kPfd16 == 8) load_dir<P16>(a.y, fin, r, s, s_nbr[ls * NSTR + 8], yout);
     }
-    // the next direction's loads leave before this direction's data is
+    // the next directions' loads leave before this direction's data is
     // touched: without this fence the scheduler hoists the lane exchanges of
     // this direction (which wait for its loads) above them, and nothing overlaps
     __builtin_amdgcn_sched_barrier(0);
-    const DirIn<P16>& b = (dir & 1) ? b1 : b0;
+    const DirIn<P16>& b = buf[dir % (kPfd16 + 1)];
     const int mu = dir & 3;
     const bool fwd = dir < 4;
     const float sc = b.sc;
@@ -538,15 +547,49 @@ __device__ __forceinline__ cx<R> row_sum(cx<R> v) {
 // UP: L = L_+ ((L z)_s = z_{s-1}, -m z_{15} at s = 0), a rotation by N;
 // else L = L_- ((L z)_s = z_{s+1}, -m z_0 at s = 15), a rotation by 16 - N.
 // Lanes whose source wraps around the column take the factor -m.
+// z[c] += f * (z[c] of lane (l - K) mod 16 of the same row) for the six complex
+// values of one chirality half, as twelve v_fmac_f32_dpp: the rotation rides
+// on the multiply-accumulate (the compiler folds a rotation into a multiply or
+// an add but not into v_fmac). The result is the same FMA as fma(f, t, z). A
+// DPP read of a VGPR needs two wait states after a VALU write of it, and the
+// compiler does not see the reads and writes inside the statement: s_nop 1 on
+// both sides covers the instruction before it and the one after it; inside,
+// every source was last written by the previous statement.
+#define EOFA_FMAC_ROR_1(K, n) "v_fmac_f32_dpp %" #n ", %" #n ", %12 row_ror:" #K " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+#define EOFA_FMAC_ROR(K)                                                                                    \
+  asm("s_nop 1\n\t" EOFA_FMAC_ROR_1(K, 0) EOFA_FMAC_ROR_1(K, 1) EOFA_FMAC_ROR_1(K, 2) EOFA_FMAC_ROR_1(K, 3) \
+      EOFA_FMAC_ROR_1(K, 4) EOFA_FMAC_ROR_1(K, 5) EOFA_FMAC_ROR_1(K, 6) EOFA_FMAC_ROR_1(K, 7)                 \
+      EOFA_FMAC_ROR_1(K, 8) EOFA_FMAC_ROR_1(K, 9) EOFA_FMAC_ROR_1(K, 10) EOFA_FMAC_ROR_1(K, 11) "s_nop 1"      \
+      : "+v"(z[0].r), "+v"(z[0].i), "+v"(z[1].r), "+v"(z[1].i), "+v"(z[2].r), "+v"(z[2].i), "+v"(z[3].r),     \
+        "+v"(z[3].i), "+v"(z[4].r), "+v"(z[4].i), "+v"(z[5].r), "+v"(z[5].i)                                  \
+      : "v"(f))
+template <int K>
+__device__ __forceinline__ void fmac_ror6(cx<float>* z, float f) {
+  static_assert(K == 1 || K == 2 || K == 4 || K == 8 || K == 12 || K == 14 || K == 15, "rotation");
+  if constexpr (K == 1) EOFA_FMAC_ROR(1);
+  else if constexpr (K == 2) EOFA_FMAC_ROR(2);
+  else if constexpr (K == 4) EOFA_FMAC_ROR(4);
+  else if constexpr (K == 8) EOFA_FMAC_ROR(8);
+  else if constexpr (K == 12) EOFA_FMAC_ROR(12);
+  else if constexpr (K == 14) EOFA_FMAC_ROR(14);
+  else EOFA_FMAC_ROR(15);
+}
+#undef EOFA_FMAC_ROR
+#undef EOFA_FMAC_ROR_1
+
 template <class R, int N, bool UP>
 __device__ __forceinline__ void scan_step(cx<R>* z, int s, R rhoN, R m) {
   const bool wrap = UP ? s < N : s > 15 - N;
   const R f = wrap ? -m * rhoN : rhoN;
+  if constexpr (sizeof(R) == 4) {
+    fmac_ror6<UP ? N : 16 - N>(z, f);
+  } else {
 #pragma unroll
-  for (int c = 0; c < 6; ++c) {
-    const cx<R> t = row_ror<UP ? N : 16 - N>(z[c]);
-    z[c].r = fma(f, t.r, z[c].r);
-    z[c].i = fma(f, t.i, z[c].i);
+    for (int c = 0; c < 6; ++c) {
+      const cx<R> t = row_ror<UP ? N : 16 - N>(z[c]);
+      z[c].r = fma(f, t.r, z[c].r);
+      z[c].i = fma(f, t.i, z[c].i);
+    }
   }
 }
 
@@ -777,7 +820,7 @@ __device__ __forceinline__ void rank_one(const cx<R>* y, cx<R>* v, R sk, R us, i
 // for FP64 (about 168); the stencil hides latency by occupancy.
 template <int P>
 struct HopOcc {
-  static constexpr int waves = P == P64 ? 3 : (P == P16 ? 5 : 4);
+  static constexpr int waves = P == P64 ? 3 : (P == P16 ? kOcc16 : 4);
 };
 
 // the same-site spinor of a.y: decoded from the words prefetched with the
