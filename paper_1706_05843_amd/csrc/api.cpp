@@ -1830,7 +1830,7 @@ int heatbath_poles(eofa_ctx* C, const HeatbathSystems& H, const double* d_om, co
   const int nsys = (int)H.sys.size(), n_poles = nsys / 2;
   const size_t fbytes = (size_t)g.Ls * g.V * 12 * 16;
   void* rhs;
-  CHK(ws(C, "hb_rhs", fbytes * nsys, &rhs));
+  CHK(ws(C, "full_rhs", fbytes * nsys, &rhs));  // shared with eofa_force
   launch_omega_rhs(g, eta, rhs, d_om, d_chir, nsys, st);
   HIPCHK(hipGetLastError());
   int rc = EOFA_OK;
@@ -1898,7 +1898,7 @@ extern "C" int eofa_heatbath_solve(eofa_ctx* C, double m1, double m2, int32_t n_
   CHK(heatbath_upload(C, H, &d_coef, &d_om, &d_chir, st));
   const size_t fbytes = (size_t)C->g.Ls * C->g.V * 12 * 16;
   void* sol;
-  CHK(ws(C, "hb_sol", fbytes * 2 * n_poles, &sol));
+  CHK(ws(C, "full_sol", fbytes * 2 * n_poles, &sol));  // shared with eofa_force
   std::vector<eofa_solver_stats> st_local(2 * n_poles);
   const int rc = heatbath_poles(C, H, d_om, d_chir, pole_tol, eta, sol, prm, stats ? stats : st_local.data(), st);
   if (rc != EOFA_OK && rc != EOFA_ERR_NOT_CONVERGED) return rc;
@@ -1975,8 +1975,8 @@ extern "C" int eofa_force(eofa_ctx* C, double m1, double m2, const void* phi, vo
   const int chir[2] = {-1, +1};
   const size_t fbytes = (size_t)g.Ls * g.V * 12 * 16;
   void *rhs, *chi, *cdev;
-  CHK(ws(C, "fo_rhs", 2 * fbytes, &rhs));
-  CHK(ws(C, "fo_chi", 2 * fbytes, &chi));
+  CHK(ws(C, "full_rhs", 2 * fbytes, &rhs));  // the heatbath's buffers: canonical fields are large
+  CHK(ws(C, "full_sol", 2 * fbytes, &chi));
   const size_t cbytes = sizeof(double) * 2 * g.Ls + sizeof(int) * 2;
   CHK(ws(C, "fo_coef", cbytes, &cdev));
   CHK(stage(C, cbytes));
