@@ -1,119 +1,155 @@
 """FP64 oracle of the gauge-covariant parallel-transport network used as a
-flexible preconditioner, its loss and gradients, and flexible CG.
+flexible preconditioner, its losses and gradients, and flexible CG.
 
 Test infrastructure only: see the package docstring. None of this is in the
-paper; the layer form, loss and optimiser are project decisions.
+paper; the layer form, losses and optimiser are project decisions.
 
-Layer (channels C_in -> C_out), on every s-slice of the full lattice:
-    y_c(x) = sum_{c'} [ W[0, c, c'] X_{c'}(x)
-                        + sum_mu W[1+mu, c, c'] T_{+mu} X_{c'}(x)
-                        + sum_mu W[5+mu, c, c'] T_{-mu} X_{c'}(x) ]
-    T_{+mu} psi(x) = U_mu(x) psi(x + mu),   T_{-mu} psi(x) = U_mu(x - mu)^dag psi(x - mu)
-with the fermion boundary phases on hops across the lattice edge. The
-weights are complex scalars: spin is untouched, colour is parallel
-transported, so the layer is gauge covariant. The network is a stack of
-layers; its input is the odd-sublattice residual embedded in the full lattice
-(even sites zero) and its output is read back on the odd sites.
+Layer (channels C_in -> C_out) on the full 5D lattice, 20 terms per channel
+pair, each a complex weight times a gauge-covariant operator:
+    y_o = sum_i sum_t W[t, o, i] S_t X_i
+    S_0 = P_+,  S_1 = P_-                                   (site local, chirality split)
+    S_{2+mu} = T_{+mu},  S_{6+mu} = T_{-mu}                 (parallel transport)
+    S_{10+mu} = gamma_mu T_{+mu},  S_{14+mu} = gamma_mu T_{-mu}
+    S_18 psi(x, s) = P_+ psi(x, s-1),  S_19 psi(x, s) = P_- psi(x, s+1)   (cyclic in s)
+    T_{+mu} psi(x) = U_mu(x) psi(x + mu),  T_{-mu} psi(x) = U_mu(x - mu)^dag psi(x - mu)
+with the fermion boundary phases on hops across the lattice edge. With a
+hop term in 1 and in gamma_mu each direction can weigh the two spin
+projections (1 -+ gamma_mu) of the Wilson hop separately, and the s terms
+the chirality-split coupling along the fifth dimension of D~ and M_ee.
+Every S_t commutes with gauge transformations.
+
+Network: B = L_n ... L_1 (channels 1 -> C -> ... -> 1) and N = B^dag B,
+Hermitian and positive semi-definite by construction (<x, N x> = |B x|^2),
+so flexible CG with N behaves like preconditioned CG. Its input is the
+odd-sublattice residual embedded in the full lattice (even sites zero), its
+output is read back on the odd sites.
 
 Losses (project decisions):
 * error loss over pairs (r, e):   sum_p |N(r_p)_odd - e_p|^2 / |e_p|^2;
-* residual loss over vectors r:   sum_p |A N(r_p)_odd - r_p|^2 / |r_p|^2 for a
-  Hermitian operator A on the odd sublattice (here A = M^dag M of the Schur
-  system), so that A N approximates the identity.
+* residual loss over vectors r:   sum_p min_c |c A N(r_p)_odd - r_p|^2 / |r_p|^2
+      = sum_p [1 - |<A y_p, r_p>|^2 / (|A y_p|^2 |r_p|^2)],  y_p = N(r_p)_odd,
+  for a Hermitian operator A on the odd sublattice (here A = M^dag M of the
+  Schur system): the scale of N does not matter to CG, so it is left out.
 Gradients are dL/dW* (Wirtinger); dL/dRe W = 2 Re(dL/dW*), dL/dIm W = 2 Im(dL/dW*).
 """
 import numpy as np
 
-from .lattice import shift, dagger, restrict, vdot, norm2
+from .lattice import GAMMA, P_PLUS, P_MINUS, shift, dagger, restrict, vdot, norm2
+
+NTERMS = 20
+S_AXIS = -7
 
 
 def _colour(u, f):
     return np.einsum("...ab,...sb->...sa", u, f)
 
 
-def transport(U, psi, t, bc):
-    """Stencil term t: 0 identity, 1..4 forward mu = t-1, 5..8 backward mu = t-5."""
-    if t == 0:
-        return psi
-    if t <= 4:
-        mu = t - 1
+def _spin(m, f):
+    return np.einsum("st,...tc->...sc", m, f)
+
+
+def _hop(U, psi, mu, fwd, bc):
+    if fwd:
         return _colour(U[mu], shift(psi, mu, +1, bc[mu]))
-    mu = t - 5
     return _colour(dagger(shift(U[mu], mu, -1)), shift(psi, mu, -1, bc[mu]))
 
 
-def transports(U, X, bc):
-    """[9, C, ...] all stencil terms of every channel of X [C, ...]."""
-    return np.stack([np.stack([transport(U, X[c], t, bc) for c in range(X.shape[0])]) for t in range(9)])
+def term(U, psi, t, bc, adj=False):
+    """S_t psi, or S_t^dag psi (adj): T_{+mu}^dag = T_{-mu}, gamma_mu Hermitian and
+    commuting with the transports, the s shifts reversed."""
+    if t == 0:
+        return _spin(P_PLUS, psi)
+    if t == 1:
+        return _spin(P_MINUS, psi)
+    if t < 18:
+        k = (t - 2) % 8
+        mu, fwd = k % 4, k < 4
+        h = _hop(U, psi, mu, fwd != adj, bc)
+        return h if t < 10 else _spin(GAMMA[mu], h)
+    if t == 18:
+        return _spin(P_PLUS, np.roll(psi, -1 if adj else 1, axis=S_AXIS))
+    return _spin(P_MINUS, np.roll(psi, 1 if adj else -1, axis=S_AXIS))
+
+
+def terms(U, X, bc, adj=False):
+    """[NTERMS, C, ...] all terms of every channel of X [C, ...]."""
+    return np.stack([np.stack([term(U, X[c], t, bc, adj) for c in range(X.shape[0])]) for t in range(NTERMS)])
 
 
 def layer(U, W, X, bc):
-    """W [9, C_out, C_in] complex, X [C_in, Ls, T, Z, Y, X, 4, 3]."""
-    Z = transports(U, X, bc)
-    return np.einsum("toi,ti...->o...", W, Z)
+    """W [NTERMS, C_out, C_in] complex, X [C_in, Ls, T, Z, Y, X, 4, 3]."""
+    return np.einsum("toi,ti...->o...", W, terms(U, X, bc))
 
 
 def layer_adjoint(U, W, G, bc):
-    """Adjoint of ``layer`` in X: sum_{t,c} conj(W[t,c,c']) T_t^dag G_c with T_{+mu}^dag = T_{-mu}."""
-    swap = [0, 5, 6, 7, 8, 1, 2, 3, 4]
-    out = np.zeros((W.shape[2],) + G.shape[1:], dtype=np.complex128)
-    for t in range(9):
-        TG = np.stack([transport(U, G[c], swap[t], bc) for c in range(G.shape[0])])
-        out += np.einsum("oi,o...->i...", np.conj(W[t]), TG)
-    return out
+    """Adjoint of ``layer`` in X: sum_{t,o} conj(W[t, o, i]) S_t^dag G_o."""
+    return np.einsum("toi,to...->i...", np.conj(W), terms(U, G, bc, adj=True))
 
 
 def weight_grad(U, X, G, bc):
-    """dL/dW*[t, c, c'] = sum_x <T_t X_{c'}, G_c> with G = dL/dy*."""
-    Z = transports(U, X, bc)
+    """D[t, o, i] = sum_x <S_t X_i, G_o> (conjugate on the first slot)."""
+    Z = terms(U, X, bc)
     G2 = G.reshape(G.shape[0], -1)
     Z2 = Z.reshape(Z.shape[0], Z.shape[1], -1)
     return np.einsum("on,tin->toi", G2, np.conj(Z2))
 
 
 def forward(U, Ws, r_odd, dims, bc):
-    """Network output on the odd sites and the activations [X0..X_L]."""
-    X = [r_odd[None]]  # the embedded odd residual (even sites already zero)
+    """N(r) = B^dag B r on the odd sites and the activations: X[0..n] of B
+    (X[0] the embedded residual) and Y[n..0] of B^dag (Y[n] = X[n])."""
+    X = [r_odd[None]]
     for W in Ws:
         X.append(layer(U, W, X[-1], bc))
-    return restrict(X[-1][0], dims, 1), X
+    Y = [X[-1]]
+    for W in reversed(Ws):
+        Y.append(layer_adjoint(U, W, Y[-1], bc))
+    return restrict(Y[-1][0], dims, 1), (X, Y[::-1])
+
+
+def _backprop(U, Ws, acts, g_out, grads, bc):
+    """Accumulate dL/dW* into grads given dL/dN(r)* = g_out (odd field).
+    Adjoint layer k (Y[k-1] = L_k^dag Y[k]): dL/dW_k* += weight_grad(G, Y[k])
+    with G = dL/dY[k-1]*, and dL/dY[k]* = L_k G; then the layers of B as usual:
+    dL/dW_k* += weight_grad(X[k-1], G), dL/dX[k-1]* = L_k^dag G."""
+    X, Y = acts
+    n = len(Ws)
+    G = g_out[None]
+    for k in range(1, n + 1):
+        grads[k - 1] += weight_grad(U, G, Y[k], bc)
+        G = layer(U, Ws[k - 1], G, bc)
+    for k in range(n, 0, -1):
+        grads[k - 1] += weight_grad(U, X[k - 1], G, bc)
+        if k > 1:
+            G = layer_adjoint(U, Ws[k - 1], G, bc)
 
 
 def loss_and_grads(U, Ws, pairs, dims, bc):
-    """L = sum_p |N(r_p) - e_p|^2 / |e_p|^2 and dL/dW* for every layer."""
+    """Error loss sum |N(r_p) - e_p|^2 / |e_p|^2 and dL/dW* for every layer."""
     L = 0.0
     grads = [np.zeros_like(W) for W in Ws]
     for r, e in pairs:
-        y, X = forward(U, Ws, r, dims, bc)
+        y, acts = forward(U, Ws, r, dims, bc)
         ne = norm2(e)
         d = y - e
         L += norm2(d) / ne
-        G = (d / ne)[None]
-        for k in range(len(Ws) - 1, -1, -1):
-            grads[k] += weight_grad(U, X[k], G, bc)
-            if k > 0:
-                G = layer_adjoint(U, Ws[k], G, bc)
+        _backprop(U, Ws, acts, restrict(d / ne, dims, 1), grads, bc)
     return L, grads
 
 
-def _backprop(U, Ws, X, G, grads, bc):
-    for k in range(len(Ws) - 1, -1, -1):
-        grads[k] += weight_grad(U, X[k], G, bc)
-        if k > 0:
-            G = layer_adjoint(U, Ws[k], G, bc)
-
-
 def residual_loss_and_grads(U, Ws, rs, A, dims, bc):
-    """L = sum_p |A y_p - r_p|^2 / |r_p|^2 with y_p = N(r_p) on the odd sites, A
-    Hermitian; dL/dy* = A (A y - r) / |r|^2, then the same back-propagation."""
+    """Residual loss sum_p [1 - |<A y, r>|^2 / (|A y|^2 |r|^2)], y = N(r_p) on
+    the odd sites, A Hermitian: with a = A y, c = <a, r>,
+    dL/da* = (|c|^2 a - conj(c) |a|^2 r) / (|a|^4 |r|^2), dL/dy* = A dL/da*."""
     L = 0.0
     grads = [np.zeros_like(W) for W in Ws]
     for r in rs:
-        y, X = forward(U, Ws, r, dims, bc)
-        nr = norm2(r)
-        d = A(y) - r
-        L += norm2(d) / nr
-        _backprop(U, Ws, X, (A(d) / nr)[None], grads, bc)
+        y, acts = forward(U, Ws, r, dims, bc)
+        a = A(y)
+        c = vdot(a, r)
+        na, nr = norm2(a), norm2(r)
+        L += 1.0 - abs(c) ** 2 / (na * nr)
+        ga = (abs(c) ** 2 * a - np.conj(c) * na * r) / (na * na * nr)
+        _backprop(U, Ws, acts, restrict(A(ga), dims, 1), grads, bc)
     return L, grads
 
 
