@@ -331,15 +331,16 @@ def bench_learned(args, eofa, synth, torch, np):
     shifted system H(m2) - Delta_+(m1, m2) P_+ (m1 = 0.04, m2 = 1.0). Training
     pairs (r_k, e_k = x* - x_k) from FP64 CG on the normal equations of
     args.train_fields seeded gauge fields (args.pairs_per_field each, spread
-    over the CG run); a 1 -> 8 -> 8 -> 8 -> 1 parallel-transport network
-    trained with Adam on the GPU; then, on args.held_fields held-out fields,
-    time to an FP64 true residual of 1e-10 for plain FP64 CGNR, FP16S/FP64
-    mixed CGNR, flexible CG with the identity, and flexible CG with the
-    trained network (network in FP32, operator in FP64). The loss is the
-    residual loss |A N(r) - r|^2/|r|^2 (A = M^dag M) unless --loss error."""
+    over the CG run); a network N = B^dag B with B of channels args.channels
+    (default 1 -> 4 -> 1) trained with Adam on the GPU; then, on
+    args.held_fields held-out fields, time to an FP64 true residual of 1e-10
+    for plain FP64 CGNR, FP16S/FP64 mixed CGNR, flexible CG with the
+    identity, and flexible CG with the trained network (network in FP32,
+    operator in FP64). The loss is the scale-free residual loss
+    1 - |<A N(r), r>|^2/(|A N(r)|^2 |r|^2) (A = M^dag M) unless --loss error."""
     dims, Ls, eps, m1, m2 = (16, 16, 16, 32), 16, 0.5, 0.04, 1.0
     system = (m2, m1, m2, -1.0, +1)
-    chans = [1, 8, 8, 8, 1]
+    chans = [int(c) for c in args.channels.split(",")]
     act = eofa.make_action(dims, Ls, 1.8, 1.5, 0.5)
     log = lambda m: print(f"bench: {m}", file=sys.stderr, flush=True)
     log(f"learned workload dims={dims} Ls={Ls}, {args.train_fields} training + {args.held_fields} held-out fields")
@@ -365,7 +366,7 @@ def bench_learned(args, eofa, synth, torch, np):
     torch.cuda.synchronize()
     t_pairs = time.perf_counter() - t0
     npairs = sum(d[2] for d in data)
-    net = eofa.Net(ctxs[0], chans, seed=7, init_scale=0.5)
+    net = eofa.Net(ctxs[0], chans, seed=7, init_scale=0.25)
     # loss of the untrained network
     lsys = system if args.loss == "residual" else None
     loss0 = sum(net.loss_grad(c, d[0], d[1], d[2], system=lsys)[0] for c, d in zip(ctxs, data)) / npairs
@@ -400,12 +401,24 @@ def bench_learned(args, eofa, synth, torch, np):
         "fgcg_learned": eofa.make_params(tol=1e-10, precond=1, net=net),
     }
     res = {k: [] for k in modes}
+    t_apply = None
     for f in range(args.held_fields):
         ctx = eofa.Context(act, torch.from_numpy(synth.gauge_field(dims, eps, 4000 + f)).cuda())
         phi = synth.fermion_torch(dims, Ls, seed=4100 + f, nrhs=1)
         if f == 0:
             for prm in modes.values():  # warm-up (autotune, workspace)
                 timed(ctx, phi, prm)
+            # one application of N (B and B^dag, all layers) on the default stream
+            pin, pout = ctx.new_packed(eofa.FP32), ctx.new_packed(eofa.FP32)
+            pin.zero_()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            net.apply(ctx, pin, pout)
+            ev0.record()
+            for _ in range(10):
+                net.apply(ctx, pin, pout)
+            ev1.record()
+            torch.cuda.synchronize()
+            t_apply = ev0.elapsed_time(ev1) / 10 * 1e-3
         for k, prm in modes.items():
             res[k].append(timed(ctx, phi, prm))
         log(f"held-out field {f}: " + ", ".join(f"{k} {v[-1]['iters']} it {v[-1]['seconds']:.3f} s" for k, v in res.items()))
@@ -431,6 +444,7 @@ def bench_learned(args, eofa, synth, torch, np):
         "time_ratio_vs_plain_fp64": {k: round(v["mean_seconds"] / plain, 3) for k, v in summ.items()},
         "iteration_ratio_learned_vs_identity": round(summ["fgcg_learned"]["mean_iters"] /
                                                      summ["fgcg_identity"]["mean_iters"], 3),
+        "network_apply_ms": None if t_apply is None else round(t_apply * 1e3, 3),
         "training": {"pairs": npairs, "pair_stride": stride, "seconds_pairs": round(t_pairs, 2),
                      "seconds_training": round(t_train, 2), "loss_untrained": loss0, "loss_per_epoch": hist,
                      "epochs": args.epochs, "batch": args.batch, "lr": args.lr, "loss": args.loss},
@@ -774,8 +788,9 @@ def main():
     ap.add_argument("--held-fields", type=int, default=8)
     ap.add_argument("--pairs-per-field", type=int, default=64)
     ap.add_argument("--epochs", type=int, default=4)
-    ap.add_argument("--batch", type=int, default=8)
-    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--lr", type=float, default=1e-2)
+    ap.add_argument("--channels", default="1,4,1", help="learned workload: channels of B, 1,...,1")
     ap.add_argument("--loss", default="residual", choices=["residual", "error"],
                     help="network loss: |A N(r) - r|^2/|r|^2 (residual) or |N(r) - e|^2/|e|^2 (error)")
     ap.add_argument("--copy-calibration", action="store_true",

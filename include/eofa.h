@@ -324,22 +324,30 @@ int eofa_cg_pairs(eofa_ctx* ctx, const eofa_system* sys, const void* phi, int32_
                   int32_t stride, double tol, int32_t max_iter, void* r_out, void* e_out, int32_t* recorded,
                   int32_t* iters, void* stream);
 
-/* Learned preconditioner (not in the paper): a stack of n_layers gauge-
- * covariant parallel-transport layers with channels channels[0..n_layers]
- * (channels[0] = channels[n_layers] = 1, each 1..8). Layer l maps C_in to
- * C_out channels on every s-slice of the full lattice:
- *   y_c(x) = sum_c' W[0][c][c'] X_c'(x) + sum_mu W[1+mu][c][c'] U_mu(x) X_c'(x+mu)
- *          + sum_mu W[5+mu][c][c'] U_mu(x-mu)^dag X_c'(x-mu)
- * (fermion boundary phases on edge hops), W complex scalars, so spin is
- * untouched and colour is parallel transported. The input is an odd
- * packed FP32 half-field embedded with zero even sites; the output is the
- * odd half of the last layer. Weights: FP32 master copy (Adam state beside
- * it), used as bfloat16 in the kernels, FP32 arithmetic. Weights are
- * stored layer by layer as W[9][C_out][C_in] complex (re, im).
+/* Learned preconditioner (not in the paper): N = B^dag B with B a stack of
+ * n_layers gauge-covariant parallel-transport layers, channels
+ * channels[0..n_layers] (channels[0] = channels[n_layers] = 1, each 1..8).
+ * Layer l maps C_in to C_out channels on the full lattice with 20 terms
+ * per channel pair, each a complex weight times a gauge-covariant operator:
+ *   y_c = sum_c' sum_t W[t][c][c'] S_t X_c',
+ *   S_0 = P_+, S_1 = P_-   (same site; P_+- = (1 +- g5)/2)
+ *   S_{2+mu} = T_{+mu}, S_{6+mu} = T_{-mu},
+ *   S_{10+mu} = g_mu T_{+mu}, S_{14+mu} = g_mu T_{-mu},
+ *   (S_18 X)(x, s) = P_+ X(x, s-1), (S_19 X)(x, s) = P_- X(x, s+1) (cyclic in s),
+ *   T_{+mu} X(x) = U_mu(x) X(x+mu), T_{-mu} X(x) = U_mu(x-mu)^dag X(x-mu)
+ * (fermion boundary phases on edge hops; g_mu in the chiral basis of the
+ * field layout). B^dag applies the adjoint layers in reverse order, so N
+ * is Hermitian and positive semi-definite (<x, N x> = |B x|^2). The input
+ * is an odd packed FP32 half-field embedded with zero even sites; the
+ * output is the odd half of B^dag B of it. Weights: FP32 master copy (Adam
+ * state beside it), used as bfloat16 in the kernels, FP32 arithmetic;
+ * stored layer by layer as W[20][C_out][C_in] complex (re, im).
  * A network holds device memory only; it may be used with any context
  * whose lattice matches the one it was last applied on (buffers are
  * resized otherwise). Initial weights: N(0, s^2) real and imaginary parts,
- * s = init_scale / sqrt(9 C_in), from `seed`.                            */
+ * s = init_scale / sqrt(20 C_in), from `seed`, plus 1 on W[0][0][0] and
+ * W[1][0][0] (the identity from channel 0 to channel 0), so that an
+ * untrained network is close to the identity.                           */
 int eofa_net_create(eofa_ctx* ctx, int32_t n_layers, const int32_t* channels, uint64_t seed,
                     double init_scale, eofa_net** out);
 int eofa_net_destroy(eofa_net* net);
@@ -354,9 +362,13 @@ int eofa_net_apply(eofa_ctx* ctx, eofa_net* net, const void* in, void* out, void
  * and imaginary parts) as host grad[2 * num_weights] (may be NULL); loss:
  * host (may be NULL). Two losses:
  *   sys == NULL: error loss     sum_p |N(r_p) - e_p|^2 / |e_p|^2  (pairs r, e);
- *   sys != NULL: residual loss  sum_p |A N(r_p) - r_p|^2 / |r_p|^2 with
- *                A = M^dag M of the odd Schur system of sys (applied by the
- *                hop kernels in FP32); e is not used and may be NULL.    */
+ *   sys != NULL: residual loss  sum_p min_c |c A N(r_p) - r_p|^2 / |r_p|^2
+ *                = sum_p [1 - |<A y_p, r_p>|^2 / (|A y_p|^2 |r_p|^2)],
+ *                y_p = N(r_p), A = M^dag M of the odd Schur system of sys
+ *                (applied by the hop kernels in FP32): the best scale c is
+ *                taken out because CG does not depend on the scale of its
+ *                preconditioner; e is not used and may be NULL. A pair with
+ *                A y_p = 0 contributes 1 and no gradient.                */
 int eofa_net_loss_grad(eofa_ctx* ctx, eofa_net* net, const eofa_system* sys, const void* r, const void* e,
                        int32_t npairs, double* loss, double* grad, void* stream);
 /* Adam training (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on the

@@ -2,12 +2,15 @@
 // and Adam training (host side; kernels in nn.hip). This part is not in the
 // paper: it is the learned flexible preconditioner of this library.
 //
-// Network: layers l = 0..L-1 with channels ch[l] -> ch[l+1], ch[0] = ch[L] = 1.
-// Input: an odd-sublattice packed FP32 field (one channel), embedded in the
-// full lattice with zero even sites; output: the odd part of the last layer.
-// Loss over pairs (r, e): sum_p |N(r_p) - e_p|^2 / |e_p|^2; gradients are
-// dL/dW* (Wirtinger); Adam steps on (Re W, Im W) with 2 dL/dW* / batch,
-// FP32 master weights, bfloat16 weights in the kernels.
+// Network N = B^dag B, B = L_{L-1} ... L_0 with channels ch[l] -> ch[l+1],
+// ch[0] = ch[L] = 1. Input: an odd-sublattice packed FP32 field (one
+// channel), embedded in the full lattice with zero even sites; output: the
+// odd part of B^dag B of it. Activations kept for the gradients: X[0..L] of
+// B (X[0] the embedded input) and Y[0..L-1] of B^dag (Y[k-1] = L_{k-1}^dag
+// Y[k], Y[L] = X[L]). Losses (see eofa_net_loss_grad): the error loss over
+// pairs (r, e) and the scale-free residual loss over residuals r;
+// gradients are dL/dW* (Wirtinger); Adam steps on (Re W, Im W) with
+// 2 dL/dW* / batch, FP32 master weights, bfloat16 weights in the kernels.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -31,13 +34,16 @@ struct eofa_net {
   unsigned short* wb = nullptr;  // bfloat16 copy used by the kernels
   double* gw = nullptr;          // dL/dW* accumulator (re, im)
   int step = 0;
-  // activations: act[l][parity] with ch[l] channels, grad buffers g[2][parity]
+  // activations: act[l][parity] = X[l] and yact[k][parity] = Y[k] with
+  // ch[l] (ch[k]) channels, grad buffers g[2][parity]
   size_t sized_for = 0;  // Vh*Ls the buffers fit
   std::vector<void*> act;
+  std::vector<void*> yact;
   void* gbuf[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   void* zero = nullptr;      // an all-zero one-channel half field
-  void* ay = nullptr;        // residual loss: A y, then (A y - r)/|r|^2 (one channel)
-  void* dg = nullptr;
+  void* ay = nullptr;        // residual loss: A y (one channel)
+  void* dg = nullptr;        // residual loss: dL/d(A y)* (one channel)
+  double* coef = nullptr;    // residual loss: the 3 coefficients of dL/d(A y)*
   double* partial = nullptr;
   size_t partial_n = 0;
   double* dev_scalars = nullptr;  // |e|^2 per pair
@@ -60,8 +66,8 @@ int nfail(int code, const std::string& m) { return set_error(code, m); }
   } while (0)
 
 constexpr int WGRAD_BLOCKS = 256;
-// weight-gradient partial sums [9*C_in][2][C_out][WGRAD_BLOCKS][2], then the loss partials
-constexpr size_t WGRAD_PARTIAL = (size_t)9 * NET_MAXC * 2 * NET_MAXC * WGRAD_BLOCKS * 2;
+// weight-gradient partial sums [20*C_in][2][C_out][WGRAD_BLOCKS][2], then the loss partials
+constexpr size_t WGRAD_PARTIAL = (size_t)NET_TERMS * NET_MAXC * 2 * NET_MAXC * WGRAD_BLOCKS * 2;
 
 double* loss_partial(eofa_net* N) { return N->partial + WGRAD_PARTIAL; }
 
@@ -77,16 +83,18 @@ int dmalloc(void** p, size_t n) {
 }
 
 void free_acts(eofa_net* N) {
-  for (void* p : N->act)
-    if (p) (void)hipFree(p);
-  N->act.clear();
+  for (auto* v : {&N->act, &N->yact}) {
+    for (void* p : *v)
+      if (p) (void)hipFree(p);
+    v->clear();
+  }
   for (auto& a : N->gbuf)
     for (auto& b : a)
       if (b) {
         (void)hipFree(b);
         b = nullptr;
       }
-  for (void** b : {&N->zero, &N->ay, &N->dg})
+  for (void** b : {&N->zero, &N->ay, &N->dg, (void**)&N->coef})
     if (*b) {
       (void)hipFree(*b);
       *b = nullptr;
@@ -103,14 +111,18 @@ int ensure_acts(eofa_ctx* C, eofa_net* N, hipStream_t st) {
   N->act.assign(2 * (N->L + 1), nullptr);
   for (int l = 0; l <= N->L; ++l)
     for (int p = 0; p < 2; ++p) NCHK(dmalloc(&N->act[2 * l + p], half_bytes(C->g, N->ch[l])));
+  N->yact.assign(2 * N->L, nullptr);
+  for (int k = 0; k < N->L; ++k)
+    for (int p = 0; p < 2; ++p) NCHK(dmalloc(&N->yact[2 * k + p], half_bytes(C->g, N->ch[k])));
   for (auto& a : N->gbuf)
     for (auto& b : a) NCHK(dmalloc(&b, half_bytes(C->g, cmax)));
   NCHK(dmalloc(&N->zero, half_bytes(C->g, 1)));
   NCHK(dmalloc(&N->ay, half_bytes(C->g, 1)));
   NCHK(dmalloc(&N->dg, half_bytes(C->g, 1)));
+  NCHK(dmalloc((void**)&N->coef, 4 * sizeof(double)));
   NHIP(hipMemsetAsync(N->zero, 0, half_bytes(C->g, 1), st));
   const size_t pn = WGRAD_PARTIAL;
-  const size_t ln = (size_t)(C->g.Vh * C->g.Ls + 255) / 256;
+  const size_t ln = std::max((size_t)(C->g.Vh * C->g.Ls + 255) / 256, (size_t)3 * NET_DOT_BLOCKS);
   if (N->partial_n < pn + ln) {
     if (N->partial) (void)hipFree(N->partial);
     N->partial_n = pn + ln;
@@ -120,29 +132,52 @@ int ensure_acts(eofa_ctx* C, eofa_net* N, hipStream_t st) {
   return EOFA_OK;
 }
 
-NetLayerArgs layer_args(eofa_ctx* C, eofa_net* N, int l, int parity) {
+// Y[k] of B^dag (Y[L] = X[L])
+void** ybuf(eofa_net* N, int k) { return k == N->L ? &N->act[2 * N->L] : &N->yact[2 * k]; }
+
+// output parity `parity` of layer l (adj: of its adjoint) applied to in[0..1]
+void run_layer(eofa_ctx* C, eofa_net* N, int l, bool adj, void* const* in, void* out, int parity, hipStream_t st) {
   NetLayerArgs a;
-  a.xin[0] = (const float*)N->act[2 * l];
-  a.xin[1] = (const float*)N->act[2 * l + 1];
-  a.yout = (float*)N->act[2 * (l + 1) + parity];
+  a.xin[0] = (const float*)in[0];
+  a.xin[1] = (const float*)in[1];
+  a.yout = (float*)out;
   a.w = N->wb + 2 * N->woff[l];
   a.links = (const float*)C->links[P32][parity];
   a.nbr = C->nbr[parity];
   a.Vh = C->g.Vh;
   a.Ls = C->g.Ls;
-  a.Cin = N->ch[l];
-  a.Cout = N->ch[l + 1];
+  a.Cin = adj ? N->ch[l + 1] : N->ch[l];
+  a.Cout = adj ? N->ch[l] : N->ch[l + 1];
   a.parity = parity;
-  return a;
+  launch_pt_layer(a, adj, st);
 }
 
-// forward pass from act[0] (odd = input, even = 0); all parities kept
-// (the last layer only on the odd parity unless keep_all)
-void forward(eofa_ctx* C, eofa_net* N, hipStream_t st, bool keep_all) {
+// dL/dW_l* (+)= sum_x <S_t x_ci, g_c> over both parities
+void run_wgrad(eofa_ctx* C, eofa_net* N, int l, void* const* x, void* const* g, bool accumulate, hipStream_t st) {
+  NetGradArgs ga;
+  for (int p = 0; p < 2; ++p) {
+    ga.x[p] = (const float*)x[p];
+    ga.g[p] = (const float*)g[p];
+    ga.links[p] = (const float*)C->links[P32][p];
+    ga.nbr[p] = C->nbr[p];
+  }
+  ga.partial = N->partial;
+  ga.Vh = C->g.Vh;
+  ga.Ls = C->g.Ls;
+  ga.Cin = N->ch[l];
+  ga.Cout = N->ch[l + 1];
+  launch_pt_wgrad(ga, WGRAD_BLOCKS, accumulate ? 1 : 0, N->gw + 2 * N->woff[l], st);
+}
+
+// N = B^dag B from act[0] (odd = input, even = 0): X[1..L] on both
+// parities, then Y[L-1..0] (Y[0] on the odd parity only)
+void forward(eofa_ctx* C, eofa_net* N, hipStream_t st) {
   for (int l = 0; l < N->L; ++l)
+    for (int p = 0; p < 2; ++p) run_layer(C, N, l, false, &N->act[2 * l], N->act[2 * (l + 1) + p], p, st);
+  for (int k = N->L; k >= 1; --k)
     for (int p = 0; p < 2; ++p) {
-      if (l == N->L - 1 && p == 0 && !keep_all) continue;
-      launch_pt_layer(layer_args(C, N, l, p), false, st);
+      if (k == 1 && p == 0) continue;
+      run_layer(C, N, k - 1, true, ybuf(N, k), N->yact[2 * (k - 1) + p], p, st);
     }
 }
 
@@ -156,8 +191,8 @@ int net_apply_internal(eofa_ctx* C, eofa_net* N, const void* in, void* out, hipS
   const size_t hb = half_bytes(C->g, 1);
   NHIP(hipMemcpyAsync(N->act[1], in, hb, hipMemcpyDeviceToDevice, st));
   NHIP(hipMemcpyAsync(N->act[0], N->zero, hb, hipMemcpyDeviceToDevice, st));
-  forward(C, N, st, false);
-  NHIP(hipMemcpyAsync(out, N->act[2 * N->L + 1], hb, hipMemcpyDeviceToDevice, st));
+  forward(C, N, st);
+  NHIP(hipMemcpyAsync(out, N->yact[1], hb, hipMemcpyDeviceToDevice, st));
   NHIP(hipGetLastError());
   return EOFA_OK;
 }
@@ -166,64 +201,45 @@ int net_apply_internal(eofa_ctx* C, eofa_net* N, const void* in, void* out, hipS
 
 namespace {
 
-// forward + backward of one pair; gradients accumulated into N->gw; the
-// pair's unnormalised loss lands in loss_dst (device). sys == nullptr: error
-// loss |y - e|^2/|e|^2 (enorm = |e|^2); else residual loss |A y - r|^2/|r|^2
-// with A = M^dag M of sys (enorm = |r|^2, e unused).
+// forward + backward of one pair; gradients accumulated into N->gw (written
+// by the first pair of a step). sys == nullptr: error loss |y - e|^2/|e|^2,
+// its unnormalised |y - e|^2 lands in loss_dst (enorm = |e|^2); else the
+// residual loss 1 - |<A y, r>|^2/(|A y|^2 |r|^2) with A = M^dag M of sys
+// lands in loss_dst (enorm = |r|^2, e unused).
+// Backward, with G = dL/d(output)* (odd, even zero) on channel 1:
+//   B^dag layers k = 1..L:  dW_{k-1}* += <S_t G, Y[k]>,  G <- L_{k-1} G;
+//   B layers k = L..1:      dW_{k-1}* += <S_t X[k-1], G>, G <- L_{k-1}^dag G.
 int pair_grad(eofa_ctx* C, eofa_net* N, const eofa_system* sys, const void* r, const void* e,
               const double* enorm, bool first, double* loss_dst, hipStream_t st) {
   const Geometry& g = C->g;
   const size_t hb = half_bytes(g, 1);
   NHIP(hipMemcpyAsync(N->act[1], r, hb, hipMemcpyDeviceToDevice, st));
   NHIP(hipMemcpyAsync(N->act[0], N->zero, hb, hipMemcpyDeviceToDevice, st));
-  forward(C, N, st, false);
+  forward(C, N, st);
   int cur = 0;
   NHIP(hipMemcpyAsync(N->gbuf[cur][0], N->zero, hb, hipMemcpyDeviceToDevice, st));
-  const float* y = (const float*)N->act[2 * N->L + 1];
-  int nb;
+  const float* y = (const float*)N->yact[1];
   if (!sys) {
-    // seed: G_L = (y - e)/|e|^2 on odd, 0 on even
-    nb = launch_net_loss(g.Vh, g.Ls, y, (const float*)e, (float*)N->gbuf[cur][1], enorm, loss_partial(N), st);
+    // seed: G = (y - e)/|e|^2 on odd, 0 on even; loss = sum of partials
+    const int nb =
+        launch_net_loss(g.Vh, g.Ls, y, (const float*)e, (float*)N->gbuf[cur][1], enorm, loss_partial(N), st);
+    launch_finalize(FIN_NORM, loss_partial(N), nb, 1, CgState{}, loss_dst, st);
   } else {
-    // seed: G_L = A (A y - r)/|r|^2 on odd, 0 on even
+    // seed: G = A dL/da* with a = A y on odd, 0 on even
     NCHK(normal_op_fp32(C, sys, y, N->ay, st));
-    nb = launch_net_loss(g.Vh, g.Ls, (const float*)N->ay, (const float*)r, (float*)N->dg, enorm, loss_partial(N), st);
+    launch_net_resid(g.Vh, g.Ls, (const float*)N->ay, (const float*)r, enorm, loss_partial(N), loss_dst, N->coef,
+                     (float*)N->dg, st);
     NCHK(normal_op_fp32(C, sys, N->dg, N->gbuf[cur][1], st));
   }
-  // loss = sum of partials, reduced on the device into loss_dst
-  launch_finalize(FIN_NORM, loss_partial(N), nb, 1, CgState{}, loss_dst, st);
-  for (int l = N->L - 1; l >= 0; --l) {
-    NetGradArgs ga;
-    ga.x[0] = (const float*)N->act[2 * l];
-    ga.x[1] = (const float*)N->act[2 * l + 1];
-    ga.g[0] = (const float*)N->gbuf[cur][0];
-    ga.g[1] = (const float*)N->gbuf[cur][1];
-    ga.links[0] = (const float*)C->links[P32][0];
-    ga.links[1] = (const float*)C->links[P32][1];
-    ga.nbr[0] = C->nbr[0];
-    ga.nbr[1] = C->nbr[1];
-    ga.partial = N->partial;
-    ga.Vh = g.Vh;
-    ga.Ls = g.Ls;
-    ga.Cin = N->ch[l];
-    ga.Cout = N->ch[l + 1];
-    launch_pt_wgrad(ga, WGRAD_BLOCKS, first ? 0 : 1, N->gw + 2 * N->woff[l], st);
-    if (l > 0) {  // G_l = adjoint of layer l applied to G_{l+1}, both parities
-      for (int p = 0; p < 2; ++p) {
-        NetLayerArgs a;
-        a.xin[0] = (const float*)N->gbuf[cur][0];
-        a.xin[1] = (const float*)N->gbuf[cur][1];
-        a.yout = (float*)N->gbuf[1 - cur][p];
-        a.w = N->wb + 2 * N->woff[l];
-        a.links = (const float*)C->links[P32][p];
-        a.nbr = C->nbr[p];
-        a.Vh = g.Vh;
-        a.Ls = g.Ls;
-        a.Cin = N->ch[l + 1];
-        a.Cout = N->ch[l];
-        a.parity = p;
-        launch_pt_layer(a, true, st);
-      }
+  for (int k = 1; k <= N->L; ++k) {
+    run_wgrad(C, N, k - 1, N->gbuf[cur], ybuf(N, k), !first, st);
+    for (int p = 0; p < 2; ++p) run_layer(C, N, k - 1, false, N->gbuf[cur], N->gbuf[1 - cur][p], p, st);
+    cur = 1 - cur;
+  }
+  for (int k = N->L; k >= 1; --k) {
+    run_wgrad(C, N, k - 1, &N->act[2 * (k - 1)], N->gbuf[cur], true, st);
+    if (k > 1) {
+      for (int p = 0; p < 2; ++p) run_layer(C, N, k - 1, true, N->gbuf[cur], N->gbuf[1 - cur][p], p, st);
       cur = 1 - cur;
     }
   }
@@ -268,10 +284,11 @@ int eofa_net_create(eofa_ctx* C, int32_t n_layers, const int32_t* channels, uint
   N->ch.assign(channels, channels + n_layers + 1);
   for (int l = 0; l < n_layers; ++l) {
     N->woff.push_back(N->nw);
-    N->nw += (size_t)9 * channels[l] * channels[l + 1];
+    N->nw += (size_t)NET_TERMS * channels[l] * channels[l + 1];
   }
   // host initialisation: N(0, s^2) real and imaginary parts with
-  // s = init_scale / sqrt(9 C_in) (splitmix64 + Box-Muller, seeded)
+  // s = init_scale / sqrt(20 C_in) (splitmix64 + Box-Muller, seeded), plus
+  // the identity P_+ + P_- from channel 0 to channel 0 of every layer
   std::vector<float> w(2 * N->nw);
   uint64_t state = seed;
   auto next = [&]() {
@@ -282,13 +299,16 @@ int eofa_net_create(eofa_ctx* C, int32_t n_layers, const int32_t* channels, uint
   };
   auto unif = [&]() { return ((next() >> 11) + 0.5) * (1.0 / 9007199254740992.0); };
   for (int l = 0; l < n_layers; ++l) {
-    const double sd = init_scale / std::sqrt(9.0 * channels[l]);
-    for (size_t k = 0; k < (size_t)9 * channels[l] * channels[l + 1]; ++k) {
+    const double sd = init_scale / std::sqrt((double)NET_TERMS * channels[l]);
+    for (size_t k = 0; k < (size_t)NET_TERMS * channels[l] * channels[l + 1]; ++k) {
       const double u1 = unif(), u2 = unif();
       const double rad = std::sqrt(-2.0 * std::log(u1));
       w[2 * (N->woff[l] + k)] = (float)(sd * rad * std::cos(2 * M_PI * u2));
       w[2 * (N->woff[l] + k) + 1] = (float)(sd * rad * std::sin(2 * M_PI * u2));
     }
+    // W[t][0][0] of t = 0 (P_+) and t = 1 (P_-)
+    w[2 * N->woff[l]] += 1.0f;
+    w[2 * (N->woff[l] + (size_t)channels[l] * channels[l + 1])] += 1.0f;
   }
   const size_t nf = 2 * N->nw;
   if (dmalloc((void**)&N->w32, nf * 4) || dmalloc((void**)&N->m, nf * 4) || dmalloc((void**)&N->v, nf * 4) ||
@@ -374,7 +394,7 @@ int eofa_net_loss_grad(eofa_ctx* C, eofa_net* N, const eofa_system* sys, const v
   (void)hipFree(losses);
   if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return nfail(EOFA_ERR_HIP, "loss read-back failed");
   double L = 0.0;
-  for (int k = 0; k < npairs; ++k) L += lh[k] / en[k];
+  for (int k = 0; k < npairs; ++k) L += sys ? lh[k] : lh[k] / en[k];
   if (loss) *loss = L;
   if (grad) NHIP(hipMemcpy(grad, N->gw, sizeof(double) * 2 * N->nw, hipMemcpyDeviceToHost));
   return EOFA_OK;
@@ -414,7 +434,7 @@ int eofa_net_train(eofa_ctx* C, eofa_net* N, const eofa_system* sys, const void*
       return nfail(EOFA_ERR_HIP, "training loss read-back failed");
     }
     double L = 0.0;
-    for (int k = 0; k < npairs; ++k) L += lh[k] / en[k];
+    for (int k = 0; k < npairs; ++k) L += sys ? lh[k] : lh[k] / en[k];
     if (loss_per_epoch) loss_per_epoch[ep] = L / npairs;
   }
   (void)hipFree(losses);

@@ -1,15 +1,19 @@
 // Kernels of the gauge-covariant parallel-transport network (flexible
 // preconditioner) and of flexible CG. Not part of the paper's method: the
-// layer form, loss and optimiser are this library's choices.
+// layer form, losses and optimiser are this library's choices.
 //
-// Layer C_in -> C_out on every s-slice, output parity p:
-//   y_c(x) = sum_t sum_c' W[t][c][c'] (T_t X_c')(x),
-//   T_0 = 1, T_{1+mu} psi(x) = U_mu(x) psi(x+mu), T_{5+mu} psi(x) = U_mu(x-mu)^dag psi(x-mu)
-// (boundary phases included: the per-parity links of the hop kernels are
-// exactly these transports). Activations are packed FP32 half-fields with
+// Layer C_in -> C_out, output parity p, 20 terms per channel pair:
+//   y_c(x, s) = sum_t sum_c' W[t][c][c'] (S_t X_c')(x, s),
+//   S_0 = P_+, S_1 = P_-, S_{2+e} = T_e, S_{10+e} = g_mu(e) T_e (e = 0..7),
+//   S_18 X(s) = P_+ X(s-1), S_19 X(s) = P_- X(s+1) (cyclic in s),
+// with the eight transports T_e of the hop kernels' per-parity links
+// (e < 4: U_mu(x) X(x+mu), mu = e; e >= 4: U_mu(x-mu)^dag X(x-mu), mu = e-4;
+// boundary phases included). Activations are packed FP32 half-fields with
 // the channel as the right-hand-side index. Weights: bfloat16 pairs
-// (re, im) [9][C_out][C_in], FP32 arithmetic.
-// Adjoint in X: conj(W[swap t][c][c']) with T_{+mu}^dag = T_{-mu} (swap t).
+// (re, im) [20][C_out][C_in], FP32 arithmetic.
+// Adjoint in X: conj(W[t'][c'][c]) S_t'^dag with T_e^dag = T_{e^4}, g_mu
+// Hermitian and commuting with the transports, P_+- Hermitian and the s
+// shifts reversed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,8 +32,6 @@ __device__ __forceinline__ unsigned short f32_to_bf16(float f) {  // round to ne
   return (unsigned short)(u >> 16);
 }
 
-__device__ __forceinline__ int swap_term(int t) { return t == 0 ? 0 : (t <= 4 ? t + 4 : t - 4); }
-
 // z <- L z for a 12-component spinor (colour matvec per spin), L = 9 complex
 __device__ __forceinline__ void link_mul(const float2* L, cx<float>* z) {
   cx<float> U[9];
@@ -43,146 +45,270 @@ __device__ __forceinline__ void link_mul(const float2* L, cx<float>* z) {
   }
 }
 
-// One thread: one 5D site (i, s) of the output parity and a block of CB
-// output channels c0 .. c0+CB-1. For each stencil term t the input channels
-// are mixed first (z_c = sum_c' W[t][c][c'] X_c'(neighbour)) and the CB mixed
-// spinors are then transported (one link product per term and channel), so
-// every input spinor is loaded once per channel block.
-constexpr int NET_CB = 4;
+__device__ __forceinline__ cx<float> times_i(cx<float> a) { return {-a.i, a.r}; }
 
+// g = g_mu v in the chiral basis of the field layout:
+// g_mu = [[0, A_mu], [A_mu^dag, 0]], A = -i sigma_1, -i sigma_2, -i sigma_3, 1
+__device__ __forceinline__ void gamma_mul(int mu, const cx<float>* v, cx<float>* g) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const cx<float> u0 = v[c], u1 = v[3 + c], l0 = v[6 + c], l1 = v[9 + c];
+    if (mu == 0) {
+      g[c] = -1.f * times_i(l1);
+      g[3 + c] = -1.f * times_i(l0);
+      g[6 + c] = times_i(u1);
+      g[9 + c] = times_i(u0);
+    } else if (mu == 1) {
+      g[c] = -1.f * l1;
+      g[3 + c] = l0;
+      g[6 + c] = u1;
+      g[9 + c] = -1.f * u0;
+    } else if (mu == 2) {
+      g[c] = -1.f * times_i(l0);
+      g[3 + c] = times_i(l1);
+      g[6 + c] = times_i(u0);
+      g[9 + c] = -1.f * times_i(u1);
+    } else {
+      g[c] = l0;
+      g[3 + c] = l1;
+      g[6 + c] = u0;
+      g[9 + c] = u1;
+    }
+  }
+}
+
+// weight of term t from input channel ci to output channel c of this
+// application; the adjoint reads conj(W[t][ci][c]) of the forward layer
+// (whose C_out is this application's C_in)
 template <bool ADJ>
+__device__ __forceinline__ cx<float> wload(const NetLayerArgs& a, int t, int c, int ci) {
+  const size_t k = ADJ ? (((size_t)t * a.Cin + ci) * a.Cout + c) * 2 : (((size_t)t * a.Cout + c) * a.Cin + ci) * 2;
+  const float wr = bf16_to_f32(a.w[k]), wi = bf16_to_f32(a.w[k + 1]);
+  return {wr, ADJ ? -wi : wi};
+}
+
+// One thread: one 5D site (i, s) of the output parity and a block of CB
+// output channels c0 .. c0+CB-1. The work-group first stages the weights it
+// needs, W[t][c0+cc][ci] as FP32 complex (conjugated and transposed for the
+// adjoint), in LDS: every lane reads the same weight, which LDS broadcasts.
+// Per transport direction e the term pair W[2+e] + W[10+e] g_mu is applied
+// in one of two orders (g_mu commutes with the link):
+//  * TF (transport first): each input channel is transported once and then
+//    mixed into the CB outputs: C_in link products, accumulators only;
+//  * otherwise mix first: z_c = sum_c' (W[2+e] + W[10+e] g_mu) X_c'(neighbour)
+//    for the CB outputs, then one link product per output: CB link products,
+//    but CB more spinors of registers.
+// The launcher takes TF when C_in <= CB. Registers: 48 CB (accumulators),
+// plus 48 CB for mix first.
+template <bool ADJ, int CB, bool TF>
 __global__ void __launch_bounds__(256) pt_layer_kernel(NetLayerArgs a) {
+  __shared__ float2 s_w[NET_TERMS * 4 * NET_MAXC];  // [t][cc][ci], CB <= 4
+  const int c0 = blockIdx.y * CB;
+  const int nco = min(CB, a.Cout - c0);
+  for (int k = threadIdx.x; k < NET_TERMS * CB * a.Cin; k += blockDim.x) {
+    const int ci = k % a.Cin, cc = (k / a.Cin) % CB, t = k / (a.Cin * CB);
+    float2 w = {0.f, 0.f};
+    if (cc < nco) {
+      const cx<float> v = wload<ADJ>(a, t, c0 + cc, ci);
+      w = {v.r, v.i};
+    }
+    s_w[k] = w;
+  }
+  __syncthreads();
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int c0 = blockIdx.y * NET_CB;
   if (idx >= a.Vh * a.Ls) return;
+  auto W = [&](int t, int cc, int ci) {
+    const float2 w = s_w[(t * CB + cc) * a.Cin + ci];
+    return cx<float>{w.x, w.y};
+  };
   const int i = idx / a.Ls, s = idx - i * a.Ls;
   const int p = a.parity;
-  const int nco = min(NET_CB, a.Cout - c0);
   const FD fin = {a.Ls, a.Vh, a.Cin};
-  cx<float> acc[NET_CB][12];
+  cx<float> acc[CB][12];
 #pragma unroll
-  for (int cc = 0; cc < NET_CB; ++cc)
+  for (int cc = 0; cc < CB; ++cc)
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[cc][k] = {0.f, 0.f};
-  for (int t = 0; t < 9; ++t) {
-    const int j = t == 0 ? i : a.nbr[(size_t)i * 8 + t - 1];
-    const float* src = a.xin[t == 0 ? p : 1 - p];
-    cx<float> z[NET_CB][12];
-#pragma unroll
-    for (int cc = 0; cc < NET_CB; ++cc)
-#pragma unroll
-      for (int k = 0; k < 12; ++k) z[cc][k] = {0.f, 0.f};
+  // same-parity terms: P_+ and P_- at (x, s); P_+ X(s-1) and P_- X(s+1),
+  // in the adjoint P_+ X(s+1) and P_- X(s-1)
+  {
+    const int sm = s == 0 ? a.Ls - 1 : s - 1, sp = s == a.Ls - 1 ? 0 : s + 1;
+    const int s_up = ADJ ? sp : sm, s_lo = ADJ ? sm : sp;
     for (int ci = 0; ci < a.Cin; ++ci) {
-      cx<float> v[12];
-      ld_spinor<P32>(src, fin, ci, s, j, v);
+      cx<float> v[12], xu[12], xl[12];
+      ld_spinor<P32>(a.xin[p], fin, ci, s, i, v);
+      ld_spinor<P32>(a.xin[p], fin, ci, s_up, i, xu);
+      ld_spinor<P32>(a.xin[p], fin, ci, s_lo, i, xl);
 #pragma unroll
-      for (int cc = 0; cc < NET_CB; ++cc) {
-        if (cc >= nco) break;
-        const int c = c0 + cc;
-        size_t k;
-        float wr, wi;
-        if (!ADJ) {
-          k = (((size_t)t * a.Cout + c) * a.Cin + ci) * 2;
-          wr = bf16_to_f32(a.w[k]);
-          wi = bf16_to_f32(a.w[k + 1]);
-        } else {  // forward layer had C_out = a.Cin, C_in = a.Cout
-          k = (((size_t)swap_term(t) * a.Cin + ci) * a.Cout + c) * 2;
-          wr = bf16_to_f32(a.w[k]);
-          wi = -bf16_to_f32(a.w[k + 1]);
-        }
-        const cx<float> w = {wr, wi};
+      for (int cc = 0; cc < CB; ++cc) {
+        const cx<float> w0 = W(0, cc, ci), w1 = W(1, cc, ci), w18 = W(18, cc, ci), w19 = W(19, cc, ci);
 #pragma unroll
-        for (int q = 0; q < 12; ++q) z[cc][q] = cfma(w, v[q], z[cc][q]);
+        for (int q = 0; q < 6; ++q) acc[cc][q] = cfma(w18, xu[q], cfma(w0, v[q], acc[cc][q]));
+#pragma unroll
+        for (int q = 6; q < 12; ++q) acc[cc][q] = cfma(w19, xl[q], cfma(w1, v[q], acc[cc][q]));
       }
     }
+  }
+  for (int e = 0; e < 8; ++e) {
+    const int j = a.nbr[(size_t)i * 8 + e];
+    const int te = ADJ ? (e ^ 4) : e;  // T_e^dag = T_{e^4}
+    const int mu = e & 3;
+    const float2* L = (const float2*)a.links + ((size_t)i * 8 + e) * 9;
+    if constexpr (TF) {
+      for (int ci = 0; ci < a.Cin; ++ci) {
+        cx<float> v[12], gv[12];
+        ld_spinor<P32>(a.xin[1 - p], fin, ci, s, j, v);
+        link_mul(L, v);
+        gamma_mul(mu, v, gv);
 #pragma unroll
-    for (int cc = 0; cc < NET_CB; ++cc) {
-      if (cc >= nco) break;
-      if (t > 0) link_mul((const float2*)a.links + ((size_t)i * 8 + t - 1) * 9, z[cc]);
+        for (int cc = 0; cc < CB; ++cc) {
+          const cx<float> wa = W(2 + te, cc, ci), wb = W(10 + te, cc, ci);
 #pragma unroll
-      for (int q = 0; q < 12; ++q) acc[cc][q] = acc[cc][q] + z[cc][q];
+          for (int q = 0; q < 12; ++q) acc[cc][q] = cfma(wb, gv[q], cfma(wa, v[q], acc[cc][q]));
+        }
+      }
+    } else {
+      cx<float> z[CB][12];
+#pragma unroll
+      for (int cc = 0; cc < CB; ++cc)
+#pragma unroll
+        for (int k = 0; k < 12; ++k) z[cc][k] = {0.f, 0.f};
+      for (int ci = 0; ci < a.Cin; ++ci) {
+        cx<float> v[12], gv[12];
+        ld_spinor<P32>(a.xin[1 - p], fin, ci, s, j, v);
+        gamma_mul(mu, v, gv);
+#pragma unroll
+        for (int cc = 0; cc < CB; ++cc) {
+          const cx<float> wa = W(2 + te, cc, ci), wb = W(10 + te, cc, ci);
+#pragma unroll
+          for (int q = 0; q < 12; ++q) z[cc][q] = cfma(wb, gv[q], cfma(wa, v[q], z[cc][q]));
+        }
+      }
+#pragma unroll
+      for (int cc = 0; cc < CB; ++cc) {
+        if (cc >= nco) break;
+        link_mul(L, z[cc]);
+#pragma unroll
+        for (int q = 0; q < 12; ++q) acc[cc][q] = acc[cc][q] + z[cc][q];
+      }
     }
   }
   const FD fo = {a.Ls, a.Vh, a.Cout};
 #pragma unroll
-  for (int cc = 0; cc < NET_CB; ++cc) {
+  for (int cc = 0; cc < CB; ++cc) {
     if (cc >= nco) break;
     st_spinor<P32>(a.yout, fo, c0 + cc, s, i, acc[cc]);
   }
 }
 
-// dL/dW*[t][c][ci] partial sums: sum over sites of G_c(x) . conj((T_t X_ci)(x)).
-// Work-group (blk, t*ncb + cb, parity): term t, output channels
-// cb*NET_CB .. +NET_CB-1, all input channels; each thread loads its site's
-// G_c once and each transported input once per channel block.
+// dL/dW*[t][c][ci] partial sums: sum over sites of G_c(x) . conj((S_t X_ci)(x)).
+// Work-group (blk, grp * ncb + cb, parity) computes two terms of group grp:
+// grp < 8 the transport e = grp (terms 2+e and 10+e), grp = 8 the same-site
+// chirality terms (0, 1), grp = 9 the s shifts (18, 19); output channels
+// cb*WG_CB .. +WG_CB-1, all input channels. Each thread loads its site's G_c
+// once and each transported input once per channel block.
+constexpr int WG_CB = 2;
+constexpr int WG_GROUPS = 10;
+
 __global__ void __launch_bounds__(256) pt_wgrad_kernel(NetGradArgs a) {
-  const int ncb = (a.Cout + NET_CB - 1) / NET_CB;
-  const int t = blockIdx.y / ncb, cb = blockIdx.y - t * ncb;
-  const int c0 = cb * NET_CB;
-  const int nco = min(NET_CB, a.Cout - c0);
+  const int ncb = (a.Cout + WG_CB - 1) / WG_CB;
+  const int grp = blockIdx.y / ncb, cb = blockIdx.y - grp * ncb;
+  const int c0 = cb * WG_CB;
+  const int nco = min(WG_CB, a.Cout - c0);
   const int p = blockIdx.z;
   const FD fx = {a.Ls, a.Vh, a.Cin}, fg = {a.Ls, a.Vh, a.Cout};
-  float ar[NET_CB][NET_MAXC], ai[NET_CB][NET_MAXC];
+  // [cc][ci][term a / b]
+  float ar[WG_CB][NET_MAXC][2], ai[WG_CB][NET_MAXC][2];
 #pragma unroll
-  for (int cc = 0; cc < NET_CB; ++cc)
+  for (int cc = 0; cc < WG_CB; ++cc)
 #pragma unroll
-    for (int ci = 0; ci < NET_MAXC; ++ci) ar[cc][ci] = ai[cc][ci] = 0.f;
+    for (int ci = 0; ci < NET_MAXC; ++ci)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) ar[cc][ci][h] = ai[cc][ci][h] = 0.f;
   const int n = a.Vh * a.Ls;
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += gridDim.x * blockDim.x) {
     const int i = idx / a.Ls, s = idx - i * a.Ls;
-    const int j = t == 0 ? i : a.nbr[p][(size_t)i * 8 + t - 1];
-    cx<float> g[NET_CB][12];
+    cx<float> g[WG_CB][12];
 #pragma unroll
-    for (int cc = 0; cc < NET_CB; ++cc) {
+    for (int cc = 0; cc < WG_CB; ++cc) {
       if (cc >= nco) break;
       ld_spinor<P32>(a.g[p], fg, c0 + cc, s, i, g[cc]);
     }
 #pragma unroll
     for (int ci = 0; ci < NET_MAXC; ++ci) {
       if (ci >= a.Cin) break;
-      cx<float> v[12];
-      ld_spinor<P32>(a.x[t == 0 ? p : 1 - p], fx, ci, s, j, v);
-      if (t > 0) link_mul((const float2*)a.links[p] + ((size_t)i * 8 + t - 1) * 9, v);
+      // va = S_ta X_ci, vb = S_tb X_ci at (x, s)
+      cx<float> va[12], vb[12];
+      if (grp < 8) {
+        const int j = a.nbr[p][(size_t)i * 8 + grp];
+        ld_spinor<P32>(a.x[1 - p], fx, ci, s, j, va);
+        link_mul((const float2*)a.links[p] + ((size_t)i * 8 + grp) * 9, va);
+        gamma_mul(grp & 3, va, vb);
+      } else if (grp == 8) {
+        ld_spinor<P32>(a.x[p], fx, ci, s, i, va);
 #pragma unroll
-      for (int cc = 0; cc < NET_CB; ++cc) {
+        for (int q = 0; q < 12; ++q) vb[q] = va[q];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) vb[q] = {0.f, 0.f};
+#pragma unroll
+        for (int q = 6; q < 12; ++q) va[q] = {0.f, 0.f};
+      } else {
+        ld_spinor<P32>(a.x[p], fx, ci, s == 0 ? a.Ls - 1 : s - 1, i, va);
+        ld_spinor<P32>(a.x[p], fx, ci, s == a.Ls - 1 ? 0 : s + 1, i, vb);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) vb[q] = {0.f, 0.f};
+#pragma unroll
+        for (int q = 6; q < 12; ++q) va[q] = {0.f, 0.f};
+      }
+#pragma unroll
+      for (int cc = 0; cc < WG_CB; ++cc) {
         if (cc >= nco) break;
-        float sr = 0.f, si = 0.f;
+        float sr0 = 0.f, si0 = 0.f, sr1 = 0.f, si1 = 0.f;
 #pragma unroll
         for (int q = 0; q < 12; ++q) {  // g * conj(v)
-          sr = fmaf(g[cc][q].r, v[q].r, fmaf(g[cc][q].i, v[q].i, sr));
-          si = fmaf(g[cc][q].i, v[q].r, fmaf(-g[cc][q].r, v[q].i, si));
+          sr0 = fmaf(g[cc][q].r, va[q].r, fmaf(g[cc][q].i, va[q].i, sr0));
+          si0 = fmaf(g[cc][q].i, va[q].r, fmaf(-g[cc][q].r, va[q].i, si0));
+          sr1 = fmaf(g[cc][q].r, vb[q].r, fmaf(g[cc][q].i, vb[q].i, sr1));
+          si1 = fmaf(g[cc][q].i, vb[q].r, fmaf(-g[cc][q].r, vb[q].i, si1));
         }
-        ar[cc][ci] += sr;
-        ai[cc][ci] += si;
+        ar[cc][ci][0] += sr0;
+        ai[cc][ci][0] += si0;
+        ar[cc][ci][1] += sr1;
+        ai[cc][ci][1] += si1;
       }
     }
   }
-  // reduce the NET_CB x C_in complex sums over the work-group
-  __shared__ double red[4][2 * NET_CB * NET_MAXC];
+  // reduce the WG_CB x C_in x 2 complex sums over the work-group
+  constexpr int NV = 2 * WG_CB * NET_MAXC * 2;  // (cc, ci, h, comp)
+  __shared__ double red[4][NV];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int cc = 0; cc < NET_CB; ++cc)
+  for (int cc = 0; cc < WG_CB; ++cc)
 #pragma unroll
-    for (int ci = 0; ci < NET_MAXC; ++ci) {
-      if (cc >= nco || ci >= a.Cin) continue;
-      double vr = ar[cc][ci], vi = ai[cc][ci];
+    for (int ci = 0; ci < NET_MAXC; ++ci)
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        vr += __shfl_xor(vr, off, 64);
-        vi += __shfl_xor(vi, off, 64);
+      for (int h = 0; h < 2; ++h) {
+        if (cc >= nco || ci >= a.Cin) continue;
+        double vr = ar[cc][ci][h], vi = ai[cc][ci][h];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          vr += __shfl_xor(vr, off, 64);
+          vi += __shfl_xor(vi, off, 64);
+        }
+        if (lane == 0) {
+          const int k = ((cc * NET_MAXC + ci) * 2 + h) * 2;
+          red[wv][k] = vr;
+          red[wv][k + 1] = vi;
+        }
       }
-      if (lane == 0) {
-        red[wv][2 * (cc * NET_MAXC + ci)] = vr;
-        red[wv][2 * (cc * NET_MAXC + ci) + 1] = vi;
-      }
-    }
   __syncthreads();
-  const int k = threadIdx.x;  // (cc, ci, comp)
-  if (k < 2 * NET_CB * NET_MAXC) {
-    const int comp = k & 1, cc = (k >> 1) / NET_MAXC, ci = (k >> 1) % NET_MAXC;
+  const int k = threadIdx.x;
+  if (k < NV) {
+    const int comp = k & 1, h = (k >> 1) & 1, ci = (k >> 2) % NET_MAXC, cc = (k >> 2) / NET_MAXC;
     if (cc < nco && ci < a.Cin) {
       double tsum = 0.0;
       for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) tsum += red[w][k];
+      const int t = grp < 8 ? (h ? 10 + grp : 2 + grp) : grp == 8 ? h : 18 + h;
       const int y = t * a.Cin + ci, c = c0 + cc;
       a.partial[((((size_t)y * 2 + p) * a.Cout + c) * gridDim.x + blockIdx.x) * 2 + comp] = tsum;
     }
@@ -191,8 +317,8 @@ __global__ void __launch_bounds__(256) pt_wgrad_kernel(NetGradArgs a) {
 
 // gW[t][c][ci] (+)= sum over parity and blocks (fixed order), as (re, im) doubles
 __global__ void pt_wgrad_final(const double* partial, int Cin, int Cout, int nblk, int accumulate, double* gw) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;  // over 9*Cout*Cin*2
-  if (k >= 9 * Cout * Cin * 2) return;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;  // over NET_TERMS*Cout*Cin*2
+  if (k >= NET_TERMS * Cout * Cin * 2) return;
   const int comp = k & 1, rest = k >> 1;
   const int ci = rest % Cin, c = (rest / Cin) % Cout, t = rest / (Cin * Cout);
   const int y = t * Cin + ci;
@@ -200,6 +326,87 @@ __global__ void pt_wgrad_final(const double* partial, int Cin, int Cout, int nbl
   for (int p = 0; p < 2; ++p)
     for (int b = 0; b < nblk; ++b) s += partial[((((size_t)y * 2 + p) * Cout + c) * nblk + b) * 2 + comp];
   gw[k] = accumulate ? gw[k] + s : s;
+}
+
+// residual loss: partial sums of <a, r> (re, im) and |a|^2 over one-channel
+// FP32 odd half-fields, as [3][nblk]
+__global__ void __launch_bounds__(256) net_dot_kernel(int Vh, int Ls, const float* av, const float* rv,
+                                                      double* partial) {
+  const FD f = {Ls, Vh, 1};
+  double cr = 0.0, ci = 0.0, na = 0.0;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < Vh * Ls; idx += gridDim.x * blockDim.x) {
+    const int i = idx / Ls, s = idx - i * Ls;
+    cx<float> x[12], y[12];
+    ld_spinor<P32>(av, f, 0, s, i, x);
+    ld_spinor<P32>(rv, f, 0, s, i, y);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {  // conj(a) r
+      cr += (double)x[q].r * y[q].r + (double)x[q].i * y[q].i;
+      ci += (double)x[q].r * y[q].i - (double)x[q].i * y[q].r;
+      na += (double)x[q].r * x[q].r + (double)x[q].i * x[q].i;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    cr += __shfl_xor(cr, off, 64);
+    ci += __shfl_xor(ci, off, 64);
+    na += __shfl_xor(na, off, 64);
+  }
+  __shared__ double red[4][3];
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6][0] = cr;
+    red[threadIdx.x >> 6][1] = ci;
+    red[threadIdx.x >> 6][2] = na;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double tsum = 0.0;
+    for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) tsum += red[w][threadIdx.x];
+    partial[threadIdx.x * gridDim.x + blockIdx.x] = tsum;
+  }
+}
+
+// loss = 1 - |c|^2/(|a|^2 |r|^2), c = <a, r>, and the coefficients of
+// dL/da* = alpha a + beta r: alpha = |c|^2/(|a|^4 |r|^2), beta = -conj(c)/(|a|^2 |r|^2)
+// as coef = (alpha, Re beta, Im beta); a = 0 (or a non-finite sum) gives
+// loss 1 and zero coefficients
+__global__ void net_resid_coef_kernel(const double* partial, int nblk, const double* rnorm, double* loss,
+                                      double* coef) {
+  if (threadIdx.x != 0) return;
+  double cr = 0.0, ci = 0.0, na = 0.0;
+  for (int b = 0; b < nblk; ++b) {
+    cr += partial[b];
+    ci += partial[nblk + b];
+    na += partial[2 * nblk + b];
+  }
+  const double nr = *rnorm, c2 = cr * cr + ci * ci;
+  const double l = 1.0 - c2 / (na * nr);
+  if (!(na > 0.0) || !(nr > 0.0) || !isfinite(l)) {
+    *loss = 1.0;
+    coef[0] = coef[1] = coef[2] = 0.0;
+    return;
+  }
+  *loss = l;
+  coef[0] = c2 / (na * na * nr);
+  coef[1] = -cr / (na * nr);
+  coef[2] = ci / (na * nr);
+}
+
+// out = alpha a + beta r (one-channel FP32 odd half-fields)
+__global__ void __launch_bounds__(256) net_combine_kernel(int Vh, int Ls, const float* av, const float* rv,
+                                                          const double* coef, float* out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= Vh * Ls) return;
+  const int i = idx / Ls, s = idx - i * Ls;
+  const FD f = {Ls, Vh, 1};
+  const float al = (float)coef[0];
+  const cx<float> be = {(float)coef[1], (float)coef[2]};
+  cx<float> x[12], y[12];
+  ld_spinor<P32>(av, f, 0, s, i, x);
+  ld_spinor<P32>(rv, f, 0, s, i, y);
+#pragma unroll
+  for (int q = 0; q < 12; ++q) x[q] = cfma(be, y[q], al * x[q]);
+  st_spinor<P32>(out, f, 0, s, i, x);
 }
 
 // loss seed: G = (y - e)/|e|^2 on the odd sites; partial |y - e|^2
@@ -390,20 +597,44 @@ __global__ void __launch_bounds__(256) fgcg_update_kernel(int n, const double* a
 
 // ---------------------------------------------------------------------------
 
-void launch_pt_layer(const NetLayerArgs& a, bool adj, hipStream_t st) {
-  dim3 grid((a.Vh * a.Ls + 255) / 256, (a.Cout + NET_CB - 1) / NET_CB);
+template <int CB, bool TF>
+void launch_pt_layer_cb(const NetLayerArgs& a, bool adj, hipStream_t st) {
+  dim3 grid((a.Vh * a.Ls + 255) / 256, (a.Cout + CB - 1) / CB);
   if (adj)
-    hipLaunchKernelGGL(pt_layer_kernel<true>, grid, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((pt_layer_kernel<true, CB, TF>), grid, dim3(256), 0, st, a);
   else
-    hipLaunchKernelGGL(pt_layer_kernel<false>, grid, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((pt_layer_kernel<false, CB, TF>), grid, dim3(256), 0, st, a);
+}
+
+// channel block and order by shape: one output channel mixes first (one
+// link product per direction); few inputs transport first; many inputs and
+// outputs mix first in blocks of 2
+void launch_pt_layer(const NetLayerArgs& a, bool adj, hipStream_t st) {
+  if (a.Cout == 1)
+    launch_pt_layer_cb<1, false>(a, adj, st);
+  else if (a.Cout == 2 && a.Cin <= 2)
+    launch_pt_layer_cb<2, true>(a, adj, st);
+  else if (a.Cin <= 4)
+    launch_pt_layer_cb<4, true>(a, adj, st);
+  else
+    launch_pt_layer_cb<2, false>(a, adj, st);
 }
 
 void launch_pt_wgrad(const NetGradArgs& a, int nblk, int accumulate, double* gw, hipStream_t st) {
-  dim3 grid(nblk, 9 * ((a.Cout + NET_CB - 1) / NET_CB), 2);
+  dim3 grid(nblk, WG_GROUPS * ((a.Cout + WG_CB - 1) / WG_CB), 2);
   hipLaunchKernelGGL(pt_wgrad_kernel, grid, dim3(256), 0, st, a);
-  const int n = 9 * a.Cout * a.Cin * 2;
+  const int n = NET_TERMS * a.Cout * a.Cin * 2;
   hipLaunchKernelGGL(pt_wgrad_final, dim3((n + 255) / 256), dim3(256), 0, st, a.partial, a.Cin, a.Cout, nblk,
                      accumulate, gw);
+}
+
+void launch_net_resid(int Vh, int Ls, const float* av, const float* rv, const double* rnorm, double* partial,
+                      double* loss, double* coef, float* out, hipStream_t st) {
+  const int n = Vh * Ls;
+  const int nblk = std::min(NET_DOT_BLOCKS, (n + 255) / 256);
+  hipLaunchKernelGGL(net_dot_kernel, dim3(nblk), dim3(256), 0, st, Vh, Ls, av, rv, partial);
+  hipLaunchKernelGGL(net_resid_coef_kernel, dim3(1), dim3(64), 0, st, partial, nblk, rnorm, loss, coef);
+  hipLaunchKernelGGL(net_combine_kernel, dim3((n + 255) / 256), dim3(256), 0, st, Vh, Ls, av, rv, coef, out);
 }
 
 int launch_net_loss(int Vh, int Ls, const float* y, const float* e, float* g, const double* enorm, double* partial,

@@ -6,12 +6,14 @@
 
 namespace eofa {
 
-constexpr int NET_MAXC = 8;  // most channels per layer
+constexpr int NET_MAXC = 8;       // most channels per layer
+constexpr int NET_TERMS = 20;     // stencil terms per channel pair
+constexpr int NET_DOT_BLOCKS = 256;  // work-groups of the residual-loss reductions
 
 struct NetLayerArgs {
   const float* xin[2];       // packed FP32 activations of both parities, Cin channels
   float* yout;               // packed FP32 output of parity `parity`, Cout channels
-  const unsigned short* w;   // bfloat16 (re, im) [9][Cout_fwd][Cin_fwd] of the forward layer
+  const unsigned short* w;   // bfloat16 (re, im) [20][Cout_fwd][Cin_fwd] of the forward layer
   const float* links;        // FP32 links of the output parity [Vh][8][9] complex
   const int* nbr;            // [Vh][8] neighbour index in the other parity
   int Vh, Ls, Cin, Cout;     // of this (forward or adjoint) application
@@ -23,12 +25,17 @@ struct NetGradArgs {
   const float* g[2];         // dL/dy* at the layer output, both parities, Cout channels
   const float* links[2];
   const int* nbr[2];
-  double* partial;           // [9*Cin][2][Cout][nblk][2]
+  double* partial;           // [20*Cin][2][Cout][nblk][2]
   int Vh, Ls, Cin, Cout;
 };
 
 void launch_pt_layer(const NetLayerArgs& a, bool adj, hipStream_t st);
 void launch_pt_wgrad(const NetGradArgs& a, int nblk, int accumulate, double* gw, hipStream_t st);
+// residual loss of one pair: partial [3 * NET_DOT_BLOCKS] scratch; *loss =
+// 1 - |<a, r>|^2/(|a|^2 |r|^2) (rnorm = |r|^2 on the device), coef[3] the
+// coefficients of dL/da*, out = dL/da* (one-channel FP32 odd half-fields)
+void launch_net_resid(int Vh, int Ls, const float* av, const float* rv, const double* rnorm, double* partial,
+                      double* loss, double* coef, float* out, hipStream_t st);
 int launch_net_loss(int Vh, int Ls, const float* y, const float* e, float* g, const double* enorm, double* partial,
                     hipStream_t st);
 void launch_net_adam(int n, float* w, float* m, float* v, const double* gw, double scale, float lr, float b1,

@@ -324,8 +324,12 @@ class Context:
         return rc, rec.value, its.value
 
 
+NET_TERMS = 20  # stencil terms per channel pair of a network layer
+
+
 class Net:
-    """An eofa_net: the gauge-covariant parallel-transport network (device weights)."""
+    """An eofa_net: N = B^dag B with B a stack of gauge-covariant
+    parallel-transport layers (device weights)."""
 
     def __init__(self, ctx, channels, seed=0, init_scale=1.0):
         self.channels = [int(c) for c in channels]
@@ -348,7 +352,7 @@ class Net:
         return int(lib().eofa_net_num_weights(self._h))
 
     def get_weights(self):
-        """Complex weights as a list of [9, C_out, C_in] arrays (FP32 master values)."""
+        """Complex weights as a list of [NET_TERMS, C_out, C_in] arrays (FP32 master values)."""
         n = self.num_weights()
         buf = (ctypes.c_double * (2 * n))()
         _check(lib().eofa_net_get_weights(self._h, buf))
@@ -356,8 +360,8 @@ class Net:
         flat = flat[0::2] + 1j * flat[1::2]
         out, k = [], 0
         for ci, co in zip(self.channels[:-1], self.channels[1:]):
-            out.append(flat[k:k + 9 * co * ci].reshape(9, co, ci))
-            k += 9 * co * ci
+            out.append(flat[k:k + NET_TERMS * co * ci].reshape(NET_TERMS, co, ci))
+            k += NET_TERMS * co * ci
         return out
 
     def set_weights(self, weights):
@@ -372,7 +376,8 @@ class Net:
 
     def loss_grad(self, ctx, r, e, npairs, system=None, stream=None):
         """(loss, [dL/dW* per layer]) over npairs packed FP32 pairs; with ``system``
-        the residual loss |A N(r) - r|^2/|r|^2 (e unused), else the error loss."""
+        the scale-free residual loss 1 - |<A N(r), r>|^2/(|A N(r)|^2 |r|^2)
+        summed over pairs (e unused), else the error loss |N(r) - e|^2/|e|^2."""
         n = self.num_weights()
         loss = ctypes.c_double()
         g = (ctypes.c_double * (2 * n))()
@@ -382,8 +387,8 @@ class Net:
         flat = flat[0::2] + 1j * flat[1::2]
         out, k = [], 0
         for ci, co in zip(self.channels[:-1], self.channels[1:]):
-            out.append(flat[k:k + 9 * co * ci].reshape(9, co, ci))
-            k += 9 * co * ci
+            out.append(flat[k:k + NET_TERMS * co * ci].reshape(NET_TERMS, co, ci))
+            k += NET_TERMS * co * ci
         return loss.value, out
 
     def train(self, ctx, r, e, npairs, epochs, batch, lr, system=None, stream=None):

@@ -4,9 +4,12 @@ CG) against the network oracle, through the C ABI.
 
 Tolerances: the network runs in FP32 with bfloat16 weights; the oracle uses
 the same bfloat16-rounded weight values and the FP32-rounded inputs in FP64,
-so the remaining difference is FP32 accumulation over at most
-9 terms x 8 channels x 4 layers: 1e-5 relative (max-norm) for outputs and
-the loss, 1e-4 for weight gradients (sums over all sites in FP32 partials).
+so the remaining difference is FP32 accumulation over 20 terms x at most 8
+channels per layer through the 2 x 3 layers of B^dag B: each layer adds a
+few 2^-24 relative errors of its largest terms, about 1e-6 after six layers,
+so 1e-5 relative (max-norm) for outputs, 1e-4 for the loss and the weight
+gradients (sums over all sites of FP32 products, and FP32 applications of
+A = M^dag M in the residual loss).
 Solves: FP64 true residual <= 1e-10, re-measured by the oracle.
 """
 import numpy as np
@@ -80,7 +83,8 @@ def from_packed(ctx, packed, n=1):
 
 def rand_weights(chans, seed, scale=0.4):
     rng = np.random.default_rng(seed)
-    return [scale * (rng.standard_normal((9, co, ci)) + 1j * rng.standard_normal((9, co, ci)))
+    T = nn.NTERMS
+    return [scale * (rng.standard_normal((T, co, ci)) + 1j * rng.standard_normal((T, co, ci)))
             for ci, co in zip(chans[:-1], chans[1:])]
 
 
@@ -132,7 +136,8 @@ def test_loss_and_gradients_match_oracle():
 
 
 def test_residual_loss_and_gradients_match_oracle():
-    """|A N(r) - r|^2/|r|^2 with A = M^dag M applied in FP32 on the GPU, FP64 in the oracle."""
+    """1 - |<A N(r), r>|^2/(|A N(r)|^2 |r|^2) with A = M^dag M applied in FP32 on
+    the GPU, FP64 in the oracle."""
     act, U, ctx = make(seed=19)
     sysm = System(0.2, 0.0, 0.0, 0.0, 1)
     net = eofa.Net(ctx, CHANS, seed=3)
@@ -219,7 +224,7 @@ def test_training_residual_loss_reduces_loss():
     assert all(np.isfinite(hist))
     loss1, _ = net.loss_grad(ctx, r, None, rec, system=sysm)
     print("residual loss per pair: untrained", loss0 / rec, "epochs", hist[0], hist[-1], "trained", loss1 / rec)
-    assert loss1 < 0.5 * loss0 and loss1 / rec < 1.0
+    assert loss1 < 0.9 * loss0 and loss1 / rec < 1.0
 
 
 @pytest.mark.parametrize("which", ["identity", "trained", "zero"])
@@ -231,7 +236,7 @@ def test_fgcg_reaches_fp64_residual(which):
     if which != "identity":
         net = eofa.Net(ctx, CHANS, seed=9, init_scale=0.5)
         if which == "zero":
-            net.set_weights([np.zeros((9, co, ci)) for ci, co in zip(CHANS[:-1], CHANS[1:])])
+            net.set_weights([np.zeros((nn.NTERMS, co, ci)) for ci, co in zip(CHANS[:-1], CHANS[1:])])
         else:
             r, _, rec, _ = _pairs(ctx, sysm, 16, 2, 91)
             net.train(ctx, r, None, rec, epochs=20, batch=4, lr=3e-3, system=sysm)
@@ -262,3 +267,56 @@ def test_fgcg_identity_iterations_match_cgnr():
     rc, st_c = ctx.eofa_cg_solve([sysm], phi, torch.zeros_like(phi), eofa.make_params(tol=1e-10, check_every=1))
     assert rc == eofa.EOFA_OK
     assert abs(st_f[0]["iters"] - st_c[0]["iters"]) <= max(3, 0.1 * st_c[0]["iters"])
+
+
+def test_network_is_hermitian_positive_on_gpu():
+    """<a, N b> = <N a, b> and <a, N a> > 0 for the GPU network (N = B^dag B)."""
+    act, U, ctx = make(seed=20)
+    net = eofa.Net(ctx, CHANS, seed=5)
+    net.set_weights(rand_weights(CHANS, 21, scale=0.3))
+    a, b = odd_field(DIMS, LS, 150), odd_field(DIMS, LS, 151)
+    pa, pb = ctx.new_packed(eofa.FP32), ctx.new_packed(eofa.FP32)
+    net.apply(ctx, to_packed(ctx, a), pa)
+    net.apply(ctx, to_packed(ctx, b), pb)
+    Na, Nb = from_packed(ctx, pa)[0], from_packed(ctx, pb)[0]
+    lhs, rhs = np.vdot(f32(a[0]), Nb), np.vdot(Na, f32(b[0]))
+    assert abs(lhs - rhs) < 1e-5 * abs(lhs)
+    q = np.vdot(f32(a[0]), Na)
+    assert q.real > 0 and abs(q.imag) < 1e-5 * q.real
+
+
+def test_trained_network_beats_identity_on_held_out_field():
+    """The purpose of the learned preconditioner: trained (residual loss) on
+    CG residuals of one gauge field, flexible CG with N needs fewer
+    iterations than flexible CG with the identity (plain CGNR) on a held-out
+    source of that field and on a held-out field of the same ensemble
+    (4^4 x Ls = 8, links exp(i 0.5 H), m1 = 0.04, m2 = 1.0)."""
+    dims, Ls = (4, 4, 4, 4), 8
+    sysm = System(1.0, 0.04, 1.0, -1.0, +1)
+    act, U, ctx = make(dims, Ls, eps=0.5, seed=3000)
+    b = ctx.packed_bytes(eofa.FP32)
+    parts, n = [], 0
+    for k in range(4):
+        r, _, rec, _ = _pairs(ctx, sysm, 64, 3, 3100 + k)
+        parts.append(r[:rec * b])
+        n += rec
+    R = torch.cat(parts)
+    net = eofa.Net(ctx, [1, 4, 1], seed=1, init_scale=0.25)
+    loss0, _ = net.loss_grad(ctx, R, None, n, system=sysm)
+    hist = net.train(ctx, R, None, n, epochs=6, batch=16, lr=1e-2, system=sysm)
+    assert all(np.isfinite(hist))
+
+    def iters(c, seed, use_net):
+        phi = dev(synth.fermion(dims, Ls, seed, nrhs=1))
+        prm = eofa.make_params(tol=1e-10, precond=1, net=net if use_net else None, check_every=1)
+        rc, st = c.eofa_cg_solve([sysm], phi, torch.zeros_like(phi), prm)
+        assert rc == eofa.EOFA_OK and st[0]["converged"] == 1 and st[0]["true_resid"] <= 1e-10
+        assert st[0]["fell_back"] == 0
+        return st[0]["iters"]
+
+    _, _, ctx1 = make(dims, Ls, eps=0.5, seed=4000)
+    res = {"source": (iters(ctx, 3104, False), iters(ctx, 3104, True)),
+           "field": (iters(ctx1, 4100, False), iters(ctx1, 4100, True))}
+    print("residual loss per pair", loss0 / n, "->", hist[-1], "; FGCG iterations (identity, trained):", res)
+    for ident, trained in res.values():
+        assert trained <= 0.85 * ident
