@@ -399,6 +399,7 @@ def bench_learned(args, eofa, synth, torch, np):
         "mixed_fp16s": eofa.make_params(tol=1e-10, inner_prec=eofa.FP16S, keep_direction=1),
         "fgcg_identity": eofa.make_params(tol=1e-10, precond=1),
         "fgcg_learned": eofa.make_params(tol=1e-10, precond=1, net=net),
+        "fgcg_learned_window8": eofa.make_params(tol=1e-10, precond=1, net=net, fcg_window=8),
     }
     res = {k: [] for k in modes}
     t_apply = None

@@ -128,12 +128,15 @@ typedef struct {
   int32_t use_graph;   /* 1: capture check_every inner iterations in a HIP graph and replay it */
   int32_t rhs_block;   /* right-hand sides per work-group in the hop kernels (links staged once
                           per work-group serve all of them); 0 = autotune                     */
-  int32_t waves;       /* waves per work-group in the hop kernels (1, 2, 4); 0 = autotune     */
+  int32_t waves;       /* waves per work-group in the hop kernels (1, 2, 4); 0 = autotune
+                          (rhs_block and waves both 0: the pair is timed on the first solve of
+                          a shape and kept for the process, per device and lattice)          */
   int32_t precond;     /* 0: CGNR as above; 1: flexible CG on the normal equations in FP64 with
                           the learned preconditioner `net` (NULL = identity), one right-hand
                           side at a time, falling back to CGNR on breakdown or stagnation     */
   int32_t fcg_window;  /* precond = 1: previous directions each new one is A-orthogonalised
-                          against (1..32; 0 = 8 with a network, 1 without)                     */
+                          against (1..32; 0 = 1: the network is Hermitian positive
+                          semi-definite, so one suffices; more guard against rounding)        */
   const eofa_net* net; /* precond = 1: network (eofa_net_create), evaluated in FP32             */
   int32_t use_guess;   /* 1: psi holds an initial guess on entry (canonical layout; the
                           iteration starts from psi' = D~^-1 psi on the odd sublattice)       */

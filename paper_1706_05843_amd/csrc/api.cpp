@@ -608,13 +608,31 @@ int inner_iteration(eofa_ctx* C, const Form& F, int S, const HopArgs& k1, const 
 
 // Autotuner: time the four inner hop kernels for each (waves per
 // work-group, right-hand sides per work-group) candidate on the solve's own
-// buffers (halt flags off, before the CG state exists) and keep the fastest.
+// buffers (halt flags off, before the CG state exists) and keep the fastest
+// (best of three timed passes per candidate). Picks are kept per context
+// and in a process-wide cache keyed by device, lattice and the context key,
+// so a later context of the same shape does not tune again.
 int tune_key(const Form& F, int S, int nrhs) { return ((F.cayley ? 0 : 8) + S) * 4096 + nrhs; }
+
+std::mutex g_tune_mu;
+std::map<std::vector<int>, std::pair<int, int>> g_tune_cache;
+
+std::vector<int> tune_cache_key(const eofa_ctx* C, int key) {
+  return {C->device, C->g.L[0], C->g.L[1], C->g.L[2], C->g.L[3], C->g.Ls, key};
+}
 
 int autotune(eofa_ctx* C, const Form& F, int S, int nrhs, HopArgs k1, HopArgs k2, HopArgs k3, HopArgs k4,
              hipStream_t st) {
   const int key = tune_key(F, S, nrhs);
   if (C->tuned.count(key)) return EOFA_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const auto it = g_tune_cache.find(tune_cache_key(C, key));
+    if (it != g_tune_cache.end()) {
+      C->tuned[key] = it->second;
+      return EOFA_OK;
+    }
+  }
   const int Ls = C->g.Ls;
   std::vector<int> waves, blocks;
   for (int w : {1, 2, 4}) {
@@ -641,21 +659,24 @@ int autotune(eofa_ctx* C, const Form& F, int S, int nrhs, HopArgs k1, HopArgs k2
       }
       const int roles[4] = {F.k1, F.k2, F.k3, F.k4};
       for (int k = 0; k < 4; ++k) CHK(hop(C, S, roles[k], a[k], st));  // warm-up
-      HIPCHK(hipEventRecord(e0, st));
-      for (int rep = 0; rep < 2; ++rep)
+      for (int rep = 0; rep < 3; ++rep) {
+        HIPCHK(hipEventRecord(e0, st));
         for (int k = 0; k < 4; ++k) CHK(hop(C, S, roles[k], a[k], st));
-      HIPCHK(hipEventRecord(e1, st));
-      HIPCHK(hipEventSynchronize(e1));
-      float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-      if (ms < best) {
-        best = ms;
-        pick = {w, rb};
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+          best = ms;
+          pick = {w, rb};
+        }
       }
     }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   C->tuned[key] = pick;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[tune_cache_key(C, key)] = pick;
   return EOFA_OK;
 }
 
@@ -1187,7 +1208,7 @@ namespace {
 // FG_WWS + j: <p_j, A p_j> of window slot j.
 constexpr int FG_MAXW = 32;  // most previous directions kept
 enum FgScalar { FG_WW = 0, FG_QZ = 2, FG_PR = 4, FG_ALPHA = 6, FG_BETA = 8, FG_NRM = 10, FG_WWS = 12,
-                FG_N = FG_WWS + FG_MAXW + 2 };
+                FG_BETAS = FG_WWS + FG_MAXW + 2, FG_N = FG_BETAS + 2 * FG_CHUNK };
 
 // One right-hand side, FP64 throughout, on the odd Schur system:
 //   s = b~ - M^ x (Schur residual), r = M^dag s (normal residual),
@@ -1234,7 +1255,7 @@ struct Fgcg {
     for (int k = 0; k < 12; ++k) CHK(ws(C, names[k], b64, bufs[k]));
     CHK(ws(C, "fg_r32", b32, &r32));
     CHK(ws(C, "fg_z32", b32, &z32));
-    const int maxblk = std::max({hop_blocks(P64, g.Vh, g.Ls, 1), (g.Ls * g.Vh + 255) / 256, 2048});
+    const int maxblk = std::max({hop_blocks(P64, g.Vh, g.Ls, 1), (g.Ls * g.Vh + 255) / 256, 512 * FG_CHUNK});
     void* pv;
     CHK(ws(C, "fg_partial", sizeof(double) * 2 * (size_t)maxblk, &pv));
     partial = (double*)pv;
@@ -1330,12 +1351,19 @@ struct Fgcg {
       p = ps[cur];
       q = qs[cur];
       ww = sc + FG_WWS + cur;
+      // (up to FG_CHUNK directions per pass over z and per pass over p)
       launch_convert(P64, P64, g, z, p, 1, st);
-      for (int k = 1; k <= nvalid; ++k) {
-        const int j = (cur - k + m + 1) % (m + 1);
-        launch_cdot(n, qs[j], z, partial, sc + FG_QZ, st);
-        launch_fgcg_ratio(sc + FG_QZ, sc + FG_WWS + j, -1.0, sc + FG_BETA, bad, st);
-        launch_caxpy_dev(n, sc + FG_BETA, ps[j], p, st);
+      for (int k0 = 1; k0 <= nvalid; k0 += FG_CHUNK) {
+        const int nq = std::min(FG_CHUNK, nvalid - k0 + 1);
+        FgPtrs qv{}, pv{};
+        for (int t = 0; t < nq; ++t) {
+          const int j = (cur - (k0 + t) + m + 1) % (m + 1);
+          qv.v[t] = qs[j];
+          qv.ww[t] = sc + FG_WWS + j;
+          pv.v[t] = ps[j];
+        }
+        launch_fgcg_orth_coefs(n, nq, qv, z, partial, sc + FG_BETAS, bad, st);
+        launch_caxpy_multi(n, nq, pv, sc + FG_BETAS, p, st);
       }
     }
     first = false;
@@ -1397,7 +1425,7 @@ int fgcg_one(eofa_ctx* C, const eofa_system* sys, const void* phi, void* psi, co
   F.C = C;
   F.st = st;
   CHK(F.init(sys, phi));
-  CHK(F.set_window(prm->fcg_window > 0 ? prm->fcg_window : (net ? 8 : 1)));
+  CHK(F.set_window(prm->fcg_window > 0 ? prm->fcg_window : 1));
   bool guess_done = false;
   if (prm->use_guess && std::isfinite(F.bb)) {
     // start from x_o = (D~^-1 psi)_o: s = b~ - M^ x, r = M^dag s

@@ -47,6 +47,15 @@ __device__ __forceinline__ void link_mul(const float2* L, cx<float>* z) {
 
 __device__ __forceinline__ cx<float> times_i(cx<float> a) { return {-a.i, a.r}; }
 
+// one chirality half of a packed FP32 spinor: h = 0 the P_+ components
+// 0..5 (into v[0..5]), h = 1 the P_- components 6..11 (into v[6..11])
+__device__ __forceinline__ void ld_half32(const float* base, const FD& f, int r, int s, int i, int h,
+                                          cx<float>* v) {
+  const size_t e0 = eidx(f, r, 0, s, i), qs = qstride(f);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) ld_pair<P32>(base, e0 + (3 * h + q) * qs, v[6 * h + 2 * q], v[6 * h + 2 * q + 1]);
+}
+
 // g = g_mu v in the chiral basis of the field layout:
 // g_mu = [[0, A_mu], [A_mu^dag, 0]], A = -i sigma_1, -i sigma_2, -i sigma_3, 1
 __device__ __forceinline__ void gamma_mul(int mu, const cx<float>* v, cx<float>* g) {
@@ -137,8 +146,8 @@ __global__ void __launch_bounds__(256) pt_layer_kernel(NetLayerArgs a) {
     for (int ci = 0; ci < a.Cin; ++ci) {
       cx<float> v[12], xu[12], xl[12];
       ld_spinor<P32>(a.xin[p], fin, ci, s, i, v);
-      ld_spinor<P32>(a.xin[p], fin, ci, s_up, i, xu);
-      ld_spinor<P32>(a.xin[p], fin, ci, s_lo, i, xl);
+      ld_half32(a.xin[p], fin, ci, s_up, i, 0, xu);
+      ld_half32(a.xin[p], fin, ci, s_lo, i, 1, xl);
 #pragma unroll
       for (int cc = 0; cc < CB; ++cc) {
         const cx<float> w0 = W(0, cc, ci), w1 = W(1, cc, ci), w18 = W(18, cc, ci), w19 = W(19, cc, ci);
@@ -253,8 +262,8 @@ __global__ void __launch_bounds__(256) pt_wgrad_kernel(NetGradArgs a) {
 #pragma unroll
         for (int q = 6; q < 12; ++q) va[q] = {0.f, 0.f};
       } else {
-        ld_spinor<P32>(a.x[p], fx, ci, s == 0 ? a.Ls - 1 : s - 1, i, va);
-        ld_spinor<P32>(a.x[p], fx, ci, s == a.Ls - 1 ? 0 : s + 1, i, vb);
+        ld_half32(a.x[p], fx, ci, s == 0 ? a.Ls - 1 : s - 1, i, 0, va);
+        ld_half32(a.x[p], fx, ci, s == a.Ls - 1 ? 0 : s + 1, i, 1, vb);
 #pragma unroll
         for (int q = 0; q < 6; ++q) vb[q] = {0.f, 0.f};
 #pragma unroll
@@ -487,12 +496,98 @@ __global__ void __launch_bounds__(256) cdot_kernel(int n, const double2* a, cons
   }
 }
 
-__global__ void partial_sum2_kernel(const double* partial, int nblk, double* out) {
-  if (threadIdx.x < 2) {
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += partial[b * 2 + threadIdx.x];
-    out[threadIdx.x] = s;
+// sum of nblk (re, im) partials in a fixed order: 128 strided sums per
+// component, then a tree (256 threads)
+__device__ __forceinline__ void sum_pairs_256(const double* partial, int nblk, double* red) {
+  const int c = threadIdx.x & 1;
+  double s = 0.0;
+  for (int b = threadIdx.x >> 1; b < nblk; b += 128) s += partial[b * 2 + c];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w >= 2; w >>= 1) {  // w even: t and t + w hold the same component
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
   }
+}
+
+__global__ void __launch_bounds__(256) partial_sum2_kernel(const double* partial, int nblk, double* out) {
+  __shared__ double red[256];
+  sum_pairs_256(partial, nblk, red);
+  if (threadIdx.x < 2) out[threadIdx.x] = red[threadIdx.x];
+}
+
+// <q_j, z> partial sums for j < nq, as [nq][nblk][2]
+__global__ void __launch_bounds__(256) cdot_multi_kernel(int n, int nq, FgPtrs q, const double2* z, double* partial) {
+  double re[FG_CHUNK], im[FG_CHUNK];
+#pragma unroll
+  for (int j = 0; j < FG_CHUNK; ++j) re[j] = im[j] = 0.0;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const double2 y = z[k];
+#pragma unroll
+    for (int j = 0; j < FG_CHUNK; ++j) {
+      if (j >= nq) break;
+      const double2 x = ((const double2*)q.v[j])[k];  // conj(x) y
+      re[j] += x.x * y.x + x.y * y.y;
+      im[j] += x.x * y.y - x.y * y.x;
+    }
+  }
+  __shared__ double red[4][2 * FG_CHUNK];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < FG_CHUNK; ++j) {
+    if (j >= nq) break;
+    double a = re[j], b = im[j];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      a += __shfl_xor(a, off, 64);
+      b += __shfl_xor(b, off, 64);
+    }
+    if (lane == 0) {
+      red[wv][2 * j] = a;
+      red[wv][2 * j + 1] = b;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < 2 * nq) {
+    double tsum = 0.0;
+    for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) tsum += red[w][threadIdx.x];
+    partial[((size_t)(threadIdx.x >> 1) * gridDim.x + blockIdx.x) * 2 + (threadIdx.x & 1)] = tsum;
+  }
+}
+
+// work-group j: beta_j = -<q_j, z> / ww_j; bad = 1 if ww_j is not a positive
+// finite number or beta_j is not finite
+__global__ void __launch_bounds__(256) fgcg_coef_kernel(const double* partial, int nblk, FgPtrs q, double* beta,
+                                                        int* bad) {
+  const int j = blockIdx.x;
+  __shared__ double red[256];
+  sum_pairs_256(partial + (size_t)j * nblk * 2, nblk, red);
+  if (threadIdx.x != 0) return;
+  const double d = *q.ww[j];
+  const double re = -red[0] / d, im = -red[1] / d;
+  if (!(d > 0.0) || !isfinite(d) || !isfinite(re) || !isfinite(im)) {
+    *bad = 1;
+    beta[2 * j] = beta[2 * j + 1] = 0.0;
+    return;
+  }
+  beta[2 * j] = re;
+  beta[2 * j + 1] = im;
+}
+
+// p += sum_j beta_j p_j, j in order
+__global__ void __launch_bounds__(256) caxpy_multi_kernel(int n, int nq, FgPtrs pp, const double* beta, double2* p) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double2 acc = p[k];
+#pragma unroll
+  for (int j = 0; j < FG_CHUNK; ++j) {
+    if (j >= nq) break;
+    const double br = beta[2 * j], bi = beta[2 * j + 1];
+    const double2 a = ((const double2*)pp.v[j])[k];
+    acc.x += br * a.x - bi * a.y;
+    acc.y += br * a.y + bi * a.x;
+  }
+  p[k] = acc;
 }
 
 // y = y + alpha x  (alpha complex)
@@ -658,7 +753,18 @@ void launch_net_to_bf16(int n, const float* w, unsigned short* wb, hipStream_t s
 void launch_cdot(int n, const void* a, const void* b, double* partial, double* out, hipStream_t st) {
   const int nblk = 512;
   hipLaunchKernelGGL(cdot_kernel, dim3(nblk), dim3(256), 0, st, n, (const double2*)a, (const double2*)b, partial);
-  hipLaunchKernelGGL(partial_sum2_kernel, dim3(1), dim3(64), 0, st, partial, nblk, out);
+  hipLaunchKernelGGL(partial_sum2_kernel, dim3(1), dim3(256), 0, st, partial, nblk, out);
+}
+
+void launch_fgcg_orth_coefs(int n, int nq, const FgPtrs& q, const void* z, double* partial, double* beta, int* bad,
+                            hipStream_t st) {
+  const int nblk = 512;
+  hipLaunchKernelGGL(cdot_multi_kernel, dim3(nblk), dim3(256), 0, st, n, nq, q, (const double2*)z, partial);
+  hipLaunchKernelGGL(fgcg_coef_kernel, dim3(nq), dim3(256), 0, st, partial, nblk, q, beta, bad);
+}
+
+void launch_caxpy_multi(int n, int nq, const FgPtrs& pp, const double* beta, void* p, hipStream_t st) {
+  hipLaunchKernelGGL(caxpy_multi_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, nq, pp, beta, (double2*)p);
 }
 
 void launch_caxpy(int n, double ar, double ai, const void* x, void* y, hipStream_t st) {

@@ -47,6 +47,18 @@ void launch_cxpby(int n, const void* z, double br, double bi, void* p, hipStream
 void launch_sub_from(size_t n, const float* xs, float* e, hipStream_t st);
 void launch_fgcg_ratio(const double* num, const double* den, double sign, double* out, int* bad, hipStream_t st);
 void launch_cxpby_dev(int n, const void* z, const double* beta, void* p, hipStream_t st);
+// flexible CG window: up to FG_CHUNK previous directions per pass
+constexpr int FG_CHUNK = 8;
+struct FgPtrs {
+  const void* v[FG_CHUNK];     // packed FP64 odd half-fields (q_j or p_j)
+  const double* ww[FG_CHUNK];  // <p_j, A p_j> on the device (coefficients only)
+};
+// beta_j = -<q_j, z>/ww_j for j < nq into beta[2 nq] (partial: 2 * 512 * nq
+// doubles of scratch); bad = 1 on a non-positive or non-finite ww_j or beta_j
+void launch_fgcg_orth_coefs(int n, int nq, const FgPtrs& q, const void* z, double* partial, double* beta, int* bad,
+                            hipStream_t st);
+// p += sum_j beta_j p_j
+void launch_caxpy_multi(int n, int nq, const FgPtrs& pp, const double* beta, void* p, hipStream_t st);
 void launch_caxpy_dev(int n, const double* alpha, const void* x, void* y, hipStream_t st);
 // returns the number of blocks; partial holds [2][nblk] (|r|^2 then |s|^2)
 int launch_fgcg_update(int n, const double* alpha, void* x, void* r, void* s, const void* p, const void* q,

@@ -10,7 +10,9 @@
 * the batched solution update (a ring of R = 4, 8 or 16 search directions,
   x updated every R/2 iterations) equals the per-iteration update: the CG
   iterates are the same, x sums the same increments in another grouping
-  (1e-13 FP64; FP32 solution storage below FP64: 1e-6).
+  (1e-13 FP64; FP32 solution storage below FP64: 1e-6);
+* a right-hand side that breaks down stops alone: the others in its
+  work-groups are unaffected (1e-13).
 """
 import numpy as np
 import pytest
@@ -118,3 +120,26 @@ def test_twelve_rhs_converged_ls12(prec):
         res = np.sqrt(norm2(H_system(act, U, s, got[r]) - phis[r]) / norm2(phis[r]))
         assert res <= 1.05e-10, (r, res)
     ctx.close()
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_one_rhs_breaking_down_leaves_the_others_exact(setup, graph):
+    """A right-hand side whose FP32 inner residual overflows (source entries
+    scaled by 1e60: finite in FP64, infinite once converted to FP32) stops on
+    its own halt flag inside work-groups it shares with two healthy ones
+    (rhs_block = 3). The healthy ones take the same iterations and reach the
+    same solutions as a batch without it, and solve their systems."""
+    act, U, phis, ctx = setup
+    systems = [SYS[0], SYS[1], SYS[2]]
+    bad = phis[:3].copy()
+    bad[1] = bad[1] * 1e60
+    kw = dict(tol=1e-10, inner_prec=eofa.FP32, waves=2, use_graph=graph, max_outer=6)
+    rc, st, got = solve(ctx, systems, bad, rhs_block=3, **kw)
+    assert rc != eofa.EOFA_OK and st[1]["converged"] == 0
+    rc2, st2, ref = solve(ctx, [SYS[0], SYS[2]], phis[[0, 2]], rhs_block=2, **kw)
+    assert rc2 == eofa.EOFA_OK
+    for k, r in ((0, 0), (2, 1)):
+        assert st[k]["converged"] == 1 and st[k]["iters"] == st2[r]["iters"]
+        assert rel2(got[k], ref[r]) < 1e-13
+        res = np.sqrt(norm2(H_system(act, U, systems[k], got[k]) - phis[k]) / norm2(phis[k]))
+        assert res <= 1.05e-10
