@@ -182,20 +182,43 @@ __device__ __forceinline__ void ld_spinor_nt(const void* base, const FD& f, int 
   }
 }
 
+// the raw FP16S words and the site scale of a streamed spinor
+__device__ __forceinline__ void ld_raw16_nt(const void* base, const FD& f, int r, int s, int i, float& sc,
+                                            unsigned* w) {
+  const size_t e0 = qidx16(f, r, 0, s, i), qs = qstride(f);
+  sc = __builtin_nontemporal_load(scale_ptr(base, f) + sidx(f, r, s, i));
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const u4v_t q = __builtin_nontemporal_load((const u4v_t*)base + e0 + j * qs);
+    w[4 * j] = q.x;
+    w[4 * j + 1] = q.y;
+    w[4 * j + 2] = q.z;
+    w[4 * j + 3] = q.w;
+  }
+}
+
 // FP16S site-spinor: the 12 components as half2 words in units of the
 // largest |component|, which is kept as the site's FP32 scale
+// Returns the site's |v|^2 as m^2 sum (v/m)^2: the sum over the scaled
+// components (each at most 1 + 2^-23) in FP32, the product with m^2 in FP64,
+// so no FP32 value overflows (a caller that does not use it pays nothing).
 template <bool NT, class R>
-__device__ __forceinline__ void st_spinor16(void* base, const FD& f, int r, int s, int i, const cx<R>* v) {
+__device__ __forceinline__ double st_spinor16(void* base, const FD& f, int r, int s, int i, const cx<R>* v) {
   float m = 0.f;
 #pragma unroll
   for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf((float)v[c].r), fabsf((float)v[c].i)));
-  const float inv = m > 0.f ? 1.0f / m : 0.f;
+  // hardware reciprocal (1 ulp): the scaled components stay within 1 + 2^-23
+  // of the unit, far inside the FP16 range
+  const float inv = m > 0.f ? __builtin_amdgcn_rcpf(m) : 0.f;
   unsigned w[12];
+  float ns = 0.f;
 #pragma unroll
   for (int c = 0; c < 12; ++c) {
+    const float xr = (float)v[c].r * inv, xi = (float)v[c].i * inv;
+    ns = fma(xi, xi, fma(xr, xr, ns));
     h2_t h;
-    h.x = (_Float16)((float)v[c].r * inv);
-    h.y = (_Float16)((float)v[c].i * inv);
+    h.x = (_Float16)xr;
+    h.y = (_Float16)xi;
     w[c] = __builtin_bit_cast(unsigned int, h);
   }
   const size_t e0 = qidx16(f, r, 0, s, i), qs = qstride(f);
@@ -213,6 +236,7 @@ __device__ __forceinline__ void st_spinor16(void* base, const FD& f, int r, int 
       ((uint4*)base)[e0 + j * qs] = make_uint4(w[4 * j], w[4 * j + 1], w[4 * j + 2], w[4 * j + 3]);
     *sp = m;
   }
+  return (double)m * (double)m * (double)ns;
 }
 
 template <int P, class R>

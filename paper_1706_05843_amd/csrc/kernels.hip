@@ -181,7 +181,7 @@ constexpr int kOcc16 = 5;
 template <bool DAG, bool PRE, int RL, bool YPRE>
 __device__ __forceinline__ void hop_site_h(const HopArgs& a, const FD& fin, int r, int s, int g, int ls,
                                            const cx<float>* s_link, const int* s_nbr, cx<float>* acc,
-                                           DirIn<P16>& yout) {
+                                           DirIn<P16>& yout, float fold) {
   const int Ls = a.Ls;
   float aup = 0.f, alo = 0.f, post = -0.5f;
   int src_up = 0, src_lo = 0;
@@ -194,6 +194,7 @@ __device__ __forceinline__ void hop_site_h(const HopArgs& a, const FD& fin, int 
     src_up = g * Ls + (s > 0 ? s - 1 : Ls - 1);
     src_lo = g * Ls + (s < Ls - 1 ? s + 1 : 0);
   }
+  post *= fold;
 #pragma unroll
   for (int c = 0; c < 12; ++c) acc[c] = {0.f, 0.f};
   // the neighbour spinors of the next kPfd16 directions are in flight while
@@ -282,8 +283,9 @@ __device__ __forceinline__ void hop_site_h(const HopArgs& a, const FD& fin, int 
       }
 #pragma unroll
     for (int c = 0; c < 6; ++c) asm volatile("" : "+v"(gv[c].r), "+v"(gv[c].i));
-    // acc += unit * [g ; sg A^dag g]
-    const float ps = unit, ms = neg ? -unit : unit;
+    // acc += post unit [g ; sg A^dag g] (the overall -1/2, or -(c+d)/2, and
+    // the epilogue's leading factor folded into each direction's unit)
+    const float ps = unit * post, ms = neg ? -ps : ps;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const cx<float> g0 = gv[c], g1 = gv[3 + c];
@@ -304,8 +306,6 @@ __device__ __forceinline__ void hop_site_h(const HopArgs& a, const FD& fin, int 
       }
     }
   }
-#pragma unroll
-  for (int c = 0; c < 12; ++c) acc[c] = post * acc[c];
 }
 
 // Dhop (or g5 Dhop g5 when DAG) applied to D~ in (PRE) at the 5D site (s, i)
@@ -316,9 +316,10 @@ __device__ __forceinline__ void hop_site_h(const HopArgs& a, const FD& fin, int 
 template <int P, bool DAG, bool PRE, int RL, bool YPRE>
 __device__ __forceinline__ void hop_site(const HopArgs& a, const FD& fin, int r, int s, int g, int ls,
                                          const cx<typename ST<P>::R>* s_link, const int* s_nbr,
-                                         cx<typename ST<P>::R>* acc, DirIn<P16>& yout) {
+                                         cx<typename ST<P>::R>* acc, DirIn<P16>& yout,
+                                         typename ST<P>::R fold) {
   if constexpr (P == P16) {
-    hop_site_h<DAG, PRE, RL, YPRE>(a, fin, r, s, g, ls, s_link, s_nbr, acc, yout);
+    hop_site_h<DAG, PRE, RL, YPRE>(a, fin, r, s, g, ls, s_link, s_nbr, acc, yout, fold);
     return;
   } else {
   using R = typename ST<P>::R;
@@ -426,6 +427,7 @@ __device__ __forceinline__ void hop_site(const HopArgs& a, const FD& fin, int r,
       }
     }
   }
+  post *= fold;
 #pragma unroll
   for (int c = 0; c < 12; ++c) acc[c] = post * acc[c];
   }
@@ -612,11 +614,20 @@ __device__ __forceinline__ void series_rows(cx<R>* z, int s, R x1, R x2, R x4, R
 // with a_s from the host. A^-T uses L^T, which for L_+ is L_- in structure
 // and vice versa. TRANS selects M_ee^-T. About 250 VALU operations per lane
 // instead of the 768 of the dense Ls x Ls product.
-template <class R, bool TRANS>
+// 1/x: the hardware reciprocal (1 ulp) in FP32, a division in FP64
+template <class R>
+__device__ __forceinline__ R recip(R x) {
+  if constexpr (sizeof(R) == 4)
+    return __builtin_amdgcn_rcpf(x);
+  else
+    return R(1) / x;
+}
+
+template <class R, bool TRANS, bool NORM = true>
 __device__ __forceinline__ void minv_rows(cx<R>* v, int s, int g, R bee, R cee, R m, R sk, int chi, R a_s) {
-  const R rho = cee / bee;
+  const R rho = cee * recip(bee);
   const R rho2 = rho * rho, rho4 = rho2 * rho2, rho8 = rho4 * rho4, rho16 = rho8 * rho8;
-  const R scale = R(1) / (bee * (R(1) + m * rho16));
+  const R scale = NORM ? recip(bee * (R(1) + m * rho16)) : R(1);
 #pragma unroll
   for (int half = 0; half < 2; ++half) {
     cx<R>* z = v + half * 6;
@@ -637,8 +648,10 @@ __device__ __forceinline__ void minv_rows(cx<R>* v, int s, int g, R bee, R cee, 
       series_rows<R, true>(z, s, rho, rho2, rho4, rho8, m);
     else
       series_rows<R, false>(z, s, rho, rho2, rho4, rho8, m);
+    if constexpr (NORM) {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) z[c] = scale * z[c];
+      for (int c = 0; c < 6; ++c) z[c] = scale * z[c];
+    }
     if constexpr (!TRANS) {
       if (shifted) {  // z += a z_{s*}
 #pragma unroll
@@ -692,12 +705,12 @@ __device__ __forceinline__ void series_cols(cx<R>* z, int s, int g, int Ls, R x,
 // v <- D~^-1 v (App. A): per chirality D~ = (c+d)(1 + q L) with q = (c-d)/(c+d)
 // (L_+ on P_+ psi, L_- on P_- psi) and L^Ls = -m, so for even Ls
 //   D~^-1 = sum_{k<Ls} (-q L)^k / ((c+d)(1 + m q^Ls)).
-template <class R, int RL>
+template <class R, int RL, bool NORM = true>
 __device__ __forceinline__ void dtinv(cx<R>* v, int s, int g, int Ls, R cpd, R cmd, R m) {
-  const R q = cmd / cpd, x1 = -q;
+  const R q = cmd * recip(cpd), x1 = -q;
   R qLs = R(1);
   for (int k = 0; k < Ls; ++k) qLs *= q;
-  const R scale = R(1) / (cpd * (R(1) + m * qLs));
+  const R scale = NORM ? recip(cpd * (R(1) + m * qLs)) : R(1);
 #pragma unroll
   for (int half = 0; half < 2; ++half) {
     cx<R>* z = v + half * 6;
@@ -710,9 +723,32 @@ __device__ __forceinline__ void dtinv(cx<R>* v, int s, int g, int Ls, R cpd, R c
     } else {
       series_cols<R>(z, s, g, Ls, x1, m, half == 0);
     }
+    if constexpr (NORM) {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) z[c] = scale * z[c];
+      for (int c = 0; c < 6; ++c) z[c] = scale * z[c];
+    }
   }
+}
+
+// the normalisations the structured inverses leave to their callers:
+// 1/(bee (1 + m rho^Ls)), rho = cee/bee, of M_ee^-1 (unshifted part), and
+// 1/((c+d)(1 + m q^Ls)), q = (c-d)/(c+d), of D~^-1
+template <class R>
+__device__ __forceinline__ R power_ls(R x, int Ls) {  // x^Ls by squaring
+  R p = R(1), b = x;
+  for (int e = Ls; e > 0; e >>= 1) {
+    if (e & 1) p *= b;
+    b *= b;
+  }
+  return p;
+}
+template <class R>
+__device__ __forceinline__ R minv_norm(R bee, R cee, R m, int Ls) {
+  return recip(bee * (R(1) + m * power_ls(cee * recip(bee), Ls)));
+}
+template <class R>
+__device__ __forceinline__ R dtinv_norm(R cpd, R cmd, R m, int Ls) {
+  return recip(cpd * (R(1) + m * power_ls(cmd * recip(cpd), Ls)));
 }
 
 // The same structured inverse for any Ls, by lane permutes within the
@@ -725,13 +761,13 @@ __device__ __forceinline__ void dtinv(cx<R>* v, int s, int g, int Ls, R cpd, R c
 // wrap). Ls = 12 = 2 2 3 takes 4 shifted copies per component instead of
 // the 12-term dense product. The rank-one term as in minv_rows; the
 // transposed form's sum over s' goes through the column's LDS slot.
-template <class R, bool TRANS>
+template <class R, bool TRANS, bool NORM = true>
 __device__ __forceinline__ void minv_cols(cx<R>* v, int s, int g, int Ls, R bee, R cee, R m, R sk, int chi, R a_s,
                                           cx<R>* mycol, bool in_col) {
-  const R rho = cee / bee;
+  const R rho = cee * recip(bee);
   R rhoLs = R(1);
   for (int k = 0; k < Ls; ++k) rhoLs *= rho;
-  const R scale = R(1) / (bee * (R(1) + m * rhoLs));
+  const R scale = NORM ? recip(bee * (R(1) + m * rhoLs)) : R(1);
 #pragma unroll
   for (int half = 0; half < 2; ++half) {
     cx<R>* z = v + half * 6;
@@ -757,8 +793,10 @@ __device__ __forceinline__ void minv_cols(cx<R>* v, int s, int g, int Ls, R bee,
     }
     // A^-1 uses L_chi (lane s takes s - j for L_+, s + j for L_-); A^-T the other
     series_cols<R>(z, s, g, Ls, rho, m, (chir > 0) != TRANS);
+    if constexpr (NORM) {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) z[c] = scale * z[c];
+      for (int c = 0; c < 6; ++c) z[c] = scale * z[c];
+    }
     if constexpr (!TRANS) {
       if (shifted) {  // z += a z_{s*}
         const int star = g * Ls + star_s;
@@ -937,7 +975,17 @@ hop_kernel(HopArgs a) {
     // FP16S: the same-site y of the B term arrives with the last direction
     constexpr bool YPRE = P == P16 && RT::BM != B_NONE;
     DirIn<P16> ypre;
-    hop_site<P, RT::DAG, RT::PRE, RL, YPRE>(a, fd, r, s, g, ls, s_link, s_nbr, acc, ypre);
+    const R cpd = (R)a.cpd, cmd = (R)a.cmd;
+    // the epilogue's leading factor, applied by the hop once per direction
+    // instead of once per component: the sign of A_NEG / A_NDTT, the (c+d)
+    // of D~ and D~^T (which then act as 1 + q L, q = (c-d)/(c+d)) and the
+    // normalisation of the structured M_ee^-1
+    R fold = R(1);
+    if constexpr (RT::AM == A_NEG) fold = R(-1);
+    if constexpr (RT::AM == A_DTT || RT::AM == A_MATDT || RT::AM == A_DMINV || RT::AM == A_MINVDT) fold = cpd;
+    if constexpr (RT::AM == A_NDTT) fold = -cpd;
+    if constexpr (SINV) fold *= minv_norm<R>((R)a.bee, (R)a.cee, (R)a.mop[r], Ls);
+    hop_site<P, RT::DAG, RT::PRE, RL, YPRE>(a, fd, r, s, g, ls, s_link, s_nbr, acc, ypre, fold);
     (void)ypre;
     // an unconditional use: stops the hop arithmetic from being sunk into the
     // (live-only) store block, away from the per-direction loads and shuffles
@@ -953,33 +1001,27 @@ hop_kernel(HopArgs a) {
       nb.fp = s > 0 ? R(1) : -m;
       nb.fn = s < Ls - 1 ? R(1) : -m;
     }
-    const R cpd = (R)a.cpd, cmd = (R)a.cmd;
+    const R qd = cmd * recip(cpd);  // D~ = (c+d)(1 + qd L), the (c+d) in the fold
 
     cx<R> v[12];
-    if constexpr (RT::AM == A_ID || RT::AM == A_MAT || RT::AM == A_DMINV) {
+    if constexpr (RT::AM == A_ID || RT::AM == A_MAT || RT::AM == A_DMINV || RT::AM == A_NEG) {
 #pragma unroll
       for (int c = 0; c < 12; ++c) v[c] = acc[c];
-    } else if constexpr (RT::AM == A_NEG) {
-#pragma unroll
-      for (int c = 0; c < 12; ++c) v[c] = R(-1) * acc[c];
-    } else {  // D~^T h = (c+d) h + (c-d) L^T h
+    } else {  // D~^T h = (c+d)(h + qd L^T h), the (c+d) and the sign in the fold
       cx<R> t[12];
       lmul<R, true, RL>(acc, t, nb);
-      const R sgn = RT::AM == A_NDTT ? R(-1) : R(1);
 #pragma unroll
-      for (int c = 0; c < 12; ++c) {
-        const cx<R> d = {fma(cmd, t[c].r, cpd * acc[c].r), fma(cmd, t[c].i, cpd * acc[c].i)};
-        v[c] = sgn * d;
-      }
+      for (int c = 0; c < 12; ++c) v[c] = {fma(qd, t[c].r, acc[c].r), fma(qd, t[c].i, acc[c].i)};
     }
     if constexpr (SINV) {  // v <- M_ee^-1 v or M_ee^-T v, structured along the column
       const double* scs = a.scoef + (size_t)r * (SCOEF_HEAD + 2 * Ls);
       const R a_s = (R)scs[SCOEF_HEAD + Ls + s];
       if constexpr (RL == 16)
-        minv_rows<R, RT::AM == A_MINVDT>(v, s, g, (R)a.bee, (R)a.cee, (R)a.mop[r], (R)scs[1], (int)scs[2], a_s);
+        minv_rows<R, RT::AM == A_MINVDT, false>(v, s, g, (R)a.bee, (R)a.cee, (R)a.mop[r], (R)scs[1], (int)scs[2],
+                                                a_s);
       else
-        minv_cols<R, RT::AM == A_MINVDT>(v, s, g, Ls, (R)a.bee, (R)a.cee, (R)a.mop[r], (R)scs[1], (int)scs[2],
-                                          a_s, s_col + ls * cstr, in_col);
+        minv_cols<R, RT::AM == A_MINVDT, false>(v, s, g, Ls, (R)a.bee, (R)a.cee, (R)a.mop[r], (R)scs[1],
+                                                 (int)scs[2], a_s, s_col + ls * cstr, in_col);
 #pragma unroll
       for (int c = 0; c < 12; ++c) asm volatile("" : "+v"(v[c].r), "+v"(v[c].i));
     } else if constexpr (DENSE && RL == 16) {  // v <- M v along the row's diagonals
@@ -1001,11 +1043,11 @@ hop_kernel(HopArgs a) {
         col_matvec<R>(s_mA, mycol, Ls, s, half, v, false);
       }
     }
-    if constexpr (RT::AM == A_DMINV) {  // v <- D~ v = (c+d) v + (c-d) L v
+    if constexpr (RT::AM == A_DMINV) {  // v <- D~ v = (c+d)(v + qd L v), the (c+d) in the fold
       cx<R> t[12];
       lmul<R, false, RL>(v, t, nb);
 #pragma unroll
-      for (int c = 0; c < 12; ++c) v[c] = {fma(cmd, t[c].r, cpd * v[c].r), fma(cmd, t[c].i, cpd * v[c].i)};
+      for (int c = 0; c < 12; ++c) v[c] = {fma(qd, t[c].r, v[c].r), fma(qd, t[c].i, v[c].i)};
     }
     if constexpr (BDENSE && RL == 16) {  // v += M y along the row's diagonals
       cx<R> y[12];
@@ -1028,16 +1070,22 @@ hop_kernel(HopArgs a) {
       //   bee y - cee L y (L^T y) + sk u e_{s*}^T y (sk e_{s*} u^T y) on chirality chi
       cx<R> y[12], t[12];
       load_y<P, YPRE>(a.y, fd, r, s, EOFA_SITE, ypre, y);
-      if constexpr (RT::BM == B_MEE_DTI) dtinv<R, RL>(y, s, g, Ls, cpd, cmd, (R)a.mop[r]);
+      // B_MEE_DTI: M_ee D~^-1 y with the normalisation of D~^-1 moved onto
+      // the coefficients of M_ee (bee, cee and the rank-one sk)
+      R yn = R(1);
+      if constexpr (RT::BM == B_MEE_DTI) {
+        dtinv<R, RL, false>(y, s, g, Ls, cpd, cmd, (R)a.mop[r]);
+        yn = dtinv_norm<R>(cpd, cmd, (R)a.mop[r], Ls);
+      }
       lmul<R, RT::BM == B_MEET, RL>(y, t, nb);
-      const R bee = (R)a.bee, cee = (R)a.cee;
+      const R bee = (R)a.bee * yn, cee = (R)a.cee * yn;
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         v[c].r = fma(bee, y[c].r, fma(-cee, t[c].r, v[c].r));
         v[c].i = fma(bee, y[c].i, fma(-cee, t[c].i, v[c].i));
       }
       const double* sc = a.scoef + (size_t)r * (SCOEF_HEAD + 2 * Ls);
-      const R sk = (R)sc[1];
+      const R sk = (R)sc[1] * yn;
       if (sk != R(0)) {  // uniform over the block
         const int chi = (int)sc[2];
         const R us = (R)sc[SCOEF_HEAD + s];
@@ -1049,9 +1097,15 @@ hop_kernel(HopArgs a) {
       }
     }
 
+    // FP16S outputs return the site's |v|^2 from their encoding (scaled by
+    // the site maximum, so FP32 cannot overflow); the others sum it in FP64
+    constexpr bool NRM16 = RT::NRM && ((RT::OM == O_STORE && P == P16) ||
+                                       ((RT::OM == O_RUPD || RT::OM == O_STORE_R) && PR == P16));
     double nrm = 0.0;
     if (live) {
-      if constexpr (RT::OM == O_STORE) {
+      if constexpr (RT::OM == O_STORE && NRM16) {
+        nrm = st_spinor16<false>(a.out, fd, r, s, EOFA_SITE, v);
+      } else if constexpr (RT::OM == O_STORE) {
         st_spinor<P>(a.out, fd, r, s, EOFA_SITE, v);
       } else if constexpr (RT::OM == O_ADDZ) {
         cx<R> z[12];
@@ -1062,7 +1116,20 @@ hop_kernel(HopArgs a) {
       } else {
         using RR = typename ST<PR>::R;
         cx<RR> w[12];
-        if constexpr (RT::OM == O_RUPD) {
+        if constexpr (RT::OM == O_RUPD && PR == P16) {
+          // r - alpha v from the raw half words: one mixed-precision FMA per
+          // component (scale x half + (-alpha v)) instead of decode, scale, FMA
+          float sc;
+          unsigned hw[12];
+          ld_raw16_nt(a.r, fd, r, s, EOFA_SITE, sc, hw);
+          const float al = (float)a.alpha[r];
+#pragma unroll
+          for (int c = 0; c < 12; ++c) {
+            const h2_t h = __builtin_bit_cast(h2_t, hw[c]);
+            w[c].r = fma((float)h.x, sc, -al * (float)v[c].r);
+            w[c].i = fma((float)h.y, sc, -al * (float)v[c].i);
+          }
+        } else if constexpr (RT::OM == O_RUPD) {
           ld_spinor_nt<PR>(a.r, fd, r, s, EOFA_SITE, w);
           const RR al = (RR)a.alpha[r];
 #pragma unroll
@@ -1074,11 +1141,14 @@ hop_kernel(HopArgs a) {
 #pragma unroll
           for (int c = 0; c < 12; ++c) w[c] = {(RR)v[c].r, (RR)v[c].i};
         }
-        st_spinor_nt<PR>(a.r, fd, r, s, EOFA_SITE, w);
+        if constexpr (NRM16)
+          nrm = st_spinor16<true>(a.r, fd, r, s, EOFA_SITE, w);
+        else
+          st_spinor_nt<PR>(a.r, fd, r, s, EOFA_SITE, w);
 #pragma unroll
         for (int c = 0; c < 12; ++c) v[c] = {(R)w[c].r, (R)w[c].i};
       }
-      if constexpr (RT::NRM) {
+      if constexpr (RT::NRM && !NRM16) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) nrm += (double)v[c].r * v[c].r + (double)v[c].i * v[c].i;
       }
