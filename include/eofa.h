@@ -180,7 +180,10 @@ typedef struct {
 
 /* Create a context: validates the action, packs the gauge field (device
  * pointer, canonical complex128 layout above) per parity with boundary
- * phases folded in. The gauge array is not retained.                    */
+ * phases folded in. The gauge array is not retained. EOFA_ERR_INVALID if
+ * Ls is odd or outside 2..32, b5 - c5 != 1, a parameter is not finite, the
+ * 5D sites of one parity (Vh * Ls, x-doubled under G-parity) reach 2^28
+ * (32-bit indexing and byte offsets), or the device is not a gfx950.      */
 int eofa_create(const eofa_action* act, const void* gauge, void* stream, eofa_ctx** out);
 int eofa_destroy(eofa_ctx* ctx);
 const char* eofa_last_error(void);

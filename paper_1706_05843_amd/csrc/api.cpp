@@ -281,7 +281,10 @@ int eofa_create(const eofa_action* act, const void* gauge, void* stream, eofa_ct
   if (!std::isfinite(act->M5) || !std::isfinite(act->b5) || !std::isfinite(act->c5))
     return fail(EOFA_ERR_INVALID, "non-finite action parameter");
   const double V = (double)act->dims[0] * act->dims[1] * act->dims[2] * act->dims[3] * (gparity ? 2 : 1);
-  if (V / 2 * act->Ls * 6 > 2.0e9) return fail(EOFA_ERR_INVALID, "lattice too large for 32-bit site indexing");
+  // 32-bit site indexing, and the FP16S gathers' 32-bit byte offsets within
+  // one quad plane (16 bytes per 5D site of a parity)
+  if (V / 2 * act->Ls * 6 > 2.0e9 || V / 2 * act->Ls * 16 >= 4294967296.0)
+    return fail(EOFA_ERR_INVALID, "lattice too large for 32-bit indexing (Vh * Ls must stay below 2^28)");
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   hipDeviceProp_t prop;

@@ -161,6 +161,40 @@ __device__ __forceinline__ void load_dir(const void* in, const FD& fin, int r, i
   }
 }
 
+// FP16S gathers through buffer descriptors: one per quad plane of the
+// field and right-hand side, and one for its scales, so a gathered site
+// costs one 32-bit offset per lane (shared by its three quads and, shifted,
+// its scale) instead of four 64-bit address additions. The offsets are below
+// 16 x Vh x Ls bytes, which the host keeps under 4 GiB (kMaxSites16).
+constexpr int kBufDword3 = 0x00020000;  // raw buffer, 32-bit data format
+struct Buf16 {
+  __amdgpu_buffer_rsrc_t v[3], sc;
+};
+__device__ __forceinline__ Buf16 buf16(const void* base, const FD& f, int r) {
+  const size_t qs = qstride(f);
+  Buf16 B;
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+    B.v[j] = __builtin_amdgcn_make_buffer_rsrc((char*)base + ((size_t)r * 3 + j) * qs * 16, (short)0, -1,
+                                               kBufDword3);
+  B.sc = __builtin_amdgcn_make_buffer_rsrc((char*)scale_ptr(base, f) + (size_t)r * qs * 4, (short)0, -1,
+                                           kBufDword3);
+  return B;
+}
+// the FP16S spinor of column site n, fifth-dimension index s
+__device__ __forceinline__ void load_dir16(const Buf16& B, int Ls, int s, int n, DirIn<P16>& b) {
+  const unsigned e = (unsigned)(n * Ls + s);
+  b.sc = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(B.sc, e * 4u, 0, 0));
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const u4v_t q = __builtin_amdgcn_raw_buffer_load_b128(B.v[j], e * 16u, 0, 0);
+    b.w[4 * j] = q.x;
+    b.w[4 * j + 1] = q.y;
+    b.w[4 * j + 2] = q.z;
+    b.w[4 * j + 3] = q.w;
+  }
+}
+
 // FP16S: neighbour spinors and links stay in half precision through the
 // SU(3) products. Each link element sits in LDS as the two half2 words
 // (Re u, -Im u) and (Im u, Re u), so that one complex multiply-accumulate
@@ -200,15 +234,16 @@ __device__ __forceinline__ void hop_site_h(const HopArgs& a, const FD& fin, int 
   // the neighbour spinors of the next kPfd16 directions are in flight while
   // one direction is computed (kPfd16 + 1 buffers in registers)
   DirIn<P16> buf[kPfd16 + 1];
+  const Buf16 bin = buf16(a.in, fin, r);
 #pragma unroll
-  for (int d = 0; d < kPfd16; ++d) load_dir<P16>(a.in, fin, r, s, s_nbr[ls * NSTR + d], buf[d]);
+  for (int d = 0; d < kPfd16; ++d) load_dir16(bin, Ls, s, s_nbr[ls * NSTR + d], buf[d]);
 #pragma unroll
   for (int dir = 0; dir < 8; ++dir) {
     __builtin_amdgcn_sched_barrier(0);
     if (dir + kPfd16 < 8)
-      load_dir<P16>(a.in, fin, r, s, s_nbr[ls * NSTR + dir + kPfd16], buf[(dir + kPfd16) % (kPfd16 + 1)]);
+      load_dir16(bin, Ls, s, s_nbr[ls * NSTR + dir + kPfd16], buf[(dir + kPfd16) % (kPfd16 + 1)]);
     if constexpr (YPRE) {
-      if (dir + kPfd16 == 8) load_dir<P16>(a.y, fin, r, s, s_nbr[ls * NSTR + 8], yout);
+      if (dir + kPfd16 == 8) load_dir16(buf16(a.y, fin, r), Ls, s, s_nbr[ls * NSTR + 8], yout);
     }
     // the next directions' loads leave before this direction's data is
     // touched: without this fence the scheduler hoists the lane exchanges of
@@ -236,7 +271,7 @@ __device__ __forceinline__ void hop_site_h(const HopArgs& a, const FD& fin, int 
     } else {
 #pragma unroll
       for (int c = 0; c < 12; ++c) x[c] = __builtin_bit_cast(h2_t, b.w[c]);
-      unit = sc != 0.f ? sc : 1.f;  // sc = 0: the halves are all zero
+      unit = sc;  // sc = 0: the halves are all zero, and so is the product
     }
     // (1 + sg g_mu) projection on packed halves (sg = -1 for (1 - g_mu));
     // i v = (-Im v, Re v)
@@ -578,6 +613,35 @@ __device__ __forceinline__ void fmac_ror6(cx<float>* z, float f) {
 }
 #undef EOFA_FMAC_ROR
 #undef EOFA_FMAC_ROR_1
+
+// z[c] += f * (y[c] of lane (l - K) mod 16 of the same row), y another array:
+// twelve v_fmac_f32_dpp with the rotated y as the DPP source (wait states as
+// above: y may have been written just before, z is read by DPP just after)
+#define EOFA_FMACS_1(K, n, m) "v_fmac_f32_dpp %" #n ", %" #m ", %24 row_ror:" #K " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+#define EOFA_FMACS(K)                                                                                          \
+  asm("s_nop 1\n\t" EOFA_FMACS_1(K, 0, 12) EOFA_FMACS_1(K, 1, 13) EOFA_FMACS_1(K, 2, 14) EOFA_FMACS_1(K, 3, 15) \
+      EOFA_FMACS_1(K, 4, 16) EOFA_FMACS_1(K, 5, 17) EOFA_FMACS_1(K, 6, 18) EOFA_FMACS_1(K, 7, 19)                 \
+      EOFA_FMACS_1(K, 8, 20) EOFA_FMACS_1(K, 9, 21) EOFA_FMACS_1(K, 10, 22) EOFA_FMACS_1(K, 11, 23) "s_nop 1"     \
+      : "+v"(z[0].r), "+v"(z[0].i), "+v"(z[1].r), "+v"(z[1].i), "+v"(z[2].r), "+v"(z[2].i), "+v"(z[3].r),         \
+        "+v"(z[3].i), "+v"(z[4].r), "+v"(z[4].i), "+v"(z[5].r), "+v"(z[5].i)                                      \
+      : "v"(y[0].r), "v"(y[0].i), "v"(y[1].r), "v"(y[1].i), "v"(y[2].r), "v"(y[2].i), "v"(y[3].r), "v"(y[3].i),    \
+        "v"(y[4].r), "v"(y[4].i), "v"(y[5].r), "v"(y[5].i), "v"(f))
+template <int K>
+__device__ __forceinline__ void fmac_ror6_from(cx<float>* z, const cx<float>* y, float f) {
+  static_assert(K == 1 || K == 15, "rotation");
+  if constexpr (K == 1) EOFA_FMACS(1);
+  else EOFA_FMACS(15);
+}
+#undef EOFA_FMACS
+#undef EOFA_FMACS_1
+
+// z += k (L y) on one chirality half, Ls = 16 rows: UP L = L_+ ((L y)_s =
+// y_{s-1}, -m y_15 at s = 0), else L = L_- (y_{s+1}, -m y_0 at s = 15)
+template <bool UP>
+__device__ __forceinline__ void lacc_rows(cx<float>* z, const cx<float>* y, int s, float k, float m) {
+  const bool wrap = UP ? s == 0 : s == 15;
+  fmac_ror6_from<UP ? 1 : 15>(z, y, wrap ? -m * k : k);
+}
 
 template <class R, int N, bool UP>
 __device__ __forceinline__ void scan_step(cx<R>* z, int s, R rhoN, R m) {
@@ -985,6 +1049,11 @@ hop_kernel(HopArgs a) {
     if constexpr (RT::AM == A_DTT || RT::AM == A_MATDT || RT::AM == A_DMINV || RT::AM == A_MINVDT) fold = cpd;
     if constexpr (RT::AM == A_NDTT) fold = -cpd;
     if constexpr (SINV) fold *= minv_norm<R>((R)a.bee, (R)a.cee, (R)a.mop[r], Ls);
+    // the residual update r -= alpha v takes -alpha into v itself: the hop
+    // through the fold, the same-site term through its coefficients
+    R vscale = R(1);
+    if constexpr (RT::OM == O_RUPD) vscale = -(R)a.alpha[r];
+    fold *= vscale;
     hop_site<P, RT::DAG, RT::PRE, RL, YPRE>(a, fd, r, s, g, ls, s_link, s_nbr, acc, ypre, fold);
     (void)ypre;
     // an unconditional use: stops the hop arithmetic from being sunk into the
@@ -1007,6 +1076,11 @@ hop_kernel(HopArgs a) {
     if constexpr (RT::AM == A_ID || RT::AM == A_MAT || RT::AM == A_DMINV || RT::AM == A_NEG) {
 #pragma unroll
       for (int c = 0; c < 12; ++c) v[c] = acc[c];
+    } else if constexpr (RL == 16 && sizeof(R) == 4) {  // D~^T h in place: L_+^T = L_- and back
+#pragma unroll
+      for (int c = 0; c < 12; ++c) v[c] = acc[c];
+      scan_step<R, 1, false>(v, s, qd, (R)a.mop[r]);
+      scan_step<R, 1, true>(v + 6, s, qd, (R)a.mop[r]);
     } else {  // D~^T h = (c+d)(h + qd L^T h), the (c+d) and the sign in the fold
       cx<R> t[12];
       lmul<R, true, RL>(acc, t, nb);
@@ -1043,7 +1117,10 @@ hop_kernel(HopArgs a) {
         col_matvec<R>(s_mA, mycol, Ls, s, half, v, false);
       }
     }
-    if constexpr (RT::AM == A_DMINV) {  // v <- D~ v = (c+d)(v + qd L v), the (c+d) in the fold
+    if constexpr (RT::AM == A_DMINV && RL == 16 && sizeof(R) == 4) {  // D~ in place along the row
+      scan_step<R, 1, true>(v, s, qd, (R)a.mop[r]);
+      scan_step<R, 1, false>(v + 6, s, qd, (R)a.mop[r]);
+    } else if constexpr (RT::AM == A_DMINV) {  // v <- D~ v = (c+d)(v + qd L v), the (c+d) in the fold
       cx<R> t[12];
       lmul<R, false, RL>(v, t, nb);
 #pragma unroll
@@ -1052,10 +1129,14 @@ hop_kernel(HopArgs a) {
     if constexpr (BDENSE && RL == 16) {  // v += M y along the row's diagonals
       cx<R> y[12];
       load_y<P, YPRE>(a.y, fd, r, s, EOFA_SITE, ypre, y);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) y[c] = vscale * y[c];
       row_matvec<R>(s_mA, y, s, v, true);
     } else if constexpr (BDENSE) {  // v += M y, M dense per chirality, through the column in LDS
       cx<R> y[12];
       load_y<P, YPRE>(a.y, fd, r, s, EOFA_SITE, ypre, y);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) y[c] = vscale * y[c];
       cx<R>* mycol = s_col + ls * cstr;
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
@@ -1077,15 +1158,23 @@ hop_kernel(HopArgs a) {
         dtinv<R, RL, false>(y, s, g, Ls, cpd, cmd, (R)a.mop[r]);
         yn = dtinv_norm<R>(cpd, cmd, (R)a.mop[r], Ls);
       }
-      lmul<R, RT::BM == B_MEET, RL>(y, t, nb);
-      const R bee = (R)a.bee * yn, cee = (R)a.cee * yn;
+      const R bee = (R)a.bee * yn * vscale, cee = (R)a.cee * yn * vscale;
+      if constexpr (RL == 16 && sizeof(R) == 4) {  // the L term rides on the rotation
 #pragma unroll
-      for (int c = 0; c < 12; ++c) {
-        v[c].r = fma(bee, y[c].r, fma(-cee, t[c].r, v[c].r));
-        v[c].i = fma(bee, y[c].i, fma(-cee, t[c].i, v[c].i));
+        for (int c = 0; c < 12; ++c) v[c] = {fma(bee, y[c].r, v[c].r), fma(bee, y[c].i, v[c].i)};
+        constexpr bool TR = RT::BM == B_MEET;  // L^T: L_+^T = L_- and back
+        lacc_rows<!TR>(v, y, s, -cee, (R)a.mop[r]);
+        lacc_rows<TR>(v + 6, y + 6, s, -cee, (R)a.mop[r]);
+      } else {
+        lmul<R, RT::BM == B_MEET, RL>(y, t, nb);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          v[c].r = fma(bee, y[c].r, fma(-cee, t[c].r, v[c].r));
+          v[c].i = fma(bee, y[c].i, fma(-cee, t[c].i, v[c].i));
+        }
       }
       const double* sc = a.scoef + (size_t)r * (SCOEF_HEAD + 2 * Ls);
-      const R sk = (R)sc[1] * yn;
+      const R sk = (R)sc[1] * yn * vscale;
       if (sk != R(0)) {  // uniform over the block
         const int chi = (int)sc[2];
         const R us = (R)sc[SCOEF_HEAD + s];
@@ -1117,25 +1206,23 @@ hop_kernel(HopArgs a) {
         using RR = typename ST<PR>::R;
         cx<RR> w[12];
         if constexpr (RT::OM == O_RUPD && PR == P16) {
-          // r - alpha v from the raw half words: one mixed-precision FMA per
-          // component (scale x half + (-alpha v)) instead of decode, scale, FMA
+          // r + (-alpha v) from the raw half words (v carries -alpha): one
+          // mixed-precision FMA per component instead of decode, scale, FMA
           float sc;
           unsigned hw[12];
           ld_raw16_nt(a.r, fd, r, s, EOFA_SITE, sc, hw);
-          const float al = (float)a.alpha[r];
 #pragma unroll
           for (int c = 0; c < 12; ++c) {
             const h2_t h = __builtin_bit_cast(h2_t, hw[c]);
-            w[c].r = fma((float)h.x, sc, -al * (float)v[c].r);
-            w[c].i = fma((float)h.y, sc, -al * (float)v[c].i);
+            w[c].r = fma((float)h.x, sc, (float)v[c].r);
+            w[c].i = fma((float)h.y, sc, (float)v[c].i);
           }
-        } else if constexpr (RT::OM == O_RUPD) {
+        } else if constexpr (RT::OM == O_RUPD) {  // r + (-alpha v), v carries -alpha
           ld_spinor_nt<PR>(a.r, fd, r, s, EOFA_SITE, w);
-          const RR al = (RR)a.alpha[r];
 #pragma unroll
           for (int c = 0; c < 12; ++c) {
-            w[c].r = fma(-al, (RR)v[c].r, w[c].r);
-            w[c].i = fma(-al, (RR)v[c].i, w[c].i);
+            w[c].r = w[c].r + (RR)v[c].r;
+            w[c].i = w[c].i + (RR)v[c].i;
           }
         } else {
 #pragma unroll
