@@ -70,6 +70,10 @@ int main(void) {
 @pytest.mark.parametrize("bad", [
     dict(dims=(4, 4, 4, 3)), dict(dims=(4, 4, 0, 4)), dict(Ls=7), dict(Ls=0), dict(Ls=34),
     dict(b5=1.5, c5=0.7), dict(bc=(1, 1, 1, 2)),
+    # Vh * Ls = 2^28 5D sites per parity: beyond the 32-bit byte offsets of the
+    # FP16S gathers (the site indexing alone would still fit), also when G-parity
+    # doubles x
+    dict(dims=(64, 64, 64, 128), Ls=16), dict(dims=(64, 64, 64, 64), Ls=16, bc=(2, 1, 1, -1)),
 ])
 def test_create_rejects_invalid_action(bad):
     kw = dict(dims=(4, 4, 4, 4), Ls=8, M5=1.8, b5=1.5, c5=0.5, bc=(1, 1, 1, -1))
