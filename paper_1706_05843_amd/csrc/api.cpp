@@ -588,9 +588,15 @@ int inner_iteration(eofa_ctx* C, const Form& F, int S, const HopArgs& k1, const 
   if (ev) HIPCHK(hipEventRecord(ev[2], st));
   CHK(hop(C, S, F.k2, a2, st));
   if (ev) HIPCHK(hipEventRecord(ev[3], st));
-  launch_finalize(FIN_ALPHA, partial, nbh, nrhs, Sst, nullptr, st);
+  // the alpha step on K2's partial sums runs in K3's work-group 0 (K3 does
+  // not need alpha; K4, the launch after it, does)
+  HopArgs a3 = k3;
+  a3.fin_partial = partial;
+  a3.fin_nblk = nbh;
+  a3.fin_mode = FIN_ALPHA;
+  a3.fin_S = Sst;
   if (ev) HIPCHK(hipEventRecord(ev[4], st));
-  CHK(hop(C, S, F.k3, k3, st));
+  CHK(hop(C, S, F.k3, a3, st));
   if (ev) HIPCHK(hipEventRecord(ev[5], st));
   if (ev) HIPCHK(hipEventRecord(ev[6], st));
   CHK(hop(C, S, F.k4, k4, st));

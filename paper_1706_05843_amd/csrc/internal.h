@@ -122,6 +122,13 @@ struct HopArgs {
   double* partial;    // [nrhs][gridDim.x]
   int Vh, Ls, nrhs, rhs_block;
   int W;              // waves per work-group (1, 2 or 4)
+  // optional CG step fused into a K3 (or D3) launch: work-group 0 of each RHS block
+  // reduces fin_partial [nrhs][fin_nblk] (the previous launch's partial
+  // sums) and applies finalize mode fin_mode to fin_S; null = none (other
+  // roles ignore it)
+  const double* fin_partial;
+  int fin_nblk, fin_mode;
+  CgState fin_S;
 };
 
 // kernel launchers (kernels.hip)

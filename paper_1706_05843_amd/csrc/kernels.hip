@@ -941,6 +941,43 @@ __device__ __forceinline__ void load_y(const void* y, const FD& fd, int r, int s
   }
 }
 
+__device__ void finalize_step(int mode, double sum, const CgState& S, int r, double* out);
+
+// A CG step fused into a hop launch (work-group 0 of each right-hand-side
+// block): the previous launch's nblk partial sums of right-hand side r,
+// reduced by the whole work-group in a fixed order (8 independent sums per
+// thread, then lanes, then waves), then finalize_step on thread 0. red: one
+// double per wave.
+__device__ __forceinline__ void fin_block(int mode, const double* __restrict__ pr, int nblk, const CgState& S, int r,
+                                          double* red) {
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  double acc[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc[k] = 0.0;
+  for (int j0 = tid; j0 < nblk; j0 += 8 * nthr) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int j = j0 + k * nthr;
+      if (j < nblk) acc[k] += pr[j];
+    }
+  }
+#pragma unroll
+  for (int w = 4; w > 0; w >>= 1)
+#pragma unroll
+    for (int k = 0; k < w; ++k) acc[k] += acc[k + w];
+  double t = acc[0];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = t;
+  __syncthreads();
+  if (tid == 0) {
+    double sum = 0.0;
+    for (int w = 0; w < (nthr + 63) / 64; ++w) sum += red[w];
+    finalize_step(mode, sum, S, r, nullptr);
+  }
+  __syncthreads();
+}
+
 // RL = 16: Ls = 16, each site's s-column is one DPP row and every exchange
 // along s (D~ premix, L, the dense Ls x Ls epilogues, the rank-one sums) is
 // a row rotation; RL = 0: any Ls, exchanges through lane permutes and LDS.
@@ -1018,6 +1055,16 @@ hop_kernel(HopArgs a) {
 
   const int rb0 = blockIdx.y * a.rhs_block;
   const int rb1 = min(rb0 + a.rhs_block, a.nrhs);
+  // the fused CG step of the previous launch's partial sums (K3 takes the
+  // alpha step that K4 reads): only this launch's work-group 0 writes the CG
+  // state; the other work-groups may read a halt flag before or after it is
+  // set, and either is right (a right-hand side halted by this step is not
+  // used by the next launch)
+  if constexpr (ROLE == ROLE_K3 || ROLE == ROLE_D3) {  // the third launch of an iteration, either form
+    if (a.fin_partial != nullptr && blockIdx.x == 0)
+      for (int r = rb0; r < rb1; ++r)
+        fin_block(a.fin_mode, a.fin_partial + (size_t)r * a.fin_nblk, a.fin_nblk, a.fin_S, r, s_red);
+  }
   __shared__ int s_halt;
   for (int r = rb0; r < rb1; ++r) {
     __syncthreads();
