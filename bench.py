@@ -947,6 +947,7 @@ def main():
         "time_to_solution_s": round(ms / 1e3, 5),
         "iters": stats[-1]["iters"], "outer_iters": stats[-1]["outer_iters"],
         "true_resid": stats[-1]["true_resid"],
+        "launch_shape": {"waves": stats[-1]["waves"], "rhs_block": stats[-1]["rhs_block"]},
         "roofline": roof,
     }
     if restart is not None:

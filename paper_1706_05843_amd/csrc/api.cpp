@@ -589,12 +589,18 @@ int inner_iteration(eofa_ctx* C, const Form& F, int S, const HopArgs& k1, const 
   CHK(hop(C, S, F.k2, a2, st));
   if (ev) HIPCHK(hipEventRecord(ev[3], st));
   // the alpha step on K2's partial sums runs in K3's work-group 0 (K3 does
-  // not need alpha; K4, the launch after it, does)
+  // not need alpha; K4, the launch after it, does) when that work-group can
+  // sum them with at most 16 loads per thread; else (small work-groups, many
+  // partials) in a finalize launch of its own
   HopArgs a3 = k3;
-  a3.fin_partial = partial;
-  a3.fin_nblk = nbh;
-  a3.fin_mode = FIN_ALPHA;
-  a3.fin_S = Sst;
+  if (nbh <= 16 * 64 * k3.W) {
+    a3.fin_partial = partial;
+    a3.fin_nblk = nbh;
+    a3.fin_mode = FIN_ALPHA;
+    a3.fin_S = Sst;
+  } else {
+    launch_finalize(FIN_ALPHA, partial, nbh, nrhs, Sst, nullptr, st);
+  }
   if (ev) HIPCHK(hipEventRecord(ev[4], st));
   CHK(hop(C, S, F.k3, a3, st));
   if (ev) HIPCHK(hipEventRecord(ev[5], st));
