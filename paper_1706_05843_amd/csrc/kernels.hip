@@ -529,6 +529,28 @@ __device__ __forceinline__ void lmul(const cx<R>* v, cx<R>* out, const SNbr<R>& 
   }
 }
 
+// z += k (L y) (TRANS: k (L^T y)) in the generic column form: the wrap factor
+// rides on the coefficient, one FMA per real component. z may alias y: each
+// component's neighbour value is read before that component is written.
+template <class R, bool TRANS, int RL>
+__device__ __forceinline__ void lacc(cx<R>* z, const cx<R>* y, const SNbr<R>& nb, R k) {
+  const R kp = nb.fp * k, kn = nb.fn * k;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const cx<R> t = TRANS ? cx<R>{col_nbr<RL, false>(y[c].r, nb.sn), col_nbr<RL, false>(y[c].i, nb.sn)}
+                          : cx<R>{col_nbr<RL, true>(y[c].r, nb.sp), col_nbr<RL, true>(y[c].i, nb.sp)};
+    const R f = TRANS ? kn : kp;
+    z[c] = {fma(f, t.r, z[c].r), fma(f, t.i, z[c].i)};
+  }
+#pragma unroll
+  for (int c = 6; c < 12; ++c) {
+    const cx<R> t = TRANS ? cx<R>{col_nbr<RL, true>(y[c].r, nb.sp), col_nbr<RL, true>(y[c].i, nb.sp)}
+                          : cx<R>{col_nbr<RL, false>(y[c].r, nb.sn), col_nbr<RL, false>(y[c].i, nb.sn)};
+    const R f = TRANS ? kp : kn;
+    z[c] = {fma(f, t.r, z[c].r), fma(f, t.i, z[c].i)};
+  }
+}
+
 // v[half] (+)= M v'[half] for the Ls x Ls matrix of chirality `half` (rows
 // padded to Ls + 1 in LDS), Ls = 16: the sum over s' runs along the cyclic
 // diagonals, M[s][s-k] times the value of lane s-k brought by a row rotation,
@@ -1129,10 +1151,9 @@ hop_kernel(HopArgs a) {
       scan_step<R, 1, false>(v, s, qd, (R)a.mop[r]);
       scan_step<R, 1, true>(v + 6, s, qd, (R)a.mop[r]);
     } else {  // D~^T h = (c+d)(h + qd L^T h), the (c+d) and the sign in the fold
-      cx<R> t[12];
-      lmul<R, true, RL>(acc, t, nb);
 #pragma unroll
-      for (int c = 0; c < 12; ++c) v[c] = {fma(qd, t[c].r, acc[c].r), fma(qd, t[c].i, acc[c].i)};
+      for (int c = 0; c < 12; ++c) v[c] = acc[c];
+      lacc<R, true, RL>(v, acc, nb, qd);
     }
     if constexpr (SINV) {  // v <- M_ee^-1 v or M_ee^-T v, structured along the column
       const double* scs = a.scoef + (size_t)r * (SCOEF_HEAD + 2 * Ls);
@@ -1168,10 +1189,7 @@ hop_kernel(HopArgs a) {
       scan_step<R, 1, true>(v, s, qd, (R)a.mop[r]);
       scan_step<R, 1, false>(v + 6, s, qd, (R)a.mop[r]);
     } else if constexpr (RT::AM == A_DMINV) {  // v <- D~ v = (c+d)(v + qd L v), the (c+d) in the fold
-      cx<R> t[12];
-      lmul<R, false, RL>(v, t, nb);
-#pragma unroll
-      for (int c = 0; c < 12; ++c) v[c] = {fma(qd, t[c].r, v[c].r), fma(qd, t[c].i, v[c].i)};
+      lacc<R, false, RL>(v, v, nb, qd);
     }
     if constexpr (BDENSE && RL == 16) {  // v += M y along the row's diagonals
       cx<R> y[12];
@@ -1196,7 +1214,7 @@ hop_kernel(HopArgs a) {
     } else if constexpr (RT::BM != B_NONE) {
       // + M_ee y (B_MEE) or + M_ee^T y (B_MEET):
       //   bee y - cee L y (L^T y) + sk u e_{s*}^T y (sk e_{s*} u^T y) on chirality chi
-      cx<R> y[12], t[12];
+      cx<R> y[12];
       load_y<P, YPRE>(a.y, fd, r, s, EOFA_SITE, ypre, y);
       // B_MEE_DTI: M_ee D~^-1 y with the normalisation of D~^-1 moved onto
       // the coefficients of M_ee (bee, cee and the rank-one sk)
@@ -1213,12 +1231,9 @@ hop_kernel(HopArgs a) {
         lacc_rows<!TR>(v, y, s, -cee, (R)a.mop[r]);
         lacc_rows<TR>(v + 6, y + 6, s, -cee, (R)a.mop[r]);
       } else {
-        lmul<R, RT::BM == B_MEET, RL>(y, t, nb);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-          v[c].r = fma(bee, y[c].r, fma(-cee, t[c].r, v[c].r));
-          v[c].i = fma(bee, y[c].i, fma(-cee, t[c].i, v[c].i));
-        }
+        for (int c = 0; c < 12; ++c) v[c] = {fma(bee, y[c].r, v[c].r), fma(bee, y[c].i, v[c].i)};
+        lacc<R, RT::BM == B_MEET, RL>(v, y, nb, -cee);
       }
       const double* sc = a.scoef + (size_t)r * (SCOEF_HEAD + 2 * Ls);
       const R sk = (R)sc[1] * yn * vscale;
