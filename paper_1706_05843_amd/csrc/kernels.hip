@@ -212,7 +212,25 @@ __device__ __forceinline__ void load_dir16(const Buf16& B, int Ls, int s, int n,
 constexpr int kPfd16 = 1;
 constexpr int kOcc16 = 5;
 
-template <bool DAG, bool PRE, int RL, bool YPRE>
+// SU(3) products on the matrix cores (MF): v_mfma_f32_4x4x4_16b_f16 runs 16
+// independent 4x4x4 products per wave, block b on lanes 4b .. 4b+3, lane 4b+j
+// supplying column j of B (its own 4 halves) and row j of A, and receiving
+// column j of D (D register q = row q). When the 4 lanes of every block hold
+// 5D sites of one 4D site (Ls a multiple of 4), they share each link, so
+// A = the real form of U (rows (Re, Im) of each output colour, columns
+// (Re, Im) of each input colour: the 2x2 blocks (Re u, -Im u; Im u, Re u)
+// staged in LDS) and B = the lane's own projected half spinor give each lane
+// its own U h. Per half spinor: top rows (Re, Im of colours 0, 1) and bottom
+// rows (colour 2, its two rows repeated on lanes 2, 3 of the block), each
+// over the K blocks (colours 0, 1) and (colour 2, zero): four products, in
+// place of 18 v_dot2 on the vector ALU. Same FP16 products, FP32 sums.
+typedef _Float16 h4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef unsigned u2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ h4_t h4_of(unsigned lo, unsigned hi) { return __builtin_bit_cast(h4_t, u2_t{lo, hi}); }
+__device__ __forceinline__ h4_t h4_of(h2_t lo, h2_t hi) { return __builtin_shufflevector(lo, hi, 0, 1, 2, 3); }
+
+template <bool DAG, bool PRE, int RL, bool YPRE, bool MF>
 __device__ __forceinline__ void hop_site_h(const HopArgs& a, const FD& fin, int r, int s, int g, int ls,
                                            const cx<float>* s_link, const int* s_nbr, cx<float>* acc,
                                            DirIn<P16>& yout, float fold) {
@@ -229,6 +247,12 @@ __device__ __forceinline__ void hop_site_h(const HopArgs& a, const FD& fin, int 
     src_lo = g * Ls + (s < Ls - 1 ? s + 1 : 0);
   }
   post *= fold;
+  // word offsets of this lane's A rows in a direction's 9 staged entries
+  // (entry e: word 2e = (Re u, -Im u), word 2e + 1 = (Im u, Re u))
+  const int mj = threadIdx.x & 3;
+  const int mf_top = 6 * (mj >> 1) + (mj & 1), mf_bot = mj & 1;
+  (void)mf_top;
+  (void)mf_bot;
 #pragma unroll
   for (int c = 0; c < 12; ++c) acc[c] = {0.f, 0.f};
   // the neighbour spinors of the next kPfd16 directions are in flight while
@@ -295,8 +319,31 @@ __device__ __forceinline__ void hop_site_h(const HopArgs& a, const FD& fin, int 
         h[3 + c] = neg ? u1 - l1 : u1 + l1;
       }
     }
-    const uint2* U = (const uint2*)(s_link + ls * LSTR + dir * 9);
     cx<float> gv[6];
+    if constexpr (MF) {
+      // lane j of its block: A rows j of the top blocks (colour j / 2, Re
+      // or Im by j % 2) and of the bottom blocks (colour 2, Re or Im by j % 2);
+      // the K columns that meet B's zero halves take another (finite) link word
+      const unsigned* Uw = (const unsigned*)(s_link + ls * LSTR + dir * 9);
+      const unsigned* Ut = Uw + mf_top;
+      const unsigned* Ub = Uw + mf_bot;
+      const h4_t A00 = h4_of(Ut[0], Ut[2]), A01 = h4_of(Ut[4], Ut[2]);
+      const h4_t A10 = h4_of(Ub[12], Ub[14]), A11 = h4_of(Ub[16], Ub[14]);
+      const h2_t z2 = {(_Float16)0.f, (_Float16)0.f};
+      const f4_t z4 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const h4_t B0 = h4_of(h[k * 3], h[k * 3 + 1]), B1 = h4_of(h[k * 3 + 2], z2);
+        f4_t top = __builtin_amdgcn_mfma_f32_4x4x4f16(A00, B0, z4, 0, 0, 0);
+        top = __builtin_amdgcn_mfma_f32_4x4x4f16(A01, B1, top, 0, 0, 0);
+        f4_t bot = __builtin_amdgcn_mfma_f32_4x4x4f16(A10, B0, z4, 0, 0, 0);
+        bot = __builtin_amdgcn_mfma_f32_4x4x4f16(A11, B1, bot, 0, 0, 0);
+        gv[k * 3] = {top[0], top[1]};
+        gv[k * 3 + 1] = {top[2], top[3]};
+        gv[k * 3 + 2] = {bot[0], bot[1]};
+      }
+    } else {
+    const uint2* U = (const uint2*)(s_link + ls * LSTR + dir * 9);
 #pragma unroll
     for (int k = 0; k < 2; ++k)
 #pragma unroll
@@ -318,6 +365,7 @@ __device__ __forceinline__ void hop_site_h(const HopArgs& a, const FD& fin, int 
       }
 #pragma unroll
     for (int c = 0; c < 6; ++c) asm volatile("" : "+v"(gv[c].r), "+v"(gv[c].i));
+    }
     // acc += post unit [g ; sg A^dag g] (the overall -1/2, or -(c+d)/2, and
     // the epilogue's leading factor folded into each direction's unit)
     const float ps = unit * post, ms = neg ? -ps : ps;
@@ -354,7 +402,8 @@ __device__ __forceinline__ void hop_site(const HopArgs& a, const FD& fin, int r,
                                          cx<typename ST<P>::R>* acc, DirIn<P16>& yout,
                                          typename ST<P>::R fold) {
   if constexpr (P == P16) {
-    hop_site_h<DAG, PRE, RL, YPRE>(a, fin, r, s, g, ls, s_link, s_nbr, acc, yout, fold);
+    // the matrix-core products need each 4-lane block inside one column
+    hop_site_h<DAG, PRE, RL, YPRE, RL == 16 || RL == 4>(a, fin, r, s, g, ls, s_link, s_nbr, acc, yout, fold);
     return;
   } else {
   using R = typename ST<P>::R;
@@ -1002,7 +1051,9 @@ __device__ __forceinline__ void fin_block(int mode, const double* __restrict__ p
 
 // RL = 16: Ls = 16, each site's s-column is one DPP row and every exchange
 // along s (D~ premix, L, the dense Ls x Ls epilogues, the rank-one sums) is
-// a row rotation; RL = 0: any Ls, exchanges through lane permutes and LDS.
+// a row rotation; RL = 0: any Ls, exchanges through lane permutes and LDS;
+// RL = 4: the same for Ls a multiple of 4 (FP16S), whose columns hold whole
+// 4-lane blocks, so the SU(3) products can run on the matrix cores.
 template <int P, int PR, int ROLE, int RL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HopOcc<P>::waves, 8)))
 hop_kernel(HopArgs a) {
@@ -1395,6 +1446,8 @@ int launch_hop_t(const HopArgs& a, hipStream_t st, int* nblk_out) {
   b.rhs_block = rb;
   b.W = W;
   void (*fn)(HopArgs) = hop_kernel<P, acc_prec<P>(), ROLE, 0>;
+  if constexpr (P == P16)
+    if (Ls % 4 == 0) fn = hop_kernel<P, acc_prec<P>(), ROLE, 4>;
   if (use_rows<P>(Ls)) fn = hop_kernel<P, acc_prec<P>(), ROLE, 16>;
   if (lds > 65536) {
     if (hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
