@@ -117,12 +117,16 @@ def _timed(fn):
     return out, w, max(1, int(round(c / max(w, 1e-9))))
 
 
-def cpu_baseline(dims, Ls, eps, m1, gseed, sseed):
+def cpu_baseline(dims, Ls, eps, m1, gseed, sseed, plain_iters=None):
     """The CPU oracle as it stands (plain numpy FP64), on this host:
     (1) its off-parity operator Dhop.D~(m) once on the same lattice as the GPU
     step, in the GPU roofline's bytes (the value); (2) its whole solve route
     (mirror mode: Schur source, CGNR, reconstruction) of the same shifted
-    system to a 1e-10 residual on the small 4^4 x Ls=8 workload."""
+    system to a 1e-10 residual on the small 4^4 x Ls=8 workload; (3) for the
+    full-size solve, which would take hours on the host, an extrapolation:
+    four such applications per CGNR iteration (two of the Schur operator, two
+    of its adjoint; the same-parity blocks and the vector updates left out,
+    so a lower bound) times the GPU's plain FP64 iteration count."""
     import numpy as np
     from oracle import eo
     from oracle.dwf import Action, Dtilde_op, System
@@ -141,6 +145,12 @@ def cpu_baseline(dims, Ls, eps, m1, gseed, sseed):
     act1 = Action(d1, l1, 1.8, 1.5, 0.5, (1, 1, 1, -1))
     U1, phi1 = synth.gauge_field(d1, e1, gs1), synth.fermion(d1, l1, ss1)
     out, t1, th1 = _timed(lambda: eo.solve_mirror(act1, U1, System(1.0, ms1, 1.0, -1.0, +1), phi1, tol=1e-10))
+    extra = {}
+    if plain_iters:
+        extra["time_to_solution_extrapolated"] = dict(
+            seconds_lower_bound=round(4 * dt * plain_iters, 1), iters=plain_iters,
+            basis=f"4 x {dt:.2f} s (measured Dhop.D~ application) x {plain_iters} CGNR iterations "
+                  f"(the GPU's plain FP64 count); same-parity blocks and vector updates not counted")
     return dict(value=byts / dt / 1e9, unit="GB/s", cores=threads, kind="oracle",
                 sample=f"one application of the oracle's FP64 off-parity operator Dhop.D~ on the full "
                        f"{dims[0]}x{dims[1]}x{dims[2]}x{dims[3]} x Ls={Ls} lattice ({dt:.2f} s), bytes counted "
@@ -149,7 +159,7 @@ def cpu_baseline(dims, Ls, eps, m1, gseed, sseed):
                 nproc=info["nproc"], usable_cores=info["usable_cores"], cpu_model=info["cpu_model"],
                 time_to_solution_c1=dict(seconds=round(t1, 3), iters=out["iters"], true_resid=out["true_resid"],
                                          cores=th1, workload="4x4x4x4 Ls=8 eps=0.3 m1=0.04 m2=1.0, "
-                                         "H(m2)-Delta_+(m1,m2)P_+, CGNR to 1e-10 (mirror mode)"))
+                                         "H(m2)-Delta_+(m1,m2)P_+, CGNR to 1e-10 (mirror mode)"), **extra)
 
 
 def gpu_c1(eofa, synth, torch):
@@ -173,7 +183,7 @@ def gpu_c1(eofa, synth, torch):
     return res
 
 
-def dslash_beyond_mall(eofa, synth, torch, np, reps=50):
+def dslash_beyond_mall(eofa, synth, torch, np, reps=100):
     """Single-RHS Dslash (Dhop.D~, odd -> even) on the 24^3 x 64 x Ls=12
     lattice, whose FP16S half-field (263 MiB) and FP32/FP64 ones exceed the
     256 MB MALL, so every launch streams from HBM. Algorithmic GB/s on the hop's
@@ -233,7 +243,7 @@ def bench_batched(args, eofa, synth, torch, np):
     # (a) Dslash: one launch over all right-hand sides vs one launch each
     pin, pout = ctx.new_packed(prec, nrhs), ctx.new_packed(prec, nrhs)
     ctx.eofa_pack(phi, pin, 1, prec, nrhs)
-    reps = 10
+    reps = 100
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     ctx.eofa_dslash(sysl, pin, pout, 0, 0, prec, nrhs)
     ev[0].record()
@@ -477,7 +487,7 @@ def bench_force(args, eofa, synth, torch, np):
     y = torch.zeros_like(F)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     ctx.eofa_dhop_derivative(phi, phi, y)
-    reps = 20
+    reps = 100
     ev[0].record()
     for _ in range(reps):
         ctx.eofa_dhop_derivative(phi, phi, y)
@@ -585,7 +595,7 @@ def bench_gparity(args, eofa, synth, torch, np):
     torch.cuda.empty_cache()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     ctx.eofa_dslash(sysl, pin, pout, 0, 0, prec, nrhs)
-    reps = 10
+    reps = 100
     ev[0].record()
     for _ in range(reps):
         ctx.eofa_dslash(sysl, pin, pout, 0, 0, prec, nrhs)
@@ -664,7 +674,7 @@ def bench_c5(args, eofa, synth, torch, np):
     del src
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     ctx.eofa_dslash(sysl, pin, pout, 0, 0, prec, nrhs)
-    reps = 10
+    reps = 100
     ev[0].record()
     for _ in range(reps):
         ctx.eofa_dslash(sysl, pin, pout, 0, 0, prec, nrhs)
@@ -966,7 +976,8 @@ def main():
     if not args.no_cpu:
         print("bench: the same solve on 4^4 x Ls=8 on the GPU and with the CPU oracle", file=sys.stderr, flush=True)
         out["gpu_c1_time_to_solution"] = gpu_c1(eofa, synth, torch)
-        out["cpu_baseline"] = cpu_baseline(dims, Ls, eps, m1, gseed, sseed)
+        out["cpu_baseline"] = cpu_baseline(dims, Ls, eps, m1, gseed, sseed,
+                                           plain_iters=plain["iters"] if plain is not None else None)
     print(json.dumps(out), flush=True)
 
 
