@@ -4,7 +4,9 @@ the Sherman-Morrison term). For Ls != 16 the hop kernels sum the geometric
 series of rho L as a product over the prime factors of Ls by lane permutes
 within the column; Ls = 6 (2 3), 10 (2 5: a pass of four shifted copies) and
 12 (2 2 3, the batched workload's extent) cover the factor patterns (Ls is
-even, as App. A assumes).
+even, as App. A assumes); the converged solves add Ls = 20 and 24 (4 and 16
+idle lanes per wave in the FP16S kernels whose SU(3) products run on the
+matrix cores).
 
 * FP64 fixed-iteration solves (K1..K4, the FP64 residual) against the
   oracle's mirror-mode CGNR of the same systems: 1e-12 relative, for the
@@ -68,7 +70,7 @@ def test_mirror_mode_fp64(Ls, name):
 
 
 @pytest.mark.parametrize("prec", [eofa.FP32, eofa.FP16S])
-@pytest.mark.parametrize("Ls", [6, 10, 12])
+@pytest.mark.parametrize("Ls", [6, 10, 12, 20, 24])
 def test_converged(Ls, prec):
     act, U, phi, ctx = setup(Ls)
     names = list(SYSTEMS)

@@ -110,7 +110,13 @@ def test_pack_roundtrip(prec):
 
 # --- Dslash -----------------------------------------------------------------
 
-LATTICES = [((2, 2, 2, 2), 4), ((4, 4, 4, 4), 8), ((4, 2, 6, 4), 6), ((6, 4, 2, 2), 12), ((2, 2, 2, 4), 16)]
+# Ls = 16: the row form; other Ls a multiple of 4 (4, 8, 12, 20, 24, 28, 32):
+# the generic form whose FP16S products run on the matrix cores, with 0, 4,
+# 16 and 8 idle lanes per wave at Ls = 32, 20, 24, 28; Ls = 2, 6: the generic
+# form with v_dot2 products. The larger lattices give several work-groups
+# and a ragged last one.
+LATTICES = [((2, 2, 2, 2), 4), ((4, 4, 4, 4), 8), ((4, 2, 6, 4), 6), ((6, 4, 2, 2), 12), ((2, 2, 2, 4), 16),
+            ((2, 2, 2, 2), 2), ((2, 2, 2, 4), 20), ((4, 2, 2, 4), 24), ((2, 2, 2, 2), 28), ((2, 2, 4, 2), 32)]
 
 
 @pytest.mark.parametrize("dims,Ls", LATTICES)
