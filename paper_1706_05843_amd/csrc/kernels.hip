@@ -230,6 +230,59 @@ typedef unsigned u2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ h4_t h4_of(unsigned lo, unsigned hi) { return __builtin_bit_cast(h4_t, u2_t{lo, hi}); }
 __device__ __forceinline__ h4_t h4_of(h2_t lo, h2_t hi) { return __builtin_shufflevector(lo, hi, 0, 1, 2, 3); }
 
+// g = U h for the two projected half spinors h[0..2], h[3..5] of one
+// direction on the matrix cores. Uw: the direction's 9 staged entries (entry
+// e: word 2e = (Re u, -Im u), word 2e + 1 = (Im u, Re u)); top, bot: this
+// lane's word offsets of its A rows (lane j of its block: row j of the top
+// blocks = colour j / 2, Re or Im by j % 2; of the bottom blocks = colour 2,
+// Re or Im by j % 2). The K columns that meet B's zero halves take another
+// (finite) link word.
+__device__ __forceinline__ void su3_mfma(const unsigned* Uw, int top, int bot, const h2_t* h, cx<float>* gv) {
+  const unsigned* Ut = Uw + top;
+  const unsigned* Ub = Uw + bot;
+  const h4_t A00 = h4_of(Ut[0], Ut[2]), A01 = h4_of(Ut[4], Ut[2]);
+  const h4_t A10 = h4_of(Ub[12], Ub[14]), A11 = h4_of(Ub[16], Ub[14]);
+  const h2_t z2 = {(_Float16)0.f, (_Float16)0.f};
+  const f4_t z4 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const h4_t B0 = h4_of(h[k * 3], h[k * 3 + 1]), B1 = h4_of(h[k * 3 + 2], z2);
+    f4_t t = __builtin_amdgcn_mfma_f32_4x4x4f16(A00, B0, z4, 0, 0, 0);
+    t = __builtin_amdgcn_mfma_f32_4x4x4f16(A01, B1, t, 0, 0, 0);
+    f4_t b = __builtin_amdgcn_mfma_f32_4x4x4f16(A10, B0, z4, 0, 0, 0);
+    b = __builtin_amdgcn_mfma_f32_4x4x4f16(A11, B1, b, 0, 0, 0);
+    gv[k * 3] = {t[0], t[1]};
+    gv[k * 3 + 1] = {t[2], t[3]};
+    gv[k * 3 + 2] = {b[0], b[1]};
+  }
+}
+
+// the same products as v_dot2 on the vector ALU (any Ls); U: the direction's
+// 9 staged entries as word pairs
+__device__ __forceinline__ void su3_dot2(const uint2* U, const h2_t* h, cx<float>* gv) {
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+#pragma unroll
+    for (int a3 = 0; a3 < 3; ++a3) {
+      // first product in the three-operand form with an inline zero
+      // accumulator (the two-operand form would need a register cleared first)
+      const uint2 u0 = U[a3 * 3];
+      const unsigned h0 = __builtin_bit_cast(unsigned, h[k * 3]);
+      float re, im;
+      asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(re) : "v"(u0.x), "v"(h0));
+      asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(im) : "v"(u0.y), "v"(h0));
+#pragma unroll
+      for (int b3 = 1; b3 < 3; ++b3) {
+        const uint2 u = U[a3 * 3 + b3];
+        re = __builtin_amdgcn_fdot2(__builtin_bit_cast(h2_t, u.x), h[k * 3 + b3], re, false);
+        im = __builtin_amdgcn_fdot2(__builtin_bit_cast(h2_t, u.y), h[k * 3 + b3], im, false);
+      }
+      gv[k * 3 + a3] = {re, im};
+    }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) asm volatile("" : "+v"(gv[c].r), "+v"(gv[c].i));
+}
+
 template <bool DAG, bool PRE, int RL, bool YPRE, bool MF>
 __device__ __forceinline__ void hop_site_h(const HopArgs& a, const FD& fin, int r, int s, int g, int ls,
                                            const cx<float>* s_link, const int* s_nbr, cx<float>* acc,
@@ -248,7 +301,7 @@ __device__ __forceinline__ void hop_site_h(const HopArgs& a, const FD& fin, int 
   }
   post *= fold;
   // word offsets of this lane's A rows in a direction's 9 staged entries
-  // (entry e: word 2e = (Re u, -Im u), word 2e + 1 = (Im u, Re u))
+  // (for the matrix-core products)
   const int mj = threadIdx.x & 3;
   const int mf_top = 6 * (mj >> 1) + (mj & 1), mf_bot = mj & 1;
   (void)mf_top;
@@ -320,52 +373,10 @@ __device__ __forceinline__ void hop_site_h(const HopArgs& a, const FD& fin, int 
       }
     }
     cx<float> gv[6];
-    if constexpr (MF) {
-      // lane j of its block: A rows j of the top blocks (colour j / 2, Re
-      // or Im by j % 2) and of the bottom blocks (colour 2, Re or Im by j % 2);
-      // the K columns that meet B's zero halves take another (finite) link word
-      const unsigned* Uw = (const unsigned*)(s_link + ls * LSTR + dir * 9);
-      const unsigned* Ut = Uw + mf_top;
-      const unsigned* Ub = Uw + mf_bot;
-      const h4_t A00 = h4_of(Ut[0], Ut[2]), A01 = h4_of(Ut[4], Ut[2]);
-      const h4_t A10 = h4_of(Ub[12], Ub[14]), A11 = h4_of(Ub[16], Ub[14]);
-      const h2_t z2 = {(_Float16)0.f, (_Float16)0.f};
-      const f4_t z4 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        const h4_t B0 = h4_of(h[k * 3], h[k * 3 + 1]), B1 = h4_of(h[k * 3 + 2], z2);
-        f4_t top = __builtin_amdgcn_mfma_f32_4x4x4f16(A00, B0, z4, 0, 0, 0);
-        top = __builtin_amdgcn_mfma_f32_4x4x4f16(A01, B1, top, 0, 0, 0);
-        f4_t bot = __builtin_amdgcn_mfma_f32_4x4x4f16(A10, B0, z4, 0, 0, 0);
-        bot = __builtin_amdgcn_mfma_f32_4x4x4f16(A11, B1, bot, 0, 0, 0);
-        gv[k * 3] = {top[0], top[1]};
-        gv[k * 3 + 1] = {top[2], top[3]};
-        gv[k * 3 + 2] = {bot[0], bot[1]};
-      }
-    } else {
-    const uint2* U = (const uint2*)(s_link + ls * LSTR + dir * 9);
-#pragma unroll
-    for (int k = 0; k < 2; ++k)
-#pragma unroll
-      for (int a3 = 0; a3 < 3; ++a3) {
-        // first product in the three-operand form with an inline zero
-        // accumulator (the two-operand form would need a register cleared first)
-        const uint2 u0 = U[a3 * 3];
-        const unsigned h0 = __builtin_bit_cast(unsigned, h[k * 3]);
-        float re, im;
-        asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(re) : "v"(u0.x), "v"(h0));
-        asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(im) : "v"(u0.y), "v"(h0));
-#pragma unroll
-        for (int b3 = 1; b3 < 3; ++b3) {
-          const uint2 u = U[a3 * 3 + b3];
-          re = __builtin_amdgcn_fdot2(__builtin_bit_cast(h2_t, u.x), h[k * 3 + b3], re, false);
-          im = __builtin_amdgcn_fdot2(__builtin_bit_cast(h2_t, u.y), h[k * 3 + b3], im, false);
-        }
-        gv[k * 3 + a3] = {re, im};
-      }
-#pragma unroll
-    for (int c = 0; c < 6; ++c) asm volatile("" : "+v"(gv[c].r), "+v"(gv[c].i));
-    }
+    if constexpr (MF)
+      su3_mfma((const unsigned*)(s_link + ls * LSTR + dir * 9), mf_top, mf_bot, h, gv);
+    else
+      su3_dot2((const uint2*)(s_link + ls * LSTR + dir * 9), h, gv);
     // acc += post unit [g ; sg A^dag g] (the overall -1/2, or -(c+d)/2, and
     // the epilogue's leading factor folded into each direction's unit)
     const float ps = unit * post, ms = neg ? -ps : ps;
