@@ -76,6 +76,29 @@ def test_launch_shapes_agree(setup):
         assert rel2(got, ref) < 1e-13, (waves, rb, rel2(got, ref))
 
 
+@pytest.mark.parametrize("Ls", [8, 12, 16])
+def test_fp16s_launch_shapes_agree(Ls):
+    """The FP16S hop kernels (SU(3) products on the matrix cores: the generic
+    form at Ls = 8 and 12, with idle lanes at 12, and the row form at 16)
+    under every launch shape: waves per work-group and right-hand sides per
+    work-group change only the order of the CG reductions, so a few fixed
+    iterations agree to FP16 storage precision, while a lane, site or
+    right-hand-side mix-up would differ at O(1)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dims = (4, 4, 2, 4)
+    U = synth.gauge_field(dims, 0.3, seed=1020 + Ls)
+    phis = synth.fermion(dims, Ls, seed=2020 + Ls, nrhs=len(SYS))
+    ctx = eofa.Context(eofa.make_action(dims, Ls, M5, B5, C5), torch.from_numpy(U).cuda())
+    kw = dict(fixed_iters=3, inner_prec=eofa.FP16S)
+    ref = solve(ctx, SYS, phis, waves=2, rhs_block=4, **kw)[2]
+    for waves, rb in ((1, 1), (4, 3), (2, 2), (1, 4)):
+        got = solve(ctx, SYS, phis, waves=waves, rhs_block=rb, **kw)[2]
+        for r in range(len(SYS)):
+            assert rel2(got[r], ref[r]) < 1e-4, (waves, rb, r, rel2(got[r], ref[r]))
+    ctx.close()
+
+
 @pytest.mark.parametrize("prec", [eofa.FP64, eofa.FP32])
 def test_batch_equals_single(setup, prec):
     act, U, phis, ctx = setup
